@@ -1,0 +1,263 @@
+"""Pins of the oracle's hierarchy construction (CPU).
+
+Aggregation is checked against its defining property by brute force (graph
+distances from SciPy), the prolongator and Galerkin product against dense
+NumPy products of the textbook formulas, the coarse factor against LAPACK.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import shortest_path, connected_components
+
+from paper_2606_09001_amd import matrices as M
+
+pytestmark = []
+
+
+def _A(rp, ci, v, shape=None):
+    n = len(rp) - 1
+    return sp.csr_matrix((v, ci, rp), shape=shape or (n, n))
+
+
+def _random_spd_pattern(n, p, seed):
+    """Random symmetric sparse SPD-ish matrix (diagonally dominant M-matrix)."""
+    rng = np.random.default_rng(seed)
+    U = sp.random(n, n, density=p, random_state=rng, format="csr")
+    U.data[:] = 1.0
+    G = ((U + U.T) > 0).astype(float)
+    G.setdiag(0)
+    G.eliminate_zeros()
+    deg = np.asarray(G.sum(axis=1)).ravel()
+    A = (sp.diags(deg + 1.0) - G).tocsr()
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+def test_key_function(oracle_mod):
+    # keys: MurmurHash3 32-bit finalizer in the high word, the index in the low word.
+    ks = [oracle_mod.node_key(i) for i in range(2000)]
+    assert len(set(ks)) == 2000
+    assert all((k & 0xFFFFFFFF) == i for i, k in enumerate(ks))
+    # published finalizer values: fmix32(0) = 0, fmix32(1) = 0x514E28B7
+    assert ks[0] >> 32 == 0
+    assert ks[1] >> 32 == 0x514E28B7
+
+
+def _check_aggregation(oracle_mod, rp, ci, v, lvl):
+    G = _A(lvl["G_rp"], lvl["G_ci"], np.ones(len(lvl["G_ci"])))
+    A = _A(rp, ci, v)
+    n = A.shape[0]
+    # strength graph at theta = 0: symmetrised off-diagonal pattern
+    off = A.copy()
+    off.setdiag(0)
+    off.eliminate_zeros()
+    Gref = ((abs(off) + abs(off.T)) > 0).astype(float).tocsr()
+    Gref.sort_indices()
+    assert np.array_equal(G.indptr, Gref.indptr) and np.array_equal(G.indices, Gref.indices)
+    D = shortest_path(G, unweighted=True, directed=False)
+    agg = lvl["agg"]
+    nagg = lvl["nagg"]
+    keys = np.array([oracle_mod.node_key(i) for i in range(n)], dtype=np.uint64)
+    # roots = nodes whose aggregate number equals their rank among... identify via definition:
+    # root of aggregate J is the unique member that is adjacent-or-equal to all first-ring members.
+    assert agg.min() >= 0 and agg.max() == nagg - 1
+    # Lexicographically-first distance-2 MIS by decreasing key, characterised directly:
+    # S = {i : no j in S with d(i,j) <= 2, key(j) > key(i)}; compute it in key order from distances.
+    order = np.argsort(-keys.astype(np.float64), kind="stable")
+    order = sorted(range(n), key=lambda i: int(keys[i]), reverse=True)
+    S = []
+    for i in order:
+        if all(D[i, j] > 2 for j in S):
+            S.append(i)
+    S = sorted(S)
+    assert len(S) == nagg
+    # roots numbered by ascending index
+    for r, i in enumerate(S):
+        assert agg[i] == r
+    Sarr = np.array(S)
+    # pairwise distance >= 3, maximality (every node within 2 of a root)
+    DS = D[np.ix_(Sarr, Sarr)]
+    assert np.all(DS[~np.eye(len(S), dtype=bool)] >= 3)
+    assert np.all(D[:, Sarr].min(axis=1) <= 2)
+    # neighbours of a root belong to it; the others to the smallest aggregate among
+    # their neighbours that are adjacent to a root
+    dist_root = D[:, Sarr]
+    for i in range(n):
+        d1 = np.where(dist_root[i] == 1)[0]
+        if dist_root[i].min() == 0:
+            continue
+        if len(d1):
+            assert len(d1) == 1 and agg[i] == d1[0]
+        else:
+            nbrs = G.indices[G.indptr[i]:G.indptr[i + 1]]
+            cand = [agg[j] for j in nbrs if dist_root[j].min() == 1]
+            assert agg[i] == min(cand)
+    # aggregates are connected
+    for J in range(nagg):
+        mem = np.where(agg == J)[0]
+        sub = G[mem][:, mem]
+        assert connected_components(sub, directed=False)[0] == 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_aggregation_random_graphs(oracle_mod, seed):
+    n = 8 + seed
+    rp, ci, v = _random_spd_pattern(n, 0.25, seed)
+    H = oracle_mod.OracleHierarchy(rp, ci, v, max_coarse=1, max_levels=2)
+    if H.num_levels < 2:
+        pytest.skip("coarsening stalled on this tiny graph")
+    _check_aggregation(oracle_mod, rp, ci, v, H.level(0))
+
+
+@pytest.mark.parametrize("N,d", [(12, 2), (5, 3)])
+def test_aggregation_grids(oracle_mod, N, d):
+    rp, ci, v = M.poisson(N, d)
+    H = oracle_mod.OracleHierarchy(rp, ci, v, max_coarse=8, max_levels=2)
+    _check_aggregation(oracle_mod, rp, ci, v, H.level(0))
+
+
+def test_aggregation_disconnected_and_isolated(oracle_mod):
+    # block-diagonal: a 4-node path, an isolated node (diagonal only), a triangle
+    A = sp.lil_matrix((8, 8))
+    for i in range(8):
+        A[i, i] = 3.0
+    for i, j in [(0, 1), (1, 2), (2, 3), (5, 6), (6, 7), (5, 7)]:
+        A[i, j] = A[j, i] = -1.0
+    A = A.tocsr()
+    A.sort_indices()
+    H = oracle_mod.OracleHierarchy(A.indptr, A.indices, A.data, max_coarse=1, max_levels=2)
+    lvl = H.level(0)
+    assert lvl["agg"][4] not in np.delete(lvl["agg"], 4)   # isolated node is its own aggregate
+    _check_aggregation(oracle_mod, A.indptr, A.indices, A.data, lvl)
+
+
+def _dense_P(A, agg, nagg, omegaP):
+    n = A.shape[0]
+    T = np.zeros((n, nagg))
+    T[np.arange(n), agg] = 1.0
+    Ad = A.toarray()
+    return (np.eye(n) - omegaP * np.diag(1.0 / np.diag(Ad)) @ Ad) @ T
+
+
+@pytest.mark.parametrize("kind", ["poisson2", "poisson3", "diffusion2", "random"])
+def test_prolongator_restriction_galerkin(oracle_mod, kind):
+    if kind == "poisson2":
+        rp, ci, v = M.poisson(16, 2)
+    elif kind == "poisson3":
+        rp, ci, v = M.poisson(6, 3)
+    elif kind == "diffusion2":
+        rp, ci, v = M.diffusion(np.exp(M.grf(16, 2, seed=11)))
+    else:
+        rp, ci, v = _random_spd_pattern(60, 0.08, 4)
+    H = oracle_mod.OracleHierarchy(rp, ci, v, max_coarse=4, max_levels=3)
+    assert H.num_levels >= 2
+    for l in range(H.num_levels - 1):
+        lv = H.level(l)
+        nxt = H.level(l + 1)
+        A = _A(lv["A_rp"], lv["A_ci"], lv["A_v"])
+        Ad = A.toarray()
+        # Gershgorin bound and the prolongator damping
+        rho = np.max(np.abs(Ad).sum(axis=1) / np.abs(np.diag(Ad)))
+        assert lv["rho"] == pytest.approx(rho, rel=1e-15)
+        assert lv["omegaP"] == pytest.approx((4.0 / 3.0) / rho, rel=1e-15)
+        if kind.startswith("poisson") and l == 0:
+            assert lv["rho"] == 2.0 and lv["omegaP"] == 2.0 / 3.0
+        P = _A(lv["P_rp"], lv["P_ci"], lv["P_v"], shape=(lv["n"], lv["nagg"]))
+        Pd = _dense_P(A, lv["agg"], lv["nagg"], lv["omegaP"])
+        assert np.max(np.abs(P.toarray() - Pd)) <= 1e-15 * max(1.0, np.abs(Pd).max())
+        # structural pattern: every aggregate touched by a row is stored
+        for i in range(lv["n"]):
+            touched = np.unique(lv["agg"][lv["A_ci"][lv["A_rp"][i]:lv["A_rp"][i + 1]]])
+            assert np.array_equal(lv["P_ci"][lv["P_rp"][i]:lv["P_rp"][i + 1]], touched)
+        # P 1 = 1 - omegaP D^-1 A 1
+        ones = np.ones(lv["n"])
+        assert np.allclose(P @ np.ones(lv["nagg"]), ones - lv["omegaP"] * (Ad @ ones) / np.diag(Ad), atol=1e-14)
+        # R = P^T exactly
+        R = _A(lv["R_rp"], lv["R_ci"], lv["R_v"], shape=(lv["nagg"], lv["n"]))
+        PT = P.T.tocsr()
+        PT.sort_indices()
+        assert np.array_equal(R.indptr, PT.indptr) and np.array_equal(R.indices, PT.indices)
+        assert np.array_equal(R.data, PT.data)
+        # Galerkin product vs dense P^T A P
+        Ac = _A(nxt["A_rp"], nxt["A_ci"], nxt["A_v"]).toarray()
+        ref = Pd.T @ Ad @ Pd
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(Ac - ref)) <= 1e-14 * scale
+        assert np.max(np.abs(Ac - Ac.T)) <= 1e-15 * scale
+        # inverse diagonal
+        assert np.array_equal(lv["dinv"], 1.0 / np.diag(Ad))
+
+
+def test_coarse_factor_vs_lapack(oracle_mod):
+    rp, ci, v = M.diffusion(np.exp(M.grf(20, 2, seed=2)))
+    H = oracle_mod.OracleHierarchy(rp, ci, v)
+    Lf = H.coarse_factor()
+    lc = H.level(H.num_levels - 1)
+    Ac = _A(lc["A_rp"], lc["A_ci"], lc["A_v"]).toarray()
+    Lref = np.linalg.cholesky(Ac)
+    assert np.max(np.abs(Lf - Lref)) <= 1e-13 * np.abs(Lref).max()
+
+
+def test_galerkin_poisson_zero_row_sums_interior(oracle_mod):
+    # With zero-row-sum fine rows away from the boundary, P 1 = 1 there and the
+    # coarse operator annihilates constants on coarse rows whose P-support avoids the boundary.
+    N = 30
+    rp, ci, v = M.poisson(N, 2)
+    H = oracle_mod.OracleHierarchy(rp, ci, v, max_coarse=8, max_levels=2)
+    lv, nxt = H.level(0), H.level(1)
+    A = _A(lv["A_rp"], lv["A_ci"], lv["A_v"])
+    fine_rs = np.asarray(A.sum(axis=1)).ravel()
+    near_bnd = np.abs(fine_rs) > 0
+    G = _A(lv["G_rp"], lv["G_ci"], np.ones(len(lv["G_ci"])))
+    D = shortest_path(G, unweighted=True, directed=False, indices=np.where(near_bnd)[0])
+    dist_b = D.min(axis=0)
+    P = _A(lv["P_rp"], lv["P_ci"], lv["P_v"], shape=(lv["n"], lv["nagg"])).tocsc()
+    Ac = _A(nxt["A_rp"], nxt["A_ci"], nxt["A_v"])
+    rs = np.asarray(Ac.sum(axis=1)).ravel()
+    checked = 0
+    for J in range(lv["nagg"]):
+        sup = P.indices[P.indptr[J]:P.indptr[J + 1]]
+        if dist_b[sup].min() >= 2:
+            assert abs(rs[J]) < 1e-13
+            checked += 1
+    assert checked > 0
+
+
+def test_refresh_equals_fresh_setup(oracle_mod):
+    N = 24
+    k1 = np.exp(M.grf(N, 2, seed=1))
+    k2 = np.exp(M.grf(N, 2, seed=2))
+    rp, ci, v1 = M.diffusion(k1)
+    _, _, v2 = M.diffusion(k2)
+    H = oracle_mod.OracleHierarchy(rp, ci, v1, max_coarse=16)
+    H.update_values(v2)
+    F = oracle_mod.OracleHierarchy(rp, ci, v2, max_coarse=16)
+    assert H.num_levels == F.num_levels
+    for l in range(H.num_levels):
+        a, b = H.level(l), F.level(l)
+        for key in a:
+            if isinstance(a[key], np.ndarray):
+                assert np.array_equal(a[key], b[key]), (l, key)
+    assert np.array_equal(H.coarse_factor(), F.coarse_factor())
+
+
+def test_validation_errors(oracle_mod):
+    rp, ci, v = M.poisson(4, 2)
+    assert oracle_mod.validate(rp, ci) == 0
+    bad = ci.copy()
+    bad[0], bad[1] = bad[1], bad[0]
+    assert oracle_mod.validate(rp, bad) == oracle_mod.OR_ERR_INVALID_ARG      # unsorted
+    bad = ci.copy()
+    bad[1] = bad[0]
+    assert oracle_mod.validate(rp, bad) == oracle_mod.OR_ERR_INVALID_ARG      # duplicate
+    bad = ci.copy()
+    bad[-1] = 99
+    assert oracle_mod.validate(rp, bad) == oracle_mod.OR_ERR_INVALID_ARG      # out of range
+    # missing diagonal: drop row 0's diagonal entry
+    A = _A(rp, ci, v).tolil()
+    A[0, 0] = 0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    assert oracle_mod.validate(A.indptr, A.indices) == oracle_mod.OR_ERR_ZERO_DIAG
+    with pytest.raises(oracle_mod.oracle.OracleError):
+        oracle_mod.OracleHierarchy(A.indptr, A.indices, A.data)
