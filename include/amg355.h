@@ -1,0 +1,201 @@
+/*
+ * amg355.h - C ABI of the MI355X (gfx950) smoothed-aggregation AMG-PCG
+ * library with adjoint solves.
+ *
+ * What the calls compute (the paper delegates the numerical method to its
+ * backend; the operations below are the ones its interface exposes):
+ *   - a sparse solve A x = b returning x plus diagnostics (iterations, final
+ *     residual, convergence status)                   -- Section 2.1/2.2
+ *   - a setup cached per sparsity pattern; a cache hit with new values updates
+ *     the coefficients in place and repeats the numeric setup -- Section 2.1
+ *     ("C++/CUDA backend")
+ *   - the adjoint solve A^T lambda = dL/dx            -- Eq. (1)
+ *   - the gradients dL/dA = -lambda x^T (restricted to the stored pattern)
+ *     and dL/db = lambda                              -- Eq. (2)
+ *   - single- and double-precision arithmetic         -- Section 2.2
+ *
+ * Conventions
+ *   - Matrices are CSR: int32 row_ptr[n+1] (row_ptr[0] = 0,
+ *     row_ptr[n] = nnz), int32 col[nnz] strictly ascending within a row and
+ *     in [0, n), every row holding its diagonal; float64 values.
+ *   - Every array argument is a DEVICE pointer owned by the caller.  The
+ *     library copies what it keeps; it never frees caller memory.
+ *   - All work is ordered on the given hipStream_t (pass the caller's current
+ *     stream).  Calls that report sizes or statuses synchronise that stream.
+ *   - A block of k right-hand sides is stored row-major: element (i, c) at
+ *     [i*k + c].
+ *   - Every entry point returns an amg_status; C++ exceptions never cross
+ *     the ABI.  Non-convergence is a status (AMG_NOT_CONVERGED), not an
+ *     error: x and the info block are still filled.
+ *   - Handles are not thread-safe; calls that overlap on one handle race.
+ */
+#ifndef AMG355_H
+#define AMG355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amg_handle_s* amg_handle;
+
+typedef enum {
+  AMG_OK = 0,
+  AMG_NOT_CONVERGED = 1,            /* maxiter reached; x holds the last iterate */
+  AMG_ERR_INVALID_ARG = -1,         /* bad pointer/size/params or malformed CSR */
+  AMG_ERR_ZERO_DIAG = -2,           /* a row has no stored or a zero diagonal */
+  AMG_ERR_PATTERN_MISMATCH = -3,    /* value update with a different pattern */
+  AMG_ERR_BREAKDOWN = -4,           /* p^T A p <= 0, r^T z <= 0, NaN, or a non-SPD coarse matrix */
+  AMG_ERR_OOM = -5,                 /* device allocation failed */
+  AMG_ERR_HIP = -6,                 /* a HIP runtime call failed */
+  AMG_ERR_COARSE_TOO_LARGE = -7     /* coarsening stalled above the dense coarse-solve limit */
+} amg_status;
+
+enum { AMG_PREC_FP64 = 0, AMG_PREC_FP32 = 1 };
+enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_L1 = 1 };
+enum { AMG_CACHE_COLD = 0, AMG_CACHE_HIT = 1, AMG_CACHE_REFRESH = 2 };
+
+/* Largest coarsest level that receives a dense factorization. */
+#define AMG_MAX_DENSE_COARSE 4096
+#define AMG_MAX_LEVELS 20
+
+typedef struct {
+  int vcycle_prec;     /* AMG_PREC_FP64 (default) or AMG_PREC_FP32 (FP32 V-cycle inside FP64 CG) */
+  int transfer_bf16;   /* FP32 cycle only: P and R values stored as bfloat16 (default 1) */
+  double theta;        /* strength threshold; 0 (default) = every off-diagonal entry is strong */
+  int max_coarse;      /* stop coarsening at or below this many unknowns (default 256) */
+  int max_levels;      /* at most this many levels (default 20, <= AMG_MAX_LEVELS) */
+  int smoother;        /* AMG_SMOOTHER_JACOBI (default, weight omega/a_ii) or AMG_SMOOTHER_L1 */
+  double omega;        /* Jacobi damping (default 2/3) */
+  int nu_pre, nu_post; /* sweeps before/after the coarse correction (default 1, 1) */
+  int maxiter;         /* PCG iteration limit (default 1000) */
+  int flexible;        /* -1 (default): flexible beta iff the cycle is not FP64; 0 standard; 1 flexible */
+  int symmetric;       /* 1 (default): A = A^T, the adjoint reuses A's hierarchy; 0 is rejected */
+  int check_every;     /* PCG iterations queued between convergence checks (default 0 = automatic) */
+} amg_params;
+
+typedef struct {
+  int iters;           /* products A p performed (sum over restarts) */
+  double rel_resid;    /* true ||b - A x||_2 / ||b||_2 in FP64 (max over columns for k > 1) */
+  int status;          /* amg_status of the solve */
+  int cache_event;     /* AMG_CACHE_COLD / HIT / REFRESH of the amg_setup that produced the handle */
+  int restarts;        /* true-residual replacements performed */
+  double setup_ms;     /* wall time of that setup or refresh */
+  double solve_ms;     /* wall time of this solve (host clock, stream synchronised) */
+} amg_info;
+
+typedef struct {
+  int num_levels;
+  int64_t n[AMG_MAX_LEVELS];
+  int64_t nnz[AMG_MAX_LEVELS];       /* nnz of A_l */
+  int64_t nnz_p[AMG_MAX_LEVELS];     /* nnz of P_l = nnz of R_l (0 on the coarsest level) */
+  int64_t nnz_g[AMG_MAX_LEVELS];     /* nnz of the strength graph of level l */
+  double rho[AMG_MAX_LEVELS];        /* Gershgorin bound of rho(D^-1 A_l) */
+  double omega_p[AMG_MAX_LEVELS];    /* prolongator damping (4/3)/rho */
+  int mis_rounds[AMG_MAX_LEVELS];    /* rounds of the parallel independent-set selection */
+  double operator_complexity;        /* sum nnz(A_l) / nnz(A_0) */
+  int group_a[AMG_MAX_LEVELS];       /* lanes per row chosen for A_l, P_l, R_l kernels */
+  int group_p[AMG_MAX_LEVELS];
+  int group_r[AMG_MAX_LEVELS];
+} amg_hier_stats;
+
+/* Fields of a level that amg_export_field can copy out (for bit-exact checks). */
+typedef enum {
+  AMG_FIELD_AGG = 0,       /* int32[n_l]        aggregate of each node */
+  AMG_FIELD_A_ROWPTR = 1,  /* int32[n_l+1] */
+  AMG_FIELD_A_COL = 2,     /* int32[nnz_l] */
+  AMG_FIELD_A_VAL = 3,     /* float64[nnz_l] */
+  AMG_FIELD_A_VAL32 = 4,   /* float32[nnz_l]    (FP32 cycle) */
+  AMG_FIELD_DINV = 5,      /* float64[n_l]      1 / a_ii */
+  AMG_FIELD_P_ROWPTR = 6,  /* int32[n_l+1] */
+  AMG_FIELD_P_COL = 7,     /* int32[nnz_p] */
+  AMG_FIELD_P_VAL = 8,     /* float64[nnz_p] */
+  AMG_FIELD_P_BF16 = 9,    /* uint16[nnz_p]     (FP32 cycle with bf16 transfers) */
+  AMG_FIELD_R_ROWPTR = 10, /* int32[n_{l+1}+1] */
+  AMG_FIELD_R_COL = 11,    /* int32[nnz_p] */
+  AMG_FIELD_R_VAL = 12,    /* float64[nnz_p] */
+  AMG_FIELD_R_BF16 = 13,   /* uint16[nnz_p] */
+  AMG_FIELD_G_ROWPTR = 14, /* int32[n_l+1]      strength graph */
+  AMG_FIELD_G_COL = 15,    /* int32[nnz_g] */
+  AMG_FIELD_COARSE_FACTOR = 16, /* float64[m*m] Cholesky factor of the coarsest A, row-major lower, m = padded size */
+  AMG_FIELD_COARSE_INV = 17,    /* float64[m*m] inverse of the coarsest A */
+  AMG_FIELD_DINV32 = 18    /* float32[n_l] smoother weights of the FP32 cycle */
+} amg_field;
+
+/* Fills *p with the defaults listed above. */
+void amg_params_default(amg_params* p);
+
+/* Setup (Section 2.1, "C++/CUDA backend"): returns a handle to the hierarchy
+ * of A = (row_ptr, col, val), n rows.  The library keeps an LRU cache keyed
+ * by a 64-bit hash of (row_ptr, col, n, nnz, params) with a full pattern
+ * compare on a hit.  Cold: full setup (strength graph, aggregation,
+ * smoothed prolongator, R = P^T, Galerkin R A P per level, inverse
+ * diagonals, coarse factorization).  Hit with identical values: the cached
+ * hierarchy is returned.  Hit with new values: the values are refreshed in
+ * place (aggregates and all patterns kept).  The handle holds one reference
+ * (release with amg_destroy); the cache holds another.
+ * n_systems must be 1.  *out is written only on success. */
+amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
+                     const int32_t* d_col, const double* d_val, int32_t n_systems, hipStream_t stream,
+                     amg_handle* out);
+
+/* Value refresh on the same pattern: recomputes every value of the hierarchy
+ * from d_val (nnz entries) and keeps aggregates and patterns. */
+amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stream);
+
+/* PCG solve A X = B from X0 = 0 for nrhs >= 1 columns (row-major blocks),
+ * preconditioned by one V-cycle per iteration.  Stops when
+ * ||r||_2 <= tol ||b||_2 for the recursive residual, then verifies the true
+ * residual in FP64 and restarts from it (at most 5 times) if it misses.
+ * tol = 0 runs exactly params.maxiter iterations.  info may be null. */
+amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, int32_t nrhs, amg_info* info,
+                     hipStream_t stream);
+
+/* Adjoint solve A^T lambda = g (Eq. (1)) with the same hierarchy, precision
+ * and tolerance rule as amg_solve (A is symmetric, so A's own hierarchy is
+ * the hierarchy of A^T and no transpose is formed). */
+amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, double tol, int32_t nrhs,
+                             amg_info* info, hipStream_t stream);
+
+/* Pattern gradient (Eq. (2)): grad_val[k] = -(lambda[row k] * x[col k]) for
+ * every stored entry k of the level-0 matrix; dL/db is lambda itself. */
+amg_status amg_pattern_grad(amg_handle h, const double* d_lambda, const double* d_x, double* d_grad_val,
+                            hipStream_t stream);
+
+/* One V-cycle z = M^-1 r on the fine level (FP64 in and out, the handle's
+ * cycle precision inside): the preconditioner as an operator. */
+amg_status amg_apply_vcycle(amg_handle h, const double* d_r, double* d_z, hipStream_t stream);
+
+/* Hierarchy statistics (Section 2.2 diagnostics). */
+amg_status amg_hierarchy_stats(amg_handle h, amg_hier_stats* out);
+
+/* Size in elements and bytes per element of a level field. */
+amg_status amg_field_info(amg_handle h, int level, int field, int64_t* count, int* elem_bytes);
+
+/* Device-to-device copy of a level field into d_dst (dst_bytes capacity). */
+amg_status amg_export_field(amg_handle h, int level, int field, void* d_dst, size_t dst_bytes, hipStream_t stream);
+
+/* Releases the caller's reference; the hierarchy is freed when neither a
+ * caller nor the cache holds it. */
+amg_status amg_destroy(amg_handle h);
+
+/* Empties the setup cache (Section 3.4 "finalize"). Handles still held by
+ * callers stay valid until destroyed. */
+amg_status amg_finalize(void);
+
+/* Number of hierarchies currently in the cache; capacity setter (default 8). */
+int amg_cache_size(void);
+amg_status amg_set_cache_capacity(int capacity);
+
+/* Human-readable name of a status. */
+const char* amg_status_string(amg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMG355_H */

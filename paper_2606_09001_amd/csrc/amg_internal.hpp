@@ -1,0 +1,318 @@
+// Internal data structures and device primitives of the gfx950 AMG-PCG library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/amg355.h"
+
+namespace amg {
+
+// ------------------------------------------------------------------ errors
+
+struct Error : std::runtime_error {
+  amg_status status;
+  Error(amg_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define AMG_HIP(call)                                                                                   \
+  do {                                                                                                  \
+    hipError_t e_ = (call);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      throw ::amg::Error(e_ == hipErrorOutOfMemory ? AMG_ERR_OOM : AMG_ERR_HIP,                         \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                           \
+  } while (0)
+
+// --------------------------------------------------------------- memory
+
+// Device buffer owned by a hierarchy.
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  int64_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(int64_t count) {
+    if (count == n && p) return;
+    release();
+    if (count > 0) AMG_HIP(hipMalloc(&p, sizeof(T) * (size_t)count));
+    n = count;
+  }
+  size_t bytes() const { return sizeof(T) * (size_t)n; }
+};
+
+// ------------------------------------------------------------- hierarchy
+
+struct Level {
+  int n = 0;
+  int64_t nnz = 0;
+  DBuf<int> rp, ci;           // A_l pattern
+  DBuf<double> v;             // A_l values
+  DBuf<float> v32;            // FP32 copy (FP32 cycle)
+  DBuf<int> diagpos;          // position of a_ii in row i
+  DBuf<double> dinv;          // 1 / a_ii
+  DBuf<double> sw;            // smoother weight per row (omega/a_ii or 1/sum|a_ij|)
+  DBuf<float> sw32;           // FP32 copy
+  // strength graph
+  DBuf<int> grp, gci;
+  int64_t gnnz = 0;
+  // aggregation (absent on the coarsest level)
+  DBuf<int> agg;
+  int nagg = 0;
+  int mis_rounds = 0;
+  double rho = 0.0, omegaP = 0.0;
+  // prolongator / restriction
+  int64_t pnnz = 0;
+  DBuf<int> prp, pci, rrp, rci, rperm;
+  DBuf<double> pv, rv;
+  DBuf<float> pv32, rv32;     // FP32 transfer copies (when not bf16)
+  DBuf<uint16_t> pbf, rbf;    // bf16 transfer copies
+  // A*P intermediate (kept for value refresh)
+  int64_t apnnz = 0;
+  DBuf<int> aprp, apci;
+  DBuf<double> apv;
+  // cycle work vectors (FP64 and FP32)
+  DBuf<double> x64, b64, r64, xs64, rs64;
+  DBuf<float> x32, b32, r32, xs32, rs32;
+  // kernel shapes
+  int gA = 8, gP = 4, gR = 8;
+};
+
+struct Coarse {
+  int n = 0;        // unknowns of the coarsest level
+  int m = 0;        // padded to a multiple of 16
+  DBuf<double> L;   // m*m Cholesky factor (row-major lower)
+  DBuf<double> inv; // m*m inverse of the coarsest matrix (symmetric)
+  DBuf<float> inv32;
+  DBuf<double> work;
+};
+
+// Device control block of one PCG solve (single right-hand side).
+struct Ctl {
+  double bb, thresh;      // ||b||^2, tol^2 ||b||^2
+  double rz, pq, rr;      // <r,z>, <p,Ap>, <r,r>
+  double rzn, zq;         // new <r,z>, <z,q> (flexible)
+  double alpha, beta;
+  double trr;             // true residual ||b - A x||^2
+  int iters, maxiter;
+  int done;               // nonzero: kernels of the current solve return at once
+  int state;              // 0 running, 1 converged (recursive), 2 iteration limit, -1 breakdown
+  int flexible;
+  int pad_;
+  unsigned int ticket[8];
+};
+
+struct Hierarchy {
+  amg_params prm{};
+  int n = 0;
+  int64_t nnz = 0;
+  std::vector<Level> lv;
+  Coarse co;
+  // solve workspace (level 0, FP64)
+  DBuf<double> r, z, p, q, bcopy;
+  DBuf<double> partials;
+  DBuf<Ctl> ctl;
+  Ctl* h_ctl = nullptr;  // pinned host mirror
+  DBuf<int> flags;       // device error flags / counters
+  int* h_flags = nullptr;
+  // cache bookkeeping
+  uint64_t key = 0;
+  int refs = 0;
+  bool in_cache = false;
+  int cache_event = AMG_CACHE_COLD;
+  double setup_ms = 0.0;
+  bool fp32() const { return prm.vcycle_prec == AMG_PREC_FP32; }
+  bool bf16() const { return fp32() && prm.transfer_bf16; }
+  ~Hierarchy();
+};
+
+// Solve-time options carried by each handle.
+struct SolveOpts {
+  int maxiter;
+  int flexible;     // -1 auto
+  int check_every;  // 0 auto
+};
+
+// setup.hip
+void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const double* d_val, hipStream_t s);
+void refresh_hierarchy(Hierarchy& H, const double* d_val, hipStream_t s);
+void validate_csr(int n, int64_t nnz, const int* d_rp, const int* d_ci, int* d_flags, int* h_flags, hipStream_t s);
+uint64_t pattern_hash(int n, int64_t nnz, const int* d_rp, const int* d_ci, int* d_flags, int* h_flags,
+                      hipStream_t s);
+bool pattern_equal(const Hierarchy& H, const int* d_rp, const int* d_ci, int* d_flags, int* h_flags, hipStream_t s);
+bool values_equal(const Hierarchy& H, const double* d_val, int* d_flags, int* h_flags, hipStream_t s);
+// coarse.hip
+void coarse_setup(Hierarchy& H, hipStream_t s);
+// solve.hip
+void alloc_solve_workspace(Hierarchy& H);
+amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int nrhs,
+                     amg_info* info, hipStream_t s);
+void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s);
+void pattern_grad(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, hipStream_t s);
+void choose_shapes(Hierarchy& H);
+
+// ------------------------------------------------------- device helpers
+
+constexpr int kBlock = 256;        // threads per block of the streaming kernels
+constexpr int kMaxGrid = 2048;     // blocks of the reducing kernels (= partial sums)
+
+__host__ __device__ inline int pow2_ceil(int x) {
+  int g = 1;
+  while (g < x) g <<= 1;
+  return g;
+}
+
+// MurmurHash3 32-bit finalizer (public domain reference hash by A. Appleby).
+__host__ __device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Priority of node i in the independent-set selection (distinct per node).
+__host__ __device__ inline uint64_t mis_key(int i) {
+  return ((uint64_t)fmix32((uint32_t)i) << 32) | (uint64_t)(uint32_t)i;
+}
+
+// float -> bfloat16 bits, round to nearest even; NaN becomes a quiet NaN.
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+template <class T>
+struct ValCvt;
+template <>
+struct ValCvt<double> { __device__ static double f(double v) { return v; } };
+template <>
+struct ValCvt<float> { __device__ static float f(float v) { return v; } };
+template <>
+struct ValCvt<uint16_t> { __device__ static float f(uint16_t v) { return bf16_to_f32(v); } };
+
+#ifdef __HIPCC__
+// Row-shift DPP move of a double within rows of 16 lanes (lanes shifted in
+// from outside the row read 0).
+template <int SHIFT>
+__device__ inline double dpp_row_shr(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x110 + SHIFT, 0xF, 0xF, true);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x110 + SHIFT, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int SHIFT>
+__device__ inline float dpp_row_shr(float v) {
+  int r = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + SHIFT, 0xF, 0xF, true);
+  return __int_as_float(r);
+}
+
+// Sum over aligned groups of G lanes; the total lands in the group's LAST
+// lane (lane % G == G-1).  G <= 16 uses row-shift DPP, wider groups a
+// butterfly through ds_bpermute (every lane then holds the total).
+template <int G, class T>
+__device__ inline T group_sum(T v) {
+  if constexpr (G >= 2) v += dpp_row_shr<1>(v);
+  if constexpr (G >= 4) v += dpp_row_shr<2>(v);
+  if constexpr (G >= 8) v += dpp_row_shr<4>(v);
+  if constexpr (G >= 16) v += dpp_row_shr<8>(v);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+template <int G>
+__device__ inline bool group_leader() {
+  return (threadIdx.x & (G - 1)) == (G - 1);
+}
+
+// Full-wavefront butterfly sum (every lane gets the total, fixed order).
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block sum of NV values; result valid in thread 0.  Uses 8*NV*4 bytes of LDS.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV]) {
+  __shared__ double red[NV][kBlock / 64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int m = 0; m < NV; ++m) v[m] = wave_sum(v[m]);
+  if (l == 0) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) red[m][w] = v[m];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      double s = red[m][0];
+      for (int k = 1; k < kBlock / 64; ++k) s += red[m][k];
+      v[m] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Deterministic grid reduction: every block publishes its NV block sums to
+// partials[m*gridDim.x + blockIdx.x]; the last block to arrive (ticket)
+// reduces them in a fixed order.  Returns true in the last block only, with
+// the totals valid in its thread 0.  The ticket is reset for the next use.
+template <int NV>
+__device__ inline bool grid_sum(double (&v)[NV], double* partials, unsigned int* ticket) {
+  __shared__ bool s_last;
+  block_sum<NV>(v);
+  const int G = gridDim.x;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) partials[m * G + blockIdx.x] = v[m];
+    __threadfence();
+    unsigned int t = atomicAdd(ticket, 1u);
+    s_last = (t == (unsigned)G - 1);
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  double acc[NV];
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock)
+      s += __hip_atomic_load(partials + m * G + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    acc[m] = s;
+  }
+  block_sum<NV>(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m] = acc[m];
+    *ticket = 0u;
+  }
+  return true;
+}
+#endif  // __HIPCC__
+
+}  // namespace amg

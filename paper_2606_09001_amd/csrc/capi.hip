@@ -1,0 +1,383 @@
+// C ABI entry points (include/amg355.h) and the setup cache.
+//
+// Cache (Section 2.1, "C++/CUDA backend"): hierarchies are kept in an LRU
+// list keyed by a 64-bit hash of the full sparsity pattern together with n,
+// nnz and the setup parameters; a hash hit is confirmed by comparing the
+// whole pattern on the device.  A confirmed hit with different values
+// refreshes the hierarchy in place (aggregates and patterns kept).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <mutex>
+
+#include "amg_internal.hpp"
+
+// A caller's reference on a (possibly shared) hierarchy, with its own
+// solve-time options.
+struct amg_handle_s {
+  amg::Hierarchy* H;
+  amg::SolveOpts opts;
+};
+
+namespace amg {
+
+Hierarchy::~Hierarchy() {
+  if (h_ctl) (void)hipHostFree(h_ctl);
+  if (h_flags) (void)hipHostFree(h_flags);
+}
+
+namespace {
+
+std::mutex g_mu;
+std::list<Hierarchy*> g_lru;  // front = most recently used
+int g_capacity = 8;
+
+void release(Hierarchy* H) {
+  if (--H->refs <= 0) delete H;
+}
+
+void evict_to(int cap) {
+  while ((int)g_lru.size() > cap) {
+    Hierarchy* H = g_lru.back();
+    g_lru.pop_back();
+    H->in_cache = false;
+    release(H);
+  }
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  return h;
+}
+
+uint64_t params_hash(const amg_params& p) {
+  uint64_t h = 0x12345678abcdefull;
+  uint64_t t;
+  h = mix(h, (uint64_t)p.vcycle_prec);
+  h = mix(h, (uint64_t)p.transfer_bf16);
+  std::memcpy(&t, &p.theta, 8);
+  h = mix(h, t);
+  h = mix(h, (uint64_t)p.max_coarse);
+  h = mix(h, (uint64_t)p.max_levels);
+  h = mix(h, (uint64_t)p.smoother);
+  std::memcpy(&t, &p.omega, 8);
+  h = mix(h, t);
+  h = mix(h, (uint64_t)p.nu_pre);
+  h = mix(h, (uint64_t)p.nu_post);
+  return h;
+}
+
+bool same_setup_params(const amg_params& a, const amg_params& b) {
+  return a.vcycle_prec == b.vcycle_prec && a.transfer_bf16 == b.transfer_bf16 && a.theta == b.theta &&
+         a.max_coarse == b.max_coarse && a.max_levels == b.max_levels && a.smoother == b.smoother &&
+         a.omega == b.omega && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post;
+}
+
+amg_status check_params(const amg_params& p) {
+  if (p.vcycle_prec != AMG_PREC_FP64 && p.vcycle_prec != AMG_PREC_FP32) return AMG_ERR_INVALID_ARG;
+  if (p.smoother != AMG_SMOOTHER_JACOBI && p.smoother != AMG_SMOOTHER_L1) return AMG_ERR_INVALID_ARG;
+  if (p.max_levels < 1 || p.max_levels > AMG_MAX_LEVELS || p.max_coarse < 1) return AMG_ERR_INVALID_ARG;
+  if (p.nu_pre < 1 || p.nu_post < 1 || p.nu_pre > 8 || p.nu_post > 8) return AMG_ERR_INVALID_ARG;
+  if (!(p.omega > 0.0) || !(p.theta >= 0.0) || p.maxiter < 0) return AMG_ERR_INVALID_ARG;
+  if (p.symmetric != 1) return AMG_ERR_INVALID_ARG;
+  return AMG_OK;
+}
+
+// Scratch flags for calls made before a hierarchy exists.
+struct GlobalFlags {
+  int* d = nullptr;
+  int* h = nullptr;
+  int dev = -1;
+} g_flags;
+
+void ensure_global_flags() {
+  int dev = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  if (g_flags.d && g_flags.dev == dev) return;
+  AMG_HIP(hipMalloc(&g_flags.d, 64));
+  AMG_HIP(hipHostMalloc((void**)&g_flags.h, 64, hipHostMallocDefault));
+  g_flags.dev = dev;
+}
+
+template <class F>
+amg_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    return AMG_ERR_OOM;
+  } catch (...) {
+    return AMG_ERR_HIP;
+  }
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+}  // namespace amg
+
+using namespace amg;
+
+extern "C" {
+
+void amg_params_default(amg_params* p) {
+  if (!p) return;
+  p->vcycle_prec = AMG_PREC_FP64;
+  p->transfer_bf16 = 1;
+  p->theta = 0.0;
+  p->max_coarse = 256;
+  p->max_levels = 20;
+  p->smoother = AMG_SMOOTHER_JACOBI;
+  p->omega = 2.0 / 3.0;
+  p->nu_pre = 1;
+  p->nu_post = 1;
+  p->maxiter = 1000;
+  p->flexible = -1;
+  p->symmetric = 1;
+  p->check_every = 0;
+}
+
+amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
+                     const int32_t* d_col, const double* d_val, int32_t n_systems, hipStream_t stream,
+                     amg_handle* out) {
+  return guarded([&]() -> amg_status {
+    if (!out || !d_row_ptr || !d_col || !d_val || n <= 0 || nnz < n || nnz >= (int64_t)INT32_MAX)
+      return AMG_ERR_INVALID_ARG;
+    if (n_systems != 1) return AMG_ERR_INVALID_ARG;
+    amg_params prm;
+    if (params) prm = *params;
+    else amg_params_default(&prm);
+    amg_status ps = check_params(prm);
+    if (ps != AMG_OK) return ps;
+    auto t0 = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lock(g_mu);
+    ensure_global_flags();
+    validate_csr(n, nnz, d_row_ptr, d_col, g_flags.d, g_flags.h, stream);
+    const uint64_t key = mix(mix(mix(pattern_hash(n, nnz, d_row_ptr, d_col, g_flags.d, g_flags.h, stream),
+                                     (uint64_t)n), (uint64_t)nnz), params_hash(prm));
+    for (auto it = g_lru.begin(); it != g_lru.end(); ++it) {
+      Hierarchy* H = *it;
+      if (H->key != key || H->n != n || H->nnz != nnz || !same_setup_params(H->prm, prm)) continue;
+      if (!pattern_equal(*H, d_row_ptr, d_col, g_flags.d, g_flags.h, stream)) continue;
+      g_lru.splice(g_lru.begin(), g_lru, it);
+      if (values_equal(*H, d_val, g_flags.d, g_flags.h, stream)) {
+        H->cache_event = AMG_CACHE_HIT;
+        H->setup_ms = ms_since(t0);
+      } else {
+        refresh_hierarchy(*H, d_val, stream);
+        H->cache_event = AMG_CACHE_REFRESH;
+        H->setup_ms = ms_since(t0);
+      }
+      ++H->refs;
+      *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every}};
+      return AMG_OK;
+    }
+    Hierarchy* H = new Hierarchy;
+    H->prm = prm;
+    H->n = n;
+    H->nnz = nnz;
+    H->lv.reserve(AMG_MAX_LEVELS + 1);
+    try {
+      H->flags.alloc(16);
+      AMG_HIP(hipHostMalloc((void**)&H->h_flags, 64, hipHostMallocDefault));
+      build_hierarchy(*H, d_row_ptr, d_col, d_val, stream);
+    } catch (...) {
+      (void)hipStreamSynchronize(stream);
+      delete H;
+      throw;
+    }
+    H->key = key;
+    H->cache_event = AMG_CACHE_COLD;
+    H->setup_ms = ms_since(t0);
+    H->refs = 1;  // the caller
+    if (g_capacity > 0) {
+      H->refs += 1;  // the cache
+      H->in_cache = true;
+      g_lru.push_front(H);
+      evict_to(g_capacity);
+    }
+    *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every}};
+    return AMG_OK;
+  });
+}
+
+amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !d_val) return AMG_ERR_INVALID_ARG;
+    auto t0 = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lock(g_mu);
+    refresh_hierarchy(*h->H, d_val, stream);
+    h->H->cache_event = AMG_CACHE_REFRESH;
+    h->H->setup_ms = ms_since(t0);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, int32_t nrhs, amg_info* info,
+                     hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !d_b || !d_x || nrhs < 1 || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
+    return pcg_solve(*h->H, h->opts, d_b, d_x, tol, nrhs, info, stream);
+  });
+}
+
+amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, double tol, int32_t nrhs,
+                             amg_info* info, hipStream_t stream) {
+  // A is symmetric (enforced at setup), so A^T lambda = g is solved with A's
+  // own hierarchy and the forward solver settings (Eq. (1)).
+  return amg_solve(h, d_g, d_lambda, tol, nrhs, info, stream);
+}
+
+amg_status amg_pattern_grad(amg_handle h, const double* d_lambda, const double* d_x, double* d_grad_val,
+                            hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !d_lambda || !d_x || !d_grad_val) return AMG_ERR_INVALID_ARG;
+    pattern_grad(*h->H, d_lambda, d_x, d_grad_val, stream);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_apply_vcycle(amg_handle h, const double* d_r, double* d_z, hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !d_r || !d_z) return AMG_ERR_INVALID_ARG;
+    apply_vcycle(*h->H, d_r, d_z, stream);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_hierarchy_stats(amg_handle h, amg_hier_stats* out) {
+  if (!h || !out) return AMG_ERR_INVALID_ARG;
+  const Hierarchy& H = *h->H;
+  std::memset(out, 0, sizeof(*out));
+  out->num_levels = (int)H.lv.size();
+  double tot = 0.0;
+  for (size_t l = 0; l < H.lv.size() && l < AMG_MAX_LEVELS; ++l) {
+    const Level& L = H.lv[l];
+    out->n[l] = L.n;
+    out->nnz[l] = L.nnz;
+    out->nnz_p[l] = (l + 1 < H.lv.size()) ? L.pnnz : 0;
+    out->nnz_g[l] = (l + 1 < H.lv.size()) ? L.gnnz : 0;
+    out->rho[l] = L.rho;
+    out->omega_p[l] = L.omegaP;
+    out->mis_rounds[l] = L.mis_rounds;
+    out->group_a[l] = L.gA;
+    out->group_p[l] = L.gP;
+    out->group_r[l] = L.gR;
+    tot += (double)L.nnz;
+  }
+  out->operator_complexity = tot / (double)H.lv[0].nnz;
+  return AMG_OK;
+}
+
+static amg_status field_ptr(const Hierarchy& H, int level, int field, const void** p, int64_t* count, int* eb) {
+  if (level < 0 || level >= (int)H.lv.size()) return AMG_ERR_INVALID_ARG;
+  const Level& L = H.lv[level];
+  const bool coarsest = level + 1 == (int)H.lv.size();
+  *p = nullptr;
+  *count = 0;
+  *eb = 0;
+  switch (field) {
+    case AMG_FIELD_AGG: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.agg.p; *count = L.n; *eb = 4; break;
+    case AMG_FIELD_A_ROWPTR: *p = L.rp.p; *count = L.n + 1; *eb = 4; break;
+    case AMG_FIELD_A_COL: *p = L.ci.p; *count = L.nnz; *eb = 4; break;
+    case AMG_FIELD_A_VAL: *p = L.v.p; *count = L.nnz; *eb = 8; break;
+    case AMG_FIELD_A_VAL32: if (!H.fp32()) return AMG_ERR_INVALID_ARG; *p = L.v32.p; *count = L.nnz; *eb = 4; break;
+    case AMG_FIELD_DINV: *p = L.dinv.p; *count = L.n; *eb = 8; break;
+    case AMG_FIELD_DINV32: if (!H.fp32()) return AMG_ERR_INVALID_ARG; *p = L.sw32.p; *count = L.n; *eb = 4; break;
+    case AMG_FIELD_P_ROWPTR: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.prp.p; *count = L.n + 1; *eb = 4; break;
+    case AMG_FIELD_P_COL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.pci.p; *count = L.pnnz; *eb = 4; break;
+    case AMG_FIELD_P_VAL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.pv.p; *count = L.pnnz; *eb = 8; break;
+    case AMG_FIELD_P_BF16: if (coarsest || !H.bf16()) return AMG_ERR_INVALID_ARG; *p = L.pbf.p; *count = L.pnnz; *eb = 2; break;
+    case AMG_FIELD_R_ROWPTR: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.rrp.p; *count = L.nagg + 1; *eb = 4; break;
+    case AMG_FIELD_R_COL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.rci.p; *count = L.pnnz; *eb = 4; break;
+    case AMG_FIELD_R_VAL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.rv.p; *count = L.pnnz; *eb = 8; break;
+    case AMG_FIELD_R_BF16: if (coarsest || !H.bf16()) return AMG_ERR_INVALID_ARG; *p = L.rbf.p; *count = L.pnnz; *eb = 2; break;
+    case AMG_FIELD_G_ROWPTR: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.grp.p; *count = L.n + 1; *eb = 4; break;
+    case AMG_FIELD_G_COL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.gci.p; *count = L.gnnz; *eb = 4; break;
+    case AMG_FIELD_COARSE_FACTOR: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.L.p; *count = (int64_t)H.co.m * H.co.m; *eb = 8; break;
+    case AMG_FIELD_COARSE_INV: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.inv.p; *count = (int64_t)H.co.m * H.co.m; *eb = 8; break;
+    default: return AMG_ERR_INVALID_ARG;
+  }
+  return AMG_OK;
+}
+
+amg_status amg_field_info(amg_handle h, int level, int field, int64_t* count, int* elem_bytes) {
+  if (!h || !count || !elem_bytes) return AMG_ERR_INVALID_ARG;
+  const void* p;
+  return field_ptr(*h->H, level, field, &p, count, elem_bytes);
+}
+
+amg_status amg_export_field(amg_handle h, int level, int field, void* d_dst, size_t dst_bytes, hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !d_dst) return AMG_ERR_INVALID_ARG;
+    const void* p;
+    int64_t count;
+    int eb;
+    amg_status st = field_ptr(*h->H, level, field, &p, &count, &eb);
+    if (st != AMG_OK) return st;
+    size_t bytes = (size_t)count * (size_t)eb;
+    if (dst_bytes < bytes) return AMG_ERR_INVALID_ARG;
+    if (bytes) AMG_HIP(hipMemcpyAsync(d_dst, p, bytes, hipMemcpyDeviceToDevice, stream));
+    AMG_HIP(hipStreamSynchronize(stream));
+    return AMG_OK;
+  });
+}
+
+amg_status amg_destroy(amg_handle h) {
+  if (!h) return AMG_ERR_INVALID_ARG;
+  return guarded([&]() -> amg_status {
+    std::lock_guard<std::mutex> lock(g_mu);
+    (void)hipDeviceSynchronize();
+    release(h->H);
+    delete h;
+    return AMG_OK;
+  });
+}
+
+amg_status amg_finalize(void) {
+  return guarded([&]() -> amg_status {
+    std::lock_guard<std::mutex> lock(g_mu);
+    (void)hipDeviceSynchronize();
+    evict_to(0);
+    return AMG_OK;
+  });
+}
+
+int amg_cache_size(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  return (int)g_lru.size();
+}
+
+amg_status amg_set_cache_capacity(int capacity) {
+  if (capacity < 0) return AMG_ERR_INVALID_ARG;
+  return guarded([&]() -> amg_status {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_capacity = capacity;
+    evict_to(capacity);
+    return AMG_OK;
+  });
+}
+
+const char* amg_status_string(amg_status s) {
+  switch (s) {
+    case AMG_OK: return "AMG_OK";
+    case AMG_NOT_CONVERGED: return "AMG_NOT_CONVERGED";
+    case AMG_ERR_INVALID_ARG: return "AMG_ERR_INVALID_ARG";
+    case AMG_ERR_ZERO_DIAG: return "AMG_ERR_ZERO_DIAG";
+    case AMG_ERR_PATTERN_MISMATCH: return "AMG_ERR_PATTERN_MISMATCH";
+    case AMG_ERR_BREAKDOWN: return "AMG_ERR_BREAKDOWN";
+    case AMG_ERR_OOM: return "AMG_ERR_OOM";
+    case AMG_ERR_HIP: return "AMG_ERR_HIP";
+    case AMG_ERR_COARSE_TOO_LARGE: return "AMG_ERR_COARSE_TOO_LARGE";
+  }
+  return "AMG_UNKNOWN_STATUS";
+}
+
+}  // extern "C"

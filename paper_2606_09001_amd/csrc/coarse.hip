@@ -1,0 +1,195 @@
+// Coarsest-level direct solve: dense FP64 Cholesky factorization of the
+// coarsest Galerkin matrix (right-looking, 16-column panels; the rank-16
+// trailing updates and the inverse product run on the FP64 matrix cores,
+// v_mfma_f64_16x16x4f64), followed by the explicit inverse so that the
+// per-cycle coarse solve is one dense matrix-vector product.
+#include <algorithm>
+
+#include "amg_internal.hpp"
+
+namespace amg {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCoBlock = 256;  // one workgroup, four wavefronts
+
+// Dense m x m (row-major) copy of the CSR matrix; padding rows/cols get the identity.
+__global__ void k_densify(int n, int m, double* __restrict__ W) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t mm = (int64_t)m * m;
+  for (int64_t e = t; e < mm; e += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(e / m), j = (int)(e % m);
+    W[e] = (i == j && i >= n) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void k_scatter(int n, int m, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ W) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) W[(int64_t)i * m + ci[k]] = v[k];
+}
+
+// C_tile(I,J) += A_tile * B_tile^T over 16 columns [k0, k0+16) of row
+// blocks I and J of X (row-major, leading dimension m), with A = sgn * X.
+// Operand layout of v_mfma_f64_16x16x4f64 (wave64): lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; its four accumulator registers hold
+// D[4*e + l/16][l%16], e = 0..3 (one row group per register).
+__device__ inline void mfma_tile_update(double* __restrict__ W, int m, int I, int J, const double* __restrict__ X,
+                                        int ldx, int k0, double sgn) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, q = l >> 4;
+  d4 acc;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) acc[e] = W[(int64_t)(I * 16 + 4 * e + q) * m + J * 16 + r];
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4) {
+    double a = sgn * X[(int64_t)(I * 16 + r) * ldx + k0 + kk + q];
+    double b = X[(int64_t)(J * 16 + r) * ldx + k0 + kk + q];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) W[(int64_t)(I * 16 + 4 * e + q) * m + J * 16 + r] = acc[e];
+}
+
+// In-place Cholesky W = L L^T (lower triangle), one workgroup.  Panel of 16
+// columns: column-by-column right-looking factorization restricted to the
+// panel, then a rank-16 update of the trailing lower triangle on MFMA.
+__global__ void __launch_bounds__(kCoBlock) k_cholesky(int m, double* __restrict__ W, int* flags) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, nwaves = kCoBlock / 64;
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int kb = 0; kb < m; kb += 16) {
+    for (int k = kb; k < kb + 16; ++k) {
+      if (tid == 0) {
+        double d = W[(int64_t)k * m + k];
+        if (!(d > 0.0)) { s_bad = 1; d = 1.0; }
+        W[(int64_t)k * m + k] = sqrt(d);
+      }
+      __syncthreads();
+      const double lkk = W[(int64_t)k * m + k];
+      for (int i = k + 1 + tid; i < m; i += kCoBlock) W[(int64_t)i * m + k] /= lkk;
+      __syncthreads();
+      // update the remaining panel columns j in (k, kb+16), rows i >= j
+      const int ncols = kb + 16 - (k + 1);
+      if (ncols > 0) {
+        const int64_t rows = m - (k + 1);
+        for (int64_t t = tid; t < rows * ncols; t += kCoBlock) {
+          int i = k + 1 + (int)(t / ncols);
+          int j = k + 1 + (int)(t % ncols);
+          if (i >= j) W[(int64_t)i * m + j] -= W[(int64_t)i * m + k] * W[(int64_t)j * m + k];
+        }
+      }
+      __syncthreads();
+    }
+    // trailing update of tiles (I, J), kb/16 < J <= I
+    const int T0 = kb / 16 + 1, T = m / 16;
+    const int nt = T - T0;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int t = wave; t < ntiles; t += nwaves) {
+      // t -> (I, J) with J <= I
+      int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while ((a + 1) * (a + 2) / 2 <= t) ++a;
+      while (a * (a + 1) / 2 > t) --a;
+      int I = T0 + a, J = T0 + (t - a * (a + 1) / 2);
+      mfma_tile_update(W, m, I, J, W, m, kb, -1.0);
+    }
+    __syncthreads();
+  }
+  // zero the strict upper triangle
+  for (int64_t e = tid; e < (int64_t)m * m; e += kCoBlock) {
+    int i = (int)(e / m), j = (int)(e % m);
+    if (j > i) W[e] = 0.0;
+  }
+  if (tid == 0 && s_bad) atomicOr(flags, 1);
+}
+
+// Linv = L^-1 by forward substitution, one column per thread.
+__global__ void k_tri_inverse(int m, const double* __restrict__ L, double* __restrict__ Linv) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  for (int i = 0; i < j; ++i) Linv[(int64_t)i * m + j] = 0.0;
+  Linv[(int64_t)j * m + j] = 1.0 / L[(int64_t)j * m + j];
+  for (int i = j + 1; i < m; ++i) {
+    double s = 0.0;
+    for (int k = j; k < i; ++k) s += L[(int64_t)i * m + k] * Linv[(int64_t)k * m + j];
+    Linv[(int64_t)i * m + j] = -s / L[(int64_t)i * m + i];
+  }
+}
+
+// Transpose (m x m): Y = X^T.
+__global__ void k_transpose(int m, const double* __restrict__ X, double* __restrict__ Y) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  int i = (int)(e / m), j = (int)(e % m);
+  Y[(int64_t)j * m + i] = X[e];
+}
+
+// inv = Linv^T Linv = X X^T with X = Linv^T (row-major): tile (I, J) sums
+// over all 16-column panels of X.  One wavefront per tile.
+__global__ void k_gram(int m, const double* __restrict__ X, double* __restrict__ G) {
+  const int T = m / 16;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= T * T) return;
+  const int I = wave / T, J = wave % T;
+  const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += 16) {
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      double a = X[(int64_t)(I * 16 + r) * m + k0 + kk + q];
+      double b = X[(int64_t)(J * 16 + r) * m + k0 + kk + q];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) G[(int64_t)(I * 16 + 4 * e + q) * m + J * 16 + r] = acc[e];
+}
+
+__global__ void k_inv_to_f32(int64_t mm, const double* __restrict__ a, float* __restrict__ b) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < mm) b[t] = (float)a[t];
+}
+
+}  // namespace
+
+void coarse_setup(Hierarchy& H, hipStream_t s) {
+  Level& L = H.lv.back();
+  Coarse& C = H.co;
+  if (L.n > AMG_MAX_DENSE_COARSE) throw Error(AMG_ERR_COARSE_TOO_LARGE, "coarsest level too large");
+  C.n = L.n;
+  C.m = (L.n + 15) / 16 * 16;
+  const int m = C.m;
+  const int64_t mm = (int64_t)m * m;
+  C.L.alloc(mm);
+  C.inv.alloc(mm);
+  C.work.alloc(mm);
+  int grid = (int)std::min<int64_t>((mm + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_densify, dim3(grid), dim3(kBlock), 0, s, C.n, m, C.L.p);
+  hipLaunchKernelGGL(k_scatter, dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C.n, m, L.rp.p, L.ci.p,
+                     L.v.p, C.L.p);
+  AMG_HIP(hipMemsetAsync(H.flags.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kCoBlock), 0, s, m, C.L.p, H.flags.p);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipMemcpyAsync(H.h_flags, H.flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  if (H.h_flags[0]) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
+  // inverse = L^-T L^-1
+  hipLaunchKernelGGL(k_tri_inverse, dim3((m + 63) / 64), dim3(64), 0, s, m, C.L.p, C.inv.p);
+  hipLaunchKernelGGL(k_transpose, dim3((int)((mm + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, m, C.inv.p,
+                     C.work.p);
+  const int T = m / 16;
+  hipLaunchKernelGGL(k_gram, dim3((T * T * 64 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m, C.work.p, C.inv.p);
+  if (H.fp32()) {
+    C.inv32.alloc(mm);
+    hipLaunchKernelGGL(k_inv_to_f32, dim3((int)((mm + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mm, C.inv.p,
+                       C.inv32.p);
+  }
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace amg

@@ -1,0 +1,841 @@
+// Hierarchy construction on the GPU (smoothed aggregation), bit-exact by
+// construction: every floating-point value is a fixed sequential fold in a
+// canonical order (no atomics on floats, no FMA contraction; built with
+// -ffp-contract=off), and the aggregation is the unique greedy distance-2
+// independent set in decreasing key order, computed by parallel rounds.
+//
+// Setup reuse on a fixed pattern (Section 2.1, "C++/CUDA backend"): the
+// refresh path keeps aggregates and every pattern and recomputes values only.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstring>
+
+#include "amg_internal.hpp"
+
+namespace amg {
+namespace {
+
+enum : int { F_BAD = 1, F_ZERO_DIAG = 2, F_NONSYM = 4, F_NOAGG = 8, F_MISMATCH = 16 };
+enum : int8_t { S_UND = 0, S_ROOT = 1, S_EXCL = 2 };
+
+inline int grid_for(int64_t items, int per_block = kBlock) {
+  int64_t g = (items + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, (int64_t)1 << 30));
+}
+
+void sync_flags(int* d_flags, int* h_flags, int count, hipStream_t s) {
+  AMG_HIP(hipMemcpyAsync(h_flags, d_flags, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+void zero_flags(int* d_flags, int count, hipStream_t s) {
+  AMG_HIP(hipMemsetAsync(d_flags, 0, sizeof(int) * count, s));
+}
+
+// ------------------------------------------------------------ validation
+
+__global__ void k_validate(int n, int64_t nnz, const int* __restrict__ rp, const int* __restrict__ ci,
+                           int* flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = rp[i], e = rp[i + 1];
+  bool bad = (i == 0 && s != 0) || (i == n - 1 && (int64_t)e != nnz) || s < 0 || e < s || (int64_t)e > nnz;
+  if (bad) { atomicOr(flags, F_BAD); return; }
+  bool diag = false;
+  int prev = -1;
+  for (int k = s; k < e; ++k) {
+    int j = ci[k];
+    if (j < 0 || j >= n || j <= prev) { atomicOr(flags, F_BAD); return; }
+    diag |= (j == i);
+    prev = j;
+  }
+  if (!diag) atomicOr(flags, F_ZERO_DIAG);
+}
+
+// ------------------------------------------------------------ hashing
+
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_hash(int n, int64_t nnz, const int* __restrict__ rp, const int* __restrict__ ci,
+                       unsigned long long* out) {
+  uint64_t h = 0;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz; k += stride)
+    h ^= splitmix64(((uint64_t)k << 32) ^ (uint32_t)ci[k]);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n; i += stride)
+    h ^= splitmix64(0x5bd1e995ull ^ ((uint64_t)(i + 1) << 33) ^ (uint32_t)rp[i]);
+  for (int o = 32; o >= 1; o >>= 1) h ^= (uint64_t)__shfl_xor((unsigned long long)h, o, 64);
+  if ((threadIdx.x & 63) == 0 && h) atomicXor(out, (unsigned long long)h);
+}
+
+template <class T>
+__global__ void k_diff(int64_t count, const T* __restrict__ a, const T* __restrict__ b, int* flags) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool d = false;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += stride) d |= (a[k] != b[k]);
+  if (d) atomicOr(flags, F_MISMATCH);
+}
+
+__global__ void k_diff_bits(int64_t count, const double* __restrict__ a, const double* __restrict__ b,
+                            int* flags) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool d = false;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count; k += stride)
+    d |= (__double_as_longlong(a[k]) != __double_as_longlong(b[k]));
+  if (d) atomicOr(flags, F_MISMATCH);
+}
+
+// ------------------------------------------------------- level numerics
+
+// Diagonal position, 1/a_ii and the smoother weight of every row.
+__global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                       int* __restrict__ diagpos, double* __restrict__ dinv, double* __restrict__ sw,
+                       float* __restrict__ sw32, double omega, int l1, int* flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = rp[i], e = rp[i + 1], pos = -1;
+  double asum = 0.0;
+  for (int k = s; k < e; ++k) {
+    if (ci[k] == i) pos = k;
+    asum += fabs(v[k]);
+  }
+  if (pos < 0) {
+    atomicOr(flags, F_ZERO_DIAG);
+    diagpos[i] = s;
+    dinv[i] = 0.0;
+    sw[i] = 0.0;
+    if (sw32) sw32[i] = 0.0f;
+    return;
+  }
+  if (v[pos] == 0.0) atomicOr(flags, F_ZERO_DIAG);
+  diagpos[i] = pos;
+  double d = 1.0 / v[pos];
+  dinv[i] = d;
+  double w = l1 ? 1.0 / asum : omega * d;
+  sw[i] = w;
+  if (sw32) sw32[i] = (float)w;
+}
+
+// Gershgorin bound max_i (sum_j |a_ij|) / |a_ii|; positive doubles order like
+// their bit patterns, so an integer max is exact and order-free.
+__global__ void k_rho(int n, const int* __restrict__ rp, const double* __restrict__ v, const int* __restrict__ diagpos,
+                      unsigned long long* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) s += fabs(v[k]);
+  double r = s / fabs(v[diagpos[i]]);
+  atomicMax(out, (unsigned long long)__double_as_longlong(r));
+}
+
+// ------------------------------------------------------- strength graph
+
+__global__ void k_sym_check(int n, const int* __restrict__ rp, const int* __restrict__ ci, int* flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    int j = ci[k];
+    if (j == i) continue;
+    int lo = rp[j], hi = rp[j + 1] - 1;
+    bool found = false;
+    while (lo <= hi) {
+      int mid = (lo + hi) >> 1;
+      int c = ci[mid];
+      if (c == i) { found = true; break; }
+      if (c < i) lo = mid + 1; else hi = mid - 1;
+    }
+    if (!found) { atomicOr(flags, F_NONSYM); return; }
+  }
+}
+
+// Structurally symmetric pattern, theta = 0: the graph is A's pattern minus
+// the diagonal (exactly one diagonal per row).
+__global__ void k_graph_offdiag(int n, const int* __restrict__ rp, const int* __restrict__ ci, int* __restrict__ grp,
+                                int* __restrict__ gci) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  grp[i] = rp[i] - i;
+  if (i == n) return;
+  int o = rp[i] - i;
+  for (int k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] != i) gci[o++] = ci[k];
+}
+
+__device__ inline bool strong(double aij, double aii, double ajj, double theta) {
+  return theta <= 0.0 || fabs(aij) >= theta * sqrt(fabs(aii * ajj));
+}
+
+__global__ void k_edge_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const double* __restrict__ v, const int* __restrict__ diagpos, double theta,
+                             int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    int j = ci[k];
+    if (j != i && strong(v[k], v[diagpos[i]], v[diagpos[j]], theta)) c += 2;
+  }
+  cnt[i] = c;
+}
+
+__global__ void k_edge_emit(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const double* __restrict__ v, const int* __restrict__ diagpos, double theta,
+                            const int* __restrict__ off, unsigned long long* __restrict__ keys) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = off[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    int j = ci[k];
+    if (j != i && strong(v[k], v[diagpos[i]], v[diagpos[j]], theta)) {
+      keys[o++] = ((unsigned long long)(uint32_t)i << 32) | (uint32_t)j;
+      keys[o++] = ((unsigned long long)(uint32_t)j << 32) | (uint32_t)i;
+    }
+  }
+}
+
+__global__ void k_edge_rows(int64_t m, const unsigned long long* __restrict__ keys, int* __restrict__ cnt,
+                            int* __restrict__ gci) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  unsigned long long k = keys[t];
+  atomicAdd(cnt + (int)(k >> 32), 1);
+  gci[t] = (int)(k & 0xffffffffu);
+}
+
+// ---------------------------------------------------- aggregation rounds
+
+// m1[i] = 1 + max key among undecided nodes in {i} U N(i) (0 if none).
+__global__ void k_mis_m1(int n, const int* __restrict__ grp, const int* __restrict__ gci,
+                         const int8_t* __restrict__ state, unsigned long long* __restrict__ m1) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long best = state[i] == S_UND ? mis_key(i) + 1 : 0;
+  for (int k = grp[i]; k < grp[i + 1]; ++k) {
+    int j = gci[k];
+    if (state[j] == S_UND) best = max(best, (unsigned long long)mis_key(j) + 1);
+  }
+  m1[i] = best;
+}
+
+// An undecided node whose key is the largest among undecided nodes within
+// distance 2 becomes a root.
+__global__ void k_mis_m2(int n, const int* __restrict__ grp, const int* __restrict__ gci,
+                         const unsigned long long* __restrict__ m1, int8_t* __restrict__ state) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || state[i] != S_UND) return;
+  unsigned long long best = m1[i];
+  for (int k = grp[i]; k < grp[i + 1]; ++k) best = max(best, m1[gci[k]]);
+  if (best == mis_key(i) + 1) state[i] = S_ROOT;
+}
+
+__global__ void k_mis_e1(int n, const int* __restrict__ grp, const int* __restrict__ gci,
+                         const int8_t* __restrict__ state, int8_t* __restrict__ e1) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool r = state[i] == S_ROOT;
+  for (int k = grp[i]; k < grp[i + 1] && !r; ++k) r = state[gci[k]] == S_ROOT;
+  e1[i] = r;
+}
+
+// Undecided nodes within distance 2 of a root are excluded; the remaining
+// undecided nodes are counted.
+__global__ void k_mis_e2(int n, const int* __restrict__ grp, const int* __restrict__ gci,
+                         const int8_t* __restrict__ e1, int8_t* __restrict__ state, int* __restrict__ undecided) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int und = 0;
+  if (i < n && state[i] == S_UND) {
+    bool r = e1[i];
+    for (int k = grp[i]; k < grp[i + 1] && !r; ++k) r = e1[gci[k]];
+    if (r) state[i] = S_EXCL; else und = 1;
+  }
+  const unsigned long long m = __ballot(und);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(undecided, (int)__popcll(m));
+}
+
+__global__ void k_is_root(int n, const int8_t* __restrict__ state, int* __restrict__ isroot) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) isroot[i] = state[i] == S_ROOT;
+  if (i == n) isroot[n] = 0;
+}
+
+// Roots take their rank among roots (ascending index); their graph
+// neighbours join them (unique: roots are at least 3 apart).
+__global__ void k_agg_phase12(int n, const int* __restrict__ grp, const int* __restrict__ gci,
+                              const int8_t* __restrict__ state, const int* __restrict__ rank,
+                              int* __restrict__ agg2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a = -1;
+  if (state[i] == S_ROOT) {
+    a = rank[i];
+  } else {
+    for (int k = grp[i]; k < grp[i + 1]; ++k) {
+      int j = gci[k];
+      if (state[j] == S_ROOT) { a = rank[j]; break; }
+    }
+  }
+  agg2[i] = a;
+}
+
+// The remaining nodes join the smallest aggregate among their neighbours
+// assigned in the previous step (reads only that step's state).
+__global__ void k_agg_phase3(int n, const int* __restrict__ grp, const int* __restrict__ gci,
+                             const int* __restrict__ agg2, int* __restrict__ agg, int* flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int a = agg2[i];
+  if (a < 0) {
+    for (int k = grp[i]; k < grp[i + 1]; ++k) {
+      int b = agg2[gci[k]];
+      if (b >= 0 && (a < 0 || b < a)) a = b;
+    }
+    if (a < 0) atomicOr(flags, F_NOAGG);
+  }
+  agg[i] = a;
+}
+
+// ------------------------------------------------------- prolongator
+
+// Number of distinct aggregates touched by row i.
+__global__ void k_p_count(int n, const int* __restrict__ rp, const int* __restrict__ ci, const int* __restrict__ agg,
+                          int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  if (i == n) { cnt[n] = 0; return; }
+  int prev = -1, c = 0;
+  for (;;) {
+    int nxt = INT_MAX;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      int a = agg[ci[k]];
+      if (a > prev && a < nxt) nxt = a;
+    }
+    if (nxt == INT_MAX) break;
+    ++c;
+    prev = nxt;
+  }
+  cnt[i] = c;
+}
+
+// P = (I - omegaP D^-1 A) T: for each touched aggregate J (ascending),
+// s_J = sum of a_ij over j in row i with agg(j) = J in stored order from
+// +0.0, w = omegaP / a_ii, P_iJ = [J == agg(i)] - w*s_J (unfused).
+__global__ void k_p_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                         const int* __restrict__ diagpos, const int* __restrict__ agg, double omegaP,
+                         const int* __restrict__ prp, int* __restrict__ pci, double* __restrict__ pv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double w = omegaP / v[diagpos[i]];
+  int ai = agg[i];
+  int pos = prp[i], prev = -1;
+  for (;;) {
+    int nxt = INT_MAX;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      int a = agg[ci[k]];
+      if (a > prev && a < nxt) nxt = a;
+    }
+    if (nxt == INT_MAX) break;
+    double sJ = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (agg[ci[k]] == nxt) sJ += v[k];
+    double delta = (nxt == ai) ? 1.0 : 0.0;
+    double ws = w * sJ;
+    pci[pos] = nxt;
+    pv[pos] = delta - ws;
+    ++pos;
+    prev = nxt;
+  }
+}
+
+__global__ void k_row_ids(int n, const int* __restrict__ rp, int* __restrict__ rowid) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) rowid[k] = i;
+}
+
+__global__ void k_iota(int64_t m, int* __restrict__ a) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < m) a[t] = (int)t;
+}
+
+__global__ void k_col_count(int64_t m, const int* __restrict__ ci, int* __restrict__ cnt) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < m) atomicAdd(cnt + ci[t], 1);
+}
+
+// R = P^T: entry t of R is entry perm[t] of P (stable sort by column keeps
+// source rows ascending inside each row of R).
+__global__ void k_r_fill(int64_t m, const int* __restrict__ perm, const int* __restrict__ rowid,
+                         const double* __restrict__ pv, int* __restrict__ rci, double* __restrict__ rv) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  int k = perm[t];
+  if (rci) rci[t] = rowid[k];
+  rv[t] = pv[k];
+}
+
+// ------------------------------------------------- canonical products
+
+// Position of column J in the sorted column list [lo, hi), or -1.
+__device__ inline int find_col(const int* __restrict__ ci, int lo, int hi, int J) {
+  --hi;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    int c = ci[mid];
+    if (c == J) return mid;
+    if (c < J) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+// Smallest column > prev in the sorted list [lo, hi), or INT_MAX.
+__device__ inline int next_col(const int* __restrict__ ci, int lo, int hi, int prev) {
+  int a = lo, b = hi;
+  while (a < b) {
+    int mid = (a + b) >> 1;
+    if (ci[mid] <= prev) a = mid + 1; else b = mid;
+  }
+  return a < hi ? ci[a] : INT_MAX;
+}
+
+// Row i of C = X Y: distinct columns over the rows of Y selected by row i of X.
+__global__ void k_spgemm_count(int nrows, const int* __restrict__ xrp, const int* __restrict__ xci,
+                               const int* __restrict__ yrp, const int* __restrict__ yci, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > nrows) return;
+  if (i == nrows) { cnt[nrows] = 0; return; }
+  int prev = -1, c = 0;
+  for (;;) {
+    int nxt = INT_MAX;
+    for (int a = xrp[i]; a < xrp[i + 1]; ++a) {
+      int k = xci[a];
+      nxt = min(nxt, next_col(yci, yrp[k], yrp[k + 1], prev));
+    }
+    if (nxt == INT_MAX) break;
+    ++c;
+    prev = nxt;
+  }
+  cnt[i] = c;
+}
+
+// Values of C = X Y in canonical order: for every output column J
+// (ascending), acc = +0.0 and for every k of row i of X in ascending order
+// with y_kJ stored, acc += x_ik * y_kJ (product rounded, then sum rounded).
+// This is the per-entry order of the row-by-row scatter "for k ascending, for
+// J ascending: acc[J] += x_ik y_kJ".
+__global__ void k_spgemm_fill(int nrows, const int* __restrict__ xrp, const int* __restrict__ xci,
+                              const double* __restrict__ xv, const int* __restrict__ yrp, const int* __restrict__ yci,
+                              const double* __restrict__ yv, const int* __restrict__ crp, int* __restrict__ cci,
+                              double* __restrict__ cv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  int pos = crp[i], prev = -1;
+  for (;;) {
+    int nxt = INT_MAX;
+    for (int a = xrp[i]; a < xrp[i + 1]; ++a) {
+      int k = xci[a];
+      nxt = min(nxt, next_col(yci, yrp[k], yrp[k + 1], prev));
+    }
+    if (nxt == INT_MAX) break;
+    double acc = 0.0;
+    for (int a = xrp[i]; a < xrp[i + 1]; ++a) {
+      int k = xci[a];
+      int q = find_col(yci, yrp[k], yrp[k + 1], nxt);
+      if (q >= 0) {
+        double prod = xv[a] * yv[q];
+        acc = acc + prod;
+      }
+    }
+    if (cci) cci[pos] = nxt;
+    cv[pos] = acc;
+    ++pos;
+    prev = nxt;
+  }
+}
+
+// ------------------------------------------------------ precision copies
+
+__global__ void k_to_f32(int64_t m, const double* __restrict__ a, float* __restrict__ b) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < m) b[t] = (float)a[t];
+}
+
+__global__ void k_to_bf16(int64_t m, const double* __restrict__ a, uint16_t* __restrict__ b) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < m) b[t] = f32_to_bf16((float)a[t]);
+}
+
+// ---------------------------------------------------------- host helpers
+
+template <class F>
+void cub_call(F&& f, hipStream_t s) {
+  size_t tmp = 0;
+  AMG_HIP(f(nullptr, tmp));
+  DBuf<unsigned char> buf;
+  buf.alloc((int64_t)std::max<size_t>(tmp, 1));
+  AMG_HIP(f(buf.p, tmp));
+  AMG_HIP(hipStreamSynchronize(s));  // the temporary buffer is freed on return
+}
+
+// Exclusive scan of cnt[0..m) into out[0..m) (int).
+void exclusive_scan(const int* cnt, int* out, int64_t m, hipStream_t s) {
+  cub_call([&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, cnt, out, (int)m, s); }, s);
+}
+
+int read_int(const int* d, hipStream_t s) {
+  int h = 0;
+  AMG_HIP(hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+void level_numerics(Hierarchy& H, Level& L, hipStream_t s) {
+  L.diagpos.alloc(L.n);
+  L.dinv.alloc(L.n);
+  L.sw.alloc(L.n);
+  if (H.fp32()) L.sw32.alloc(L.n);
+  zero_flags(H.flags.p, 1, s);
+  hipLaunchKernelGGL(k_diag, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p,
+                     L.dinv.p, L.sw.p, H.fp32() ? L.sw32.p : nullptr, H.prm.omega,
+                     (int)(H.prm.smoother == AMG_SMOOTHER_L1), H.flags.p);
+  AMG_HIP(hipGetLastError());
+  sync_flags(H.flags.p, H.h_flags, 1, s);
+  if (H.h_flags[0] & F_ZERO_DIAG) throw Error(AMG_ERR_ZERO_DIAG, "zero diagonal");
+}
+
+void strength_graph(Hierarchy& H, Level& L, hipStream_t s) {
+  L.grp.alloc(L.n + 1);
+  bool fast = H.prm.theta <= 0.0;
+  if (fast) {
+    zero_flags(H.flags.p, 1, s);
+    hipLaunchKernelGGL(k_sym_check, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.ci.p, H.flags.p);
+    sync_flags(H.flags.p, H.h_flags, 1, s);
+    fast = !(H.h_flags[0] & F_NONSYM);
+  }
+  if (fast) {
+    L.gnnz = L.nnz - L.n;
+    L.gci.alloc(std::max<int64_t>(L.gnnz, 1));
+    hipLaunchKernelGGL(k_graph_offdiag, dim3(grid_for(L.n + 1)), dim3(kBlock), 0, s, L.n, L.rp.p, L.ci.p, L.grp.p,
+                       L.gci.p);
+    AMG_HIP(hipGetLastError());
+    return;
+  }
+  // general path: emit (i,j) and (j,i) for every strong entry, sort, unique
+  DBuf<int> cnt, off;
+  cnt.alloc(L.n + 1);
+  off.alloc(L.n + 1);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (L.n + 1), s));
+  hipLaunchKernelGGL(k_edge_count, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.ci.p, L.v.p,
+                     L.diagpos.p, H.prm.theta, cnt.p);
+  exclusive_scan(cnt.p, off.p, L.n + 1, s);
+  int m = read_int(off.p + L.n, s);
+  DBuf<unsigned long long> keys, sorted, uniq;
+  DBuf<int> nuniq;
+  nuniq.alloc(1);
+  int64_t mm = std::max(m, 1);
+  keys.alloc(mm);
+  sorted.alloc(mm);
+  uniq.alloc(mm);
+  hipLaunchKernelGGL(k_edge_emit, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p,
+                     H.prm.theta, off.p, keys.p);
+  cub_call([&](void* t, size_t& b) {
+    return hipcub::DeviceRadixSort::SortKeys(t, b, keys.p, sorted.p, m, 0, 64, s);
+  }, s);
+  cub_call([&](void* t, size_t& b) {
+    return hipcub::DeviceSelect::Unique(t, b, sorted.p, uniq.p, nuniq.p, m, s);
+  }, s);
+  int u = read_int(nuniq.p, s);
+  L.gnnz = u;
+  L.gci.alloc(std::max(u, 1));
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (L.n + 1), s));
+  if (u > 0)
+    hipLaunchKernelGGL(k_edge_rows, dim3(grid_for(u)), dim3(kBlock), 0, s, (int64_t)u, uniq.p, cnt.p, L.gci.p);
+  exclusive_scan(cnt.p, L.grp.p, L.n + 1, s);
+  AMG_HIP(hipGetLastError());
+}
+
+// Returns the number of aggregates.
+int aggregate(Hierarchy& H, Level& L, hipStream_t s) {
+  const int n = L.n;
+  DBuf<int8_t> state, e1;
+  DBuf<unsigned long long> m1;
+  state.alloc(n);
+  e1.alloc(n);
+  m1.alloc(n);
+  AMG_HIP(hipMemsetAsync(state.p, 0, n, s));
+  int rounds = 0;
+  const dim3 g(grid_for(n)), b(kBlock);
+  for (;;) {
+    ++rounds;
+    if (rounds > n + 1) throw Error(AMG_ERR_HIP, "independent-set rounds did not terminate");
+    hipLaunchKernelGGL(k_mis_m1, g, b, 0, s, n, L.grp.p, L.gci.p, state.p, m1.p);
+    hipLaunchKernelGGL(k_mis_m2, g, b, 0, s, n, L.grp.p, L.gci.p, m1.p, state.p);
+    hipLaunchKernelGGL(k_mis_e1, g, b, 0, s, n, L.grp.p, L.gci.p, state.p, e1.p);
+    zero_flags(H.flags.p + 1, 1, s);
+    hipLaunchKernelGGL(k_mis_e2, g, b, 0, s, n, L.grp.p, L.gci.p, e1.p, state.p, H.flags.p + 1);
+    AMG_HIP(hipGetLastError());
+    sync_flags(H.flags.p + 1, H.h_flags + 1, 1, s);
+    if (H.h_flags[1] == 0) break;
+  }
+  L.mis_rounds = rounds;
+  DBuf<int> isroot, rank, agg2;
+  isroot.alloc(n + 1);
+  rank.alloc(n + 1);
+  agg2.alloc(n);
+  hipLaunchKernelGGL(k_is_root, dim3(grid_for(n + 1)), b, 0, s, n, state.p, isroot.p);
+  exclusive_scan(isroot.p, rank.p, n + 1, s);
+  int nagg = read_int(rank.p + n, s);
+  hipLaunchKernelGGL(k_agg_phase12, g, b, 0, s, n, L.grp.p, L.gci.p, state.p, rank.p, agg2.p);
+  L.agg.alloc(n);
+  zero_flags(H.flags.p, 1, s);
+  hipLaunchKernelGGL(k_agg_phase3, g, b, 0, s, n, L.grp.p, L.gci.p, agg2.p, L.agg.p, H.flags.p);
+  AMG_HIP(hipGetLastError());
+  sync_flags(H.flags.p, H.h_flags, 1, s);
+  if (H.h_flags[0] & F_NOAGG) throw Error(AMG_ERR_HIP, "aggregation left a node unassigned");
+  return nagg;
+}
+
+double gershgorin(Hierarchy& H, Level& L, hipStream_t s) {
+  DBuf<unsigned long long> r;
+  r.alloc(1);
+  AMG_HIP(hipMemsetAsync(r.p, 0, sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(k_rho, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.v.p, L.diagpos.p, r.p);
+  AMG_HIP(hipGetLastError());
+  unsigned long long bits = 0;
+  AMG_HIP(hipMemcpyAsync(&bits, r.p, sizeof(bits), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  double rho;
+  std::memcpy(&rho, &bits, sizeof(rho));
+  return rho;
+}
+
+// Builds P, R and the Galerkin operator of level l+1 (symbolic when
+// `symbolic`, else reusing the stored patterns).
+void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s) {
+  Level& L = H.lv[l];
+  const int n = L.n;
+  const dim3 b(kBlock);
+  L.rho = gershgorin(H, L, s);
+  L.omegaP = (4.0 / 3.0) / L.rho;
+  // P
+  if (symbolic) {
+    DBuf<int> cnt;
+    cnt.alloc(n + 1);
+    hipLaunchKernelGGL(k_p_count, dim3(grid_for(n + 1)), b, 0, s, n, L.rp.p, L.ci.p, L.agg.p, cnt.p);
+    L.prp.alloc(n + 1);
+    exclusive_scan(cnt.p, L.prp.p, n + 1, s);
+    L.pnnz = read_int(L.prp.p + n, s);
+    L.pci.alloc(L.pnnz);
+    L.pv.alloc(L.pnnz);
+  }
+  hipLaunchKernelGGL(k_p_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.agg.p, L.omegaP,
+                     L.prp.p, L.pci.p, L.pv.p);
+  AMG_HIP(hipGetLastError());
+  // R = P^T
+  const int nc = L.nagg;
+  if (symbolic) {
+    DBuf<int> rowid, iota, keys_out, cnt;
+    rowid.alloc(L.pnnz);
+    iota.alloc(L.pnnz);
+    keys_out.alloc(L.pnnz);
+    L.rperm.alloc(L.pnnz);
+    hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n)), b, 0, s, n, L.prp.p, rowid.p);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, iota.p);
+    int end_bit = 1;
+    while ((1ll << end_bit) < (long long)nc) ++end_bit;
+    cub_call([&](void* t, size_t& bb) {
+      return hipcub::DeviceRadixSort::SortPairs(t, bb, L.pci.p, keys_out.p, iota.p, L.rperm.p, (int)L.pnnz, 0,
+                                                end_bit, s);
+    }, s);
+    cnt.alloc(nc + 1);
+    AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (nc + 1), s));
+    hipLaunchKernelGGL(k_col_count, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.pci.p, cnt.p);
+    L.rrp.alloc(nc + 1);
+    exclusive_scan(cnt.p, L.rrp.p, nc + 1, s);
+    L.rci.alloc(L.pnnz);
+    L.rv.alloc(L.pnnz);
+    hipLaunchKernelGGL(k_r_fill, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rperm.p, rowid.p, L.pv.p, L.rci.p,
+                       L.rv.p);
+    AMG_HIP(hipStreamSynchronize(s));
+  } else {
+    hipLaunchKernelGGL(k_r_fill, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rperm.p, (const int*)nullptr, L.pv.p,
+                       (int*)nullptr, L.rv.p);
+  }
+  AMG_HIP(hipGetLastError());
+  // AP = A P
+  if (symbolic) {
+    DBuf<int> cnt;
+    cnt.alloc(n + 1);
+    hipLaunchKernelGGL(k_spgemm_count, dim3(grid_for(n + 1)), b, 0, s, n, L.rp.p, L.ci.p, L.prp.p, L.pci.p, cnt.p);
+    L.aprp.alloc(n + 1);
+    exclusive_scan(cnt.p, L.aprp.p, n + 1, s);
+    L.apnnz = read_int(L.aprp.p + n, s);
+    L.apci.alloc(L.apnnz);
+    L.apv.alloc(L.apnnz);
+  }
+  hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p,
+                     L.aprp.p, symbolic ? L.apci.p : (int*)nullptr, L.apv.p);
+  AMG_HIP(hipGetLastError());
+  // A_{l+1} = R (A P)
+  if (symbolic) {
+    H.lv.emplace_back();
+  }
+  Level& C = H.lv[l + 1];
+  Level& Lr = H.lv[l];  // re-fetch: emplace_back may reallocate
+  if (symbolic) {
+    C.n = nc;
+    DBuf<int> cnt;
+    cnt.alloc(nc + 1);
+    hipLaunchKernelGGL(k_spgemm_count, dim3(grid_for(nc + 1)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p,
+                       cnt.p);
+    C.rp.alloc(nc + 1);
+    exclusive_scan(cnt.p, C.rp.p, nc + 1, s);
+    C.nnz = read_int(C.rp.p + nc, s);
+    C.ci.alloc(C.nnz);
+    C.v.alloc(C.nnz);
+  }
+  hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(nc)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.rv.p, Lr.aprp.p,
+                     Lr.apci.p, Lr.apv.p, C.rp.p, symbolic ? C.ci.p : (int*)nullptr, C.v.p);
+  AMG_HIP(hipGetLastError());
+}
+
+void precision_copies(Hierarchy& H, hipStream_t s) {
+  if (!H.fp32()) return;
+  const dim3 b(kBlock);
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    Level& L = H.lv[l];
+    L.v32.alloc(L.nnz);
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.nnz)), b, 0, s, L.nnz, L.v.p, L.v32.p);
+    if (l + 1 == H.lv.size()) break;
+    if (H.bf16()) {
+      L.pbf.alloc(L.pnnz);
+      L.rbf.alloc(L.pnnz);
+      hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.pv.p, L.pbf.p);
+      hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rv.p, L.rbf.p);
+    } else {
+      L.pv32.alloc(L.pnnz);
+      L.rv32.alloc(L.pnnz);
+      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.pv.p, L.pv32.p);
+      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rv.p, L.rv32.p);
+    }
+  }
+  AMG_HIP(hipGetLastError());
+}
+
+void alloc_cycle_vectors(Hierarchy& H) {
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    Level& L = H.lv[l];
+    if (H.fp32()) {
+      L.x32.alloc(L.n);
+      L.b32.alloc(L.n);
+      L.r32.alloc(L.n);
+    } else {
+      L.x64.alloc(L.n);
+      L.b64.alloc(L.n);
+      L.r64.alloc(L.n);
+    }
+  }
+}
+
+}  // namespace
+
+// ================================================================ public
+
+void validate_csr(int n, int64_t nnz, const int* d_rp, const int* d_ci, int* d_flags, int* h_flags, hipStream_t s) {
+  zero_flags(d_flags, 1, s);
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(n)), dim3(kBlock), 0, s, n, nnz, d_rp, d_ci, d_flags);
+  AMG_HIP(hipGetLastError());
+  sync_flags(d_flags, h_flags, 1, s);
+  if (h_flags[0] & F_BAD) throw Error(AMG_ERR_INVALID_ARG, "malformed CSR");
+  if (h_flags[0] & F_ZERO_DIAG) throw Error(AMG_ERR_ZERO_DIAG, "row without a stored diagonal");
+}
+
+uint64_t pattern_hash(int n, int64_t nnz, const int* d_rp, const int* d_ci, int* d_flags, int* h_flags,
+                      hipStream_t s) {
+  AMG_HIP(hipMemsetAsync(d_flags, 0, 8, s));
+  hipLaunchKernelGGL(k_hash, dim3(1024), dim3(kBlock), 0, s, n, nnz, d_rp, d_ci, (unsigned long long*)d_flags);
+  AMG_HIP(hipGetLastError());
+  sync_flags(d_flags, h_flags, 2, s);
+  uint64_t h;
+  std::memcpy(&h, h_flags, 8);
+  return h;
+}
+
+bool pattern_equal(const Hierarchy& H, const int* d_rp, const int* d_ci, int* d_flags, int* h_flags, hipStream_t s) {
+  const Level& L = H.lv[0];
+  zero_flags(d_flags, 1, s);
+  hipLaunchKernelGGL(k_diff<int>, dim3(1024), dim3(kBlock), 0, s, (int64_t)L.n + 1, d_rp, L.rp.p, d_flags);
+  hipLaunchKernelGGL(k_diff<int>, dim3(1024), dim3(kBlock), 0, s, L.nnz, d_ci, L.ci.p, d_flags);
+  AMG_HIP(hipGetLastError());
+  sync_flags(d_flags, h_flags, 1, s);
+  return !(h_flags[0] & F_MISMATCH);
+}
+
+bool values_equal(const Hierarchy& H, const double* d_val, int* d_flags, int* h_flags, hipStream_t s) {
+  const Level& L = H.lv[0];
+  zero_flags(d_flags, 1, s);
+  hipLaunchKernelGGL(k_diff_bits, dim3(1024), dim3(kBlock), 0, s, L.nnz, d_val, L.v.p, d_flags);
+  AMG_HIP(hipGetLastError());
+  sync_flags(d_flags, h_flags, 1, s);
+  return !(h_flags[0] & F_MISMATCH);
+}
+
+void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const double* d_val, hipStream_t s) {
+  H.lv.clear();
+  H.lv.emplace_back();
+  {
+    Level& L0 = H.lv[0];
+    L0.n = H.n;
+    L0.nnz = H.nnz;
+    L0.rp.alloc(H.n + 1);
+    L0.ci.alloc(H.nnz);
+    L0.v.alloc(H.nnz);
+    AMG_HIP(hipMemcpyAsync(L0.rp.p, d_rp, L0.rp.bytes(), hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipMemcpyAsync(L0.ci.p, d_ci, L0.ci.bytes(), hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipMemcpyAsync(L0.v.p, d_val, L0.v.bytes(), hipMemcpyDeviceToDevice, s));
+  }
+  for (size_t l = 0;; ++l) {
+    Level& L = H.lv[l];
+    level_numerics(H, L, s);
+    bool last = L.n <= H.prm.max_coarse || (int)(l + 1) >= H.prm.max_levels;
+    if (!last) {
+      strength_graph(H, L, s);
+      L.nagg = aggregate(H, L, s);
+      if (10LL * L.nagg > 9LL * L.n) last = true;
+    }
+    if (last) {
+      L.agg.release();
+      L.nagg = 0;
+      break;
+    }
+    transfer_and_galerkin(H, l, true, s);
+  }
+  coarse_setup(H, s);
+  precision_copies(H, s);
+  alloc_cycle_vectors(H);
+  choose_shapes(H);
+  alloc_solve_workspace(H);
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+void refresh_hierarchy(Hierarchy& H, const double* d_val, hipStream_t s) {
+  Level& L0 = H.lv[0];
+  AMG_HIP(hipMemcpyAsync(L0.v.p, d_val, L0.v.bytes(), hipMemcpyDeviceToDevice, s));
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    level_numerics(H, H.lv[l], s);
+    if (l + 1 == H.lv.size()) break;
+    transfer_and_galerkin(H, l, false, s);
+  }
+  coarse_setup(H, s);
+  precision_copies(H, s);
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace amg

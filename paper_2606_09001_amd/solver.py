@@ -1,0 +1,238 @@
+"""Torch-facing API over the C ABI: hierarchy handles, solve, and autograd.
+
+Section 2.1 ("Python API" / "JAX integration"): a single solve entry point
+returning (x, info), with a reverse-mode rule that solves the adjoint system
+A^T lambda = dL/dx (Eq. (1)) on the cached hierarchy and returns
+dL/dA = -lambda x^T on the stored pattern and dL/db = lambda (Eq. (2)).
+Torch only supplies device memory and the stream; every arithmetic step runs
+in libamg355.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+__all__ = ["AmgHierarchy", "solve", "amg_solve", "AmgSolve", "make_params", "finalize", "cache_size",
+           "set_cache_capacity", "make_preconditioner"]
+
+_PARAM_KEYS = ("vcycle_prec", "transfer_bf16", "theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre",
+               "nu_post", "maxiter", "flexible", "symmetric", "check_every")
+
+
+def make_params(**kw) -> _lib.amg_params:
+    """amg_params with the library defaults, overridden by keyword (Section 2.2:
+    users set only the parameters they change).  Accepts 'fp64'/'fp32' for
+    vcycle_prec and 'jacobi'/'l1' for smoother."""
+    L = _lib.load()
+    p = _lib.amg_params()
+    L.amg_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k not in _PARAM_KEYS:
+            raise TypeError(f"unknown AMG parameter {k!r}")
+        if k == "vcycle_prec" and isinstance(v, str):
+            v = {"fp64": _lib.AMG_PREC_FP64, "fp32": _lib.AMG_PREC_FP32, "mixed": _lib.AMG_PREC_FP32}[v]
+        if k == "smoother" and isinstance(v, str):
+            v = {"jacobi": _lib.AMG_SMOOTHER_JACOBI, "l1": _lib.AMG_SMOOTHER_L1}[v]
+        setattr(p, k, v)
+    return p
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_i32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != torch.int32:
+        t = t.to(torch.int32)
+    return t.contiguous()
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:          # automatic promotion (Section 2.2)
+        t = t.to(torch.float64)
+    return t.contiguous()
+
+
+class AmgHierarchy:
+    """Handle on a cached smoothed-aggregation hierarchy of a CSR matrix.
+
+    Construction calls amg_setup: a cold setup, a cache hit, or an in-place
+    value refresh when the same pattern arrives with new values.
+    """
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, **params):
+        self._L = _lib.load()
+        self.row_ptr = _dev_i32(row_ptr, "row_ptr")
+        self.col = _dev_i32(col, "col")
+        val = _dev_f64(val, "val")
+        self.n = self.row_ptr.numel() - 1
+        self.nnz = self.col.numel()
+        if val.numel() != self.nnz:
+            raise ValueError("val and col must have the same length")
+        self.params = make_params(**params)
+        h = C.c_void_p()
+        st = self._L.amg_setup(C.byref(self.params), self.n, self.nnz, self.row_ptr.data_ptr(),
+                               self.col.data_ptr(), val.data_ptr(), 1, _stream(), C.byref(h))
+        _lib.check(st, "amg_setup")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._L.amg_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update_values(self, val: torch.Tensor):
+        val = _dev_f64(val, "val")
+        _lib.check(self._L.amg_update_values(self._h, val.data_ptr(), _stream()), "amg_update_values")
+
+    def _solve(self, fn, b: torch.Tensor, tol: float, out: Optional[torch.Tensor]):
+        b = _dev_f64(b, "b")
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        if b.shape[0] != self.n:
+            raise ValueError(f"rhs has {b.shape[0]} rows, matrix has {self.n}")
+        x = torch.empty_like(b) if out is None else out
+        info = _lib.amg_info()
+        st = fn(self._h, b.data_ptr(), x.data_ptr(), float(tol), nrhs, C.byref(info), _stream())
+        _lib.check(st, fn.__name__, allow=(_lib.AMG_OK, _lib.AMG_NOT_CONVERGED))
+        d = info.to_dict()
+        d["converged"] = st == _lib.AMG_OK
+        return x, d
+
+    def solve(self, b: torch.Tensor, tol: float = 1e-8, out: Optional[torch.Tensor] = None):
+        """x with A x = b (x0 = 0); returns (x, info)."""
+        return self._solve(self._L.amg_solve, b, tol, out)
+
+    def solve_adjoint(self, g: torch.Tensor, tol: float = 1e-8, out: Optional[torch.Tensor] = None):
+        """lambda with A^T lambda = g (Eq. (1)); returns (lambda, info)."""
+        return self._solve(self._L.amg_solve_adjoint, g, tol, out)
+
+    def pattern_grad(self, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+        """dL/dA on the stored pattern: -(lambda_i x_j) per entry (Eq. (2))."""
+        lam = _dev_f64(lam, "lambda")
+        x = _dev_f64(x, "x")
+        g = torch.empty(self.nnz, dtype=torch.float64, device=lam.device)
+        _lib.check(self._L.amg_pattern_grad(self._h, lam.data_ptr(), x.data_ptr(), g.data_ptr(), _stream()),
+                   "amg_pattern_grad")
+        return g
+
+    def apply_vcycle(self, r: torch.Tensor) -> torch.Tensor:
+        """z = M^-1 r, one V-cycle (the preconditioner as an operator)."""
+        r = _dev_f64(r, "r")
+        z = torch.empty_like(r)
+        _lib.check(self._L.amg_apply_vcycle(self._h, r.data_ptr(), z.data_ptr(), _stream()), "amg_apply_vcycle")
+        return z
+
+    def stats(self) -> dict:
+        s = _lib.amg_hier_stats()
+        _lib.check(self._L.amg_hierarchy_stats(self._h, C.byref(s)), "amg_hierarchy_stats")
+        return s.to_dict()
+
+    def export(self, level: int, field: str) -> torch.Tensor:
+        """Copy of one level array (aggregates, A, P, R, strength graph, coarse factor...)."""
+        fid = _lib.FIELDS[field]
+        count = C.c_int64(0)
+        eb = C.c_int(0)
+        _lib.check(self._L.amg_field_info(self._h, level, fid, C.byref(count), C.byref(eb)), "amg_field_info")
+        dtype = {(4, False): torch.int32, (8, False): torch.float64, (2, False): torch.int16}[(eb.value, False)]
+        if field in ("A_v32", "sw32"):
+            dtype = torch.float32
+        t = torch.empty(max(count.value, 1), dtype=dtype, device="cuda")
+        _lib.check(self._L.amg_export_field(self._h, level, fid, t.data_ptr(), t.numel() * t.element_size(),
+                                            _stream()), "amg_export_field")
+        return t[:count.value]
+
+
+def solve(A, b: torch.Tensor, tol: float = 1e-8, **params):
+    """Solve A x = b; A is (row_ptr, col, val) or a torch sparse CSR tensor.
+    Returns (x, info) (Section 3.1)."""
+    row_ptr, col, val = _unpack(A)
+    h = AmgHierarchy(row_ptr, col, val, **params)
+    try:
+        return h.solve(b, tol)
+    finally:
+        h.close()
+
+
+def _unpack(A):
+    if isinstance(A, torch.Tensor) and A.layout == torch.sparse_csr:
+        return A.crow_indices(), A.col_indices(), A.values()
+    return A
+
+
+class AmgSolve(torch.autograd.Function):
+    """x = A^-1 b with A = CSR(row_ptr, col, val), differentiable in val and b.
+
+    Backward (Eq. (1)-(2)): A^T lambda = dL/dx on the cached hierarchy
+    (A symmetric: A's own hierarchy, no transpose formed); grad_val =
+    -(lambda_i x_j) on the stored entries; grad_b = lambda.
+    """
+
+    @staticmethod
+    def forward(ctx, row_ptr, col, val, b, tol, params):
+        kw = dict(params)
+        h = AmgHierarchy(row_ptr, col, val, **kw)
+        try:
+            x, info = h.solve(b, tol)
+        finally:
+            h.close()
+        ctx.save_for_backward(row_ptr, col, val, x)
+        ctx.tol = tol
+        ctx.params = kw
+        ctx.info = info
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        row_ptr, col, val, x = ctx.saved_tensors
+        # a cache hit: same pattern and values as the forward solve
+        h = AmgHierarchy(row_ptr, col, val.detach(), **ctx.params)
+        try:
+            lam, _ = h.solve_adjoint(gx.contiguous(), ctx.tol)
+            gval = h.pattern_grad(lam, x) if ctx.needs_input_grad[2] else None
+        finally:
+            h.close()
+        gb = lam if ctx.needs_input_grad[3] else None
+        return None, None, gval, gb, None, None
+
+
+def amg_solve(row_ptr, col, val, b, tol: float = 1e-8, **params):
+    """Differentiable solve (autograd through val and b)."""
+    return AmgSolve.apply(row_ptr, col, val, b, tol, tuple(sorted(params.items())))
+
+
+def make_preconditioner(row_ptr, col, val, **params):
+    """The V-cycle as a callable r -> M^-1 r for other Krylov solvers (Section 2.2)."""
+    h = AmgHierarchy(row_ptr, col, val, **params)
+    return h.apply_vcycle
+
+
+def finalize():
+    """Empty the setup cache (Section 3.4)."""
+    _lib.check(_lib.load().amg_finalize(), "amg_finalize")
+
+
+def cache_size() -> int:
+    return _lib.load().amg_cache_size()
+
+
+def set_cache_capacity(n: int):
+    _lib.check(_lib.load().amg_set_cache_capacity(n), "amg_set_cache_capacity")

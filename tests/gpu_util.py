@@ -1,0 +1,60 @@
+"""Helpers shared by the GPU parity tests (host/device copies, pairing a HIP
+hierarchy with an oracle hierarchy built from the same seeded inputs)."""
+import numpy as np
+import torch
+
+ORACLE_KEYS = ("theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre", "nu_post")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def pair(rp, ci, v, **kw):
+    """(HIP hierarchy, oracle hierarchy) for the same matrix and parameters."""
+    import oracle
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    print(f"[case] n={len(rp) - 1} nnz={len(ci)} params={kw}", flush=True)
+    okw = {k: kw[k] for k in ORACLE_KEYS if k in kw}
+    O = oracle.OracleHierarchy(rp, ci, v, **okw)
+    H = AmgHierarchy(dev(rp), dev(ci), dev(v), **kw)
+    return H, O
+
+
+def assert_hierarchy_bitexact(H, O, mixed=False):
+    st = H.stats()
+    assert st["num_levels"] == O.num_levels, (st["num_levels"], O.num_levels)
+    for l in range(O.num_levels):
+        o = O.level(l)
+        coarsest = l == O.num_levels - 1
+        assert st["n"][l] == o["n"]
+        names = ["A_rp", "A_ci", "A_v", "dinv"]
+        if not coarsest:
+            names += ["agg", "P_rp", "P_ci", "P_v", "R_rp", "R_ci", "R_v", "G_rp", "G_ci"]
+            assert st["rho"][l] == o["rho"] and st["omega_p"][l] == o["omegaP"], l
+        for name in names:
+            g = host(H.export(l, name))
+            ref = o[name]
+            assert g.shape == ref.shape, (l, name, g.shape, ref.shape)
+            if ref.dtype == np.float64:
+                assert np.array_equal(g.view(np.int64), ref.view(np.int64)), (l, name)
+            else:
+                assert np.array_equal(g, ref), (l, name)
+        if mixed:
+            a32 = host(H.export(l, "A_v32"))
+            assert np.array_equal(a32, o["A_v"].astype(np.float32)), (l, "A_v32")
+            if not coarsest:
+                for name, src in (("P_bf16", "P_v"), ("R_bf16", "R_v")):
+                    gb = host(H.export(l, name)).view(np.uint16)
+                    ref = torch.from_numpy(o[src].astype(np.float32)).to(torch.bfloat16).view(torch.int16)
+                    assert np.array_equal(gb, ref.numpy().view(np.uint16)), (l, name)
+    # coarse factor: tolerance (different summation order)
+    Lo = O.coarse_factor()
+    nL = Lo.shape[0]
+    m = int(round(np.sqrt(H.export(O.num_levels - 1, "coarse_factor").numel())))
+    Lg = host(H.export(O.num_levels - 1, "coarse_factor")).reshape(m, m)[:nL, :nL]
+    assert np.max(np.abs(Lg - Lo)) <= 1e-12 * np.abs(Lo).max()

@@ -1,0 +1,231 @@
+"""HIP path vs the FP64 oracle, element by element, on seeded inputs.
+
+Bars: hierarchy arrays (aggregates, every pattern, FP64 values of A_l, P, R,
+1/a_ii, their FP32/bf16 copies) bit-exact; coarse factor to 1e-12; FP64
+solution at equal iteration count to 1e-9 relative; iteration counts within
+one; mixed-precision true residual <= tolerance; adjoint and gradients to
+1e-5 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_09001_amd import matrices as M
+from gpu_util import dev, host, pair, assert_hierarchy_bitexact
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_spd(n, p, seed):
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    U = sp.random(n, n, density=p, random_state=rng, format="csr")
+    U.data[:] = 1.0
+    G = ((U + U.T) > 0).astype(float)
+    G.setdiag(0)
+    G.eliminate_zeros()
+    w = rng.uniform(0.5, 2.0, G.nnz)
+    G.data[:] = w
+    G = (G + G.T) * 0.5
+    deg = np.asarray(abs(G).sum(axis=1)).ravel()
+    A = (sp.diags(deg + 0.1) - G).tocsr()
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+CASES = {
+    "poisson2d_32": lambda: M.poisson(32, 2),
+    "poisson2d_75": lambda: M.poisson(75, 2),
+    "diffusion2d_64": lambda: M.diffusion(np.exp(M.grf(64, 2, seed=3))),
+    "poisson3d_24": lambda: M.poisson(24, 3),
+    "diffusion3d_21": lambda: M.diffusion(np.exp(M.grf(21, 3, seed=4))),
+    "tridiag_3000": lambda: M.tridiagonal(3000, 2.5),
+    "random_spd_700": lambda: _random_spd(700, 0.01, 5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("kw", [dict(), dict(max_coarse=12)], ids=["default", "deep"])
+def test_hierarchy_bitexact(case, kw):
+    rp, ci, v = CASES[case]()
+    H, O = pair(rp, ci, v, **kw)
+    assert_hierarchy_bitexact(H, O)
+
+
+@pytest.mark.parametrize("case", ["diffusion3d_21", "poisson2d_75"])
+def test_hierarchy_bitexact_mixed_copies(case):
+    rp, ci, v = CASES[case]()
+    H, O = pair(rp, ci, v, vcycle_prec="fp32", max_coarse=20)
+    assert_hierarchy_bitexact(H, O, mixed=True)
+
+
+@pytest.mark.parametrize("kw", [dict(theta=0.08), dict(smoother="l1"), dict(nu_pre=2, nu_post=3)],
+                         ids=["theta", "l1", "nu23"])
+def test_hierarchy_options_bitexact(kw):
+    rp, ci, v = M.diffusion(np.exp(1.5 * M.grf(18, 3, seed=8)))
+    H, O = pair(rp, ci, v, max_coarse=10, **kw)
+    assert_hierarchy_bitexact(H, O)
+
+
+def _solve_parity(rp, ci, v, b, tol, **kw):
+    import oracle
+    H, O = pair(rp, ci, v, **kw)
+    # single V-cycle application
+    z = host(H.apply_vcycle(dev(b)))
+    zo = O.vcycle(b)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    # converged solve: counts within one, both meet the tolerance (true FP64 residual)
+    x, info = H.solve(dev(b), tol)
+    xo, io = O.pcg(b, tol=tol)
+    assert info["status"] == 0 and io["status"] == 0
+    assert abs(info["iters"] - io["iters"]) <= 1, (info["iters"], io["iters"])
+    xg = host(x)
+    assert oracle.rel_residual(rp, ci, v, b, xg) <= tol
+    assert info["rel_resid"] <= tol
+    # iterate parity: same number of iterations, tol = 0
+    k = io["iters"]
+    Hk, _ = pair(rp, ci, v, maxiter=k, **kw)
+    xk, ik = Hk.solve(dev(b), 0.0)
+    xok, iok = O.pcg(b, tol=0.0, maxiter=k)
+    assert ik["iters"] == k and iok["iters"] == k
+    err = np.linalg.norm(host(xk) - xok) / np.linalg.norm(xok)
+    assert err <= 1e-9, err
+    return H, O
+
+
+def test_solve_c1_poisson_32():
+    rp, ci, v = M.poisson(32, 2)
+    _solve_parity(rp, ci, v, M.rhs_normal(1024, 0), 1e-10)
+
+
+@pytest.mark.parametrize("case", ["diffusion2d_64", "poisson3d_24", "diffusion3d_21", "random_spd_700",
+                                  "tridiag_3000"])
+def test_solve_parity(case):
+    rp, ci, v = CASES[case]()
+    _solve_parity(rp, ci, v, M.rhs_normal(len(rp) - 1, 7), 1e-10)
+
+
+def test_solve_parity_deep_and_options():
+    rp, ci, v = M.diffusion(np.exp(M.grf(20, 3, seed=6)))
+    b = M.rhs_normal(len(rp) - 1, 9)
+    for kw in (dict(max_coarse=10), dict(smoother="l1", max_coarse=10), dict(nu_pre=2, nu_post=2)):
+        _solve_parity(rp, ci, v, b, 1e-10, **kw)
+
+
+def test_single_level_direct():
+    rp, ci, v = M.poisson(12, 2)      # 144 <= 256: one level, the coarse solve is the preconditioner
+    H, O = pair(rp, ci, v)
+    assert H.stats()["num_levels"] == 1
+    b = M.rhs_normal(144, 1)
+    x, info = H.solve(dev(b), 1e-12)
+    A = np.zeros((144, 144))
+    for i in range(144):
+        A[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    xr = np.linalg.solve(A, b)
+    assert np.linalg.norm(host(x) - xr) <= 1e-11 * np.linalg.norm(xr)
+    assert info["iters"] <= 2
+
+
+def test_edge_cases():
+    from paper_2606_09001_amd._lib import AmgError, AMG_ERR_BREAKDOWN
+    rp, ci, v = M.poisson(30, 2)
+    H, O = pair(rp, ci, v, max_coarse=20)
+    n = len(rp) - 1
+    x, info = H.solve(dev(np.zeros(n)), 1e-8)
+    assert info["iters"] == 0 and info["converged"] and not host(x).any()
+    H1, _ = pair(rp, ci, v, max_coarse=20, maxiter=1)
+    x, info = H1.solve(dev(M.rhs_normal(n, 2)), 1e-10)
+    assert info["iters"] == 1 and not info["converged"]
+    bn = M.rhs_normal(n, 2)
+    bn[5] = np.nan
+    with pytest.raises(AmgError) as e:
+        H.solve(dev(bn), 1e-8)
+    assert e.value.status == AMG_ERR_BREAKDOWN
+
+
+def test_invalid_csr_rejected():
+    from paper_2606_09001_amd._lib import AmgError, AMG_ERR_INVALID_ARG, AMG_ERR_ZERO_DIAG
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    rp, ci, v = M.poisson(6, 2)
+    bad = ci.copy()
+    bad[0], bad[1] = bad[1], bad[0]
+    with pytest.raises(AmgError) as e:
+        AmgHierarchy(dev(rp), dev(bad), dev(v))
+    assert e.value.status == AMG_ERR_INVALID_ARG
+    bad = ci.copy()
+    bad[3] = 999
+    with pytest.raises(AmgError) as e:
+        AmgHierarchy(dev(rp), dev(bad), dev(v))
+    assert e.value.status == AMG_ERR_INVALID_ARG
+    v0 = v.copy()
+    v0[rp[4] + list(ci[rp[4]:rp[5]]).index(4)] = 0.0
+    with pytest.raises(AmgError) as e:
+        AmgHierarchy(dev(rp), dev(ci), dev(v0))
+    assert e.value.status == AMG_ERR_ZERO_DIAG
+
+
+def test_determinism_bitwise():
+    rp, ci, v = M.diffusion(np.exp(M.grf(40, 2, seed=2)))
+    H, _ = pair(rp, ci, v)
+    b = dev(M.rhs_normal(len(rp) - 1, 3))
+    x1, i1 = H.solve(b, 1e-10)
+    x2, i2 = H.solve(b, 1e-10)
+    assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
+
+
+def test_pattern_grad_bitexact_and_adjoint():
+    import oracle
+    rp, ci, v = M.diffusion(np.exp(M.grf(48, 2, seed=12)))
+    n = len(rp) - 1
+    H, O = pair(rp, ci, v)
+    rng = np.random.default_rng(0)
+    lam, x = rng.standard_normal(n), rng.standard_normal(n)
+    g = host(H.pattern_grad(dev(lam), dev(x)))
+    assert np.array_equal(g, oracle.pattern_grad(rp, ci, lam, x))
+    gx = rng.standard_normal(n)
+    lg, info = H.solve_adjoint(dev(gx), 1e-10)
+    lo, io = O.solve_adjoint(gx, tol=1e-10)
+    assert np.linalg.norm(host(lg) - lo) <= 1e-7 * np.linalg.norm(lo)
+
+
+def test_refresh_bitexact_and_cache_events():
+    import oracle
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    N = 40
+    rp, ci, v1 = M.diffusion(np.exp(M.grf(N, 2, seed=1)))
+    _, _, v2 = M.diffusion(np.exp(M.grf(N, 2, seed=2)))
+    H = AmgHierarchy(dev(rp), dev(ci), dev(v1), max_coarse=16)
+    b = dev(M.rhs_normal(N * N, 1))
+    _, info = H.solve(b, 1e-8)
+    assert info["cache_event"] in (0, 1)
+    H2 = AmgHierarchy(dev(rp), dev(ci), dev(v1), max_coarse=16)   # same values: hit
+    _, info = H2.solve(b, 1e-8)
+    assert info["cache_event"] == 1
+    H3 = AmgHierarchy(dev(rp), dev(ci), dev(v2), max_coarse=16)   # new values: in-place refresh
+    _, info = H3.solve(b, 1e-8)
+    assert info["cache_event"] == 2
+    O2 = oracle.OracleHierarchy(rp, ci, v2, max_coarse=16)
+    assert_hierarchy_bitexact(H3, O2)
+    # explicit update_values on a handle
+    H3.update_values(dev(v1))
+    O1 = oracle.OracleHierarchy(rp, ci, v1, max_coarse=16)
+    assert_hierarchy_bitexact(H3, O1)
+
+
+def test_mixed_precision_residual():
+    import oracle
+    rp, ci, v = M.diffusion(np.exp(M.grf(24, 3, seed=2)))
+    b = M.rhs_normal(len(rp) - 1, 100)
+    H, O = pair(rp, ci, v, vcycle_prec="fp32")
+    x, info = H.solve(dev(b), 1e-8)
+    assert info["status"] == 0
+    rr = oracle.rel_residual(rp, ci, v, b, host(x))
+    assert rr <= 1e-8, rr
+    xo, io = O.pcg(b, tol=1e-12)
+    err = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    print(f"[mixed] iters={info['iters']} (fp64 oracle {O.pcg(b, tol=1e-8)[1]['iters']}) "
+          f"rel_resid={rr:.3e} err_vs_fp64={err:.3e}", flush=True)
+    # bf16 off: FP32 transfers
+    H32, _ = pair(rp, ci, v, vcycle_prec="fp32", transfer_bf16=0)
+    x32, info32 = H32.solve(dev(b), 1e-8)
+    assert oracle.rel_residual(rp, ci, v, b, host(x32)) <= 1e-8
