@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the AMG-PCG solve phase on one MI355X.
+
+Workload: 3D Poisson, 7-point finite differences on a 128^3 interior grid
+(2,097,152 unknowns, 14,581,760 nonzeros, CSR FP64 with int32 indices),
+b ~ N(0,1) from seed 1, smoothed-aggregation V(1,1) damped-Jacobi
+(omega = 2/3) preconditioned CG from x0 = 0 to a relative residual of 1e-8.
+A step is one complete solve (setup cached, input resident in HBM).
+
+Prints ONE JSON line on stdout: FP64 solves/s as `value`, the FP32-cycle
+(mixed) solves/s and its speedup, the roofline of the dominant kernel timed
+with HIP events around its launches inside the timed solves, and the oracle
+timed on the host as the CPU baseline.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+METRIC = "AMG-PCG solves/s to 1e-8 rel resid + HBM GB/s; mixed vs FP64 speedup"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(kernel_tag: str, src_hash: str):
+    """HBM bytes per launch from committed PMC summaries, if they were taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != src_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("solve.hip", "amg_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2606_09001_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=128, help="interior grid points per axis (default 128)")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=512,
+                    help="size of a plain device copy run once (PMC calibration of FETCH/WRITE_SIZE)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solve path is single-GPU "
+              f"by design and multi-GPU runs are not part of this benchmark.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2606_09001_amd import matrices as M
+    from paper_2606_09001_amd.solver import AmgHierarchy
+
+    assert torch.cuda.is_available(), "no HIP device visible"
+    dev = torch.device("cuda:0")
+    N = args.grid
+    t0 = time.time()
+    rp, ci, v = M.poisson(N, 3)
+    n = len(rp) - 1
+    b = M.rhs_normal(n, seed=1)
+    log(f"generated 3D Poisson {N}^3: n={n} nnz={len(ci)} in {time.time() - t0:.1f}s")
+    d_rp = torch.from_numpy(rp).to(dev)
+    d_ci = torch.from_numpy(ci).to(dev)
+    d_v = torch.from_numpy(v).to(dev)
+    d_b = torch.from_numpy(b).to(dev)
+    x = torch.empty_like(d_b)
+
+    # calibration copy for PMC byte counters (known size: read + write)
+    if args.calib_copy_mib > 0:
+        src = torch.empty(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    res = {}
+    hier = {}
+    for prec in ("fp64", "fp32"):
+        t0 = time.time()
+        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec)
+        torch.cuda.synchronize()
+        setup_s = time.time() - t0
+        hier[prec] = H
+        _, info = H.solve(d_b, args.tol, out=x)
+        log(f"{prec}: setup {setup_s * 1e3:.1f} ms, first solve iters={info['iters']} "
+            f"rel_resid={info['rel_resid']:.3e} status={info['status']}")
+        for _ in range(args.warmup):
+            H.solve(d_b, args.tol, out=x)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev0.record()
+        iters = []
+        rr = []
+        for _ in range(args.steps):
+            _, info = H.solve(d_b, args.tol, out=x)
+            iters.append(info["iters"])
+            rr.append(info["rel_resid"])
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = ev0.elapsed_time(ev1) / args.steps
+        per_iter_bytes = H.kernel_bytes(None, 0, flexible=(prec == "fp32"))
+        it = float(np.mean(iters))
+        res[prec] = dict(ms_per_step=ms, wall_ms_per_step=wall * 1e3 / args.steps, iters=it,
+                         rel_resid=max(rr), solves_per_s=1e3 / ms, setup_ms=setup_s * 1e3,
+                         solve_gbs=it * per_iter_bytes / (ms * 1e-3) / 1e9, bytes_per_iter=per_iter_bytes)
+        log(f"{prec}: {ms:.3f} ms/solve ({1e3 / ms:.1f} solves/s), iters {it}, "
+            f"{res[prec]['solve_gbs']:.0f} GB/s algorithmic over the solve")
+        # value refresh (same pattern, new values: full numeric resetup)
+        t0 = time.time()
+        H.update_values(d_v)
+        torch.cuda.synchronize()
+        res[prec]["refresh_ms"] = (time.time() - t0) * 1e3
+
+    # per-kernel durations: HIP events around every launch inside timed solves
+    H = hier["fp64"]
+    st = H.stats()
+    kernels = {}
+    for name, lvl in (("spmv_dot", 0), ("pre", 0), ("post", 0), ("restrict", 0), ("prolong", 0),
+                      ("cg_update", 0), ("xpay", 0), ("pre", 1), ("post", 1)):
+        H.instrument(name, lvl)
+        for _ in range(max(2, args.steps // 2)):
+            H.solve(d_b, args.tol, out=x)
+        r = H.instrument_read()
+        H.instrument(None)
+        nbytes = H.kernel_bytes(name, lvl, flexible=False)
+        if r["launches"] == 0:
+            continue
+        # launches queued past convergence return at once; time the working ones
+        kernels[f"{name}_L{lvl}"] = dict(avg_us=r["avg_ms"] * 1e3, min_us=r["min_ms"] * 1e3,
+                                         launches=r["launches"], bytes_per_launch=nbytes,
+                                         gbs_avg=nbytes / (r["avg_ms"] * 1e-3) / 1e9,
+                                         gbs_best=nbytes / (r["min_ms"] * 1e-3) / 1e9)
+    for k, d in kernels.items():
+        log(f"kernel {k}: avg {d['avg_us']:.1f} us, min {d['min_us']:.1f} us, "
+            f"{d['bytes_per_launch'] / 1e6:.1f} MB -> {d['gbs_avg']:.0f} GB/s avg, {d['gbs_best']:.0f} best")
+    dom_name = max(("spmv_dot_L0", "pre_L0", "post_L0"), key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
+    dom = kernels[dom_name]
+    src_hash = kernel_source_hash()
+    traffic = traffic_from_profiles(f"poisson3d_{N}_{dom_name}", src_hash)
+    roofline = {"bound": "hbm", "achieved": round(dom["gbs_avg"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom["gbs_avg"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom_name,
+                "bytes_per_launch": dom["bytes_per_launch"], "avg_us": round(dom["avg_us"], 2),
+                "launches_timed": dom["launches"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.time()
+        O = oracle.OracleHierarchy(rp, ci, v)
+        osetup = time.time() - t0
+        t0 = time.time()
+        xo, io = O.pcg(b, tol=args.tol)
+        osolve = time.time() - t0
+        err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+        cpu = {"value": round(1.0 / osolve, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full FP64 AMG-PCG solve of the {N}^3 Poisson system to {args.tol:g} "
+                         f"({io['iters']} iterations, {osolve:.2f} s; setup {osetup:.2f} s not included), "
+                         f"single-threaded C++ oracle on the host",
+               "oracle_iters": io["iters"], "gpu_vs_oracle_rel_err": err}
+        log(f"oracle: setup {osetup:.2f}s solve {osolve:.2f}s iters {io['iters']}; |x_gpu-x_oracle|/|x|={err:.2e}")
+
+    f64, f32 = res["fp64"], res["fp32"]
+    out = {
+        "metric": METRIC,
+        "value": round(f64["solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f64["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D Poisson 7-point FD {N}^3 ({n} unknowns, {len(ci)} nnz, CSR FP64 int32), "
+                               f"b ~ N(0,1) seed 1, SA-AMG V(1,1) Jacobi 2/3 + PCG to {args.tol:g}",
+                   "global_batch": 1, "parallelism": "single-gpu"},
+        "iters": f64["iters"],
+        "rel_resid": f64["rel_resid"],
+        "solve_hbm_gbs": round(f64["solve_gbs"], 1),
+        "setup_ms": round(f64["setup_ms"], 1),
+        "refresh_ms": round(f64["refresh_ms"], 1),
+        "mixed": {"dtype": "f64 CG + f32 cycle + bf16 P/R", "solves_per_s": round(f32["solves_per_s"], 3),
+                  "ms_per_step": round(f32["ms_per_step"], 4), "iters": f32["iters"],
+                  "rel_resid": f32["rel_resid"], "solve_hbm_gbs": round(f32["solve_gbs"], 1),
+                  "speedup_vs_fp64": round(f64["ms_per_step"] / f32["ms_per_step"], 4),
+                  "setup_ms": round(f32["setup_ms"], 1)},
+        "levels": {"n": st["n"], "nnz": st["nnz"], "operator_complexity": round(st["operator_complexity"], 4)},
+        "kernels": {k: {kk: (round(vv, 2) if isinstance(vv, float) else vv) for kk, vv in d.items()}
+                    for k, d in kernels.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,6 +179,34 @@ amg_status amg_field_info(amg_handle h, int level, int field, int64_t* count, in
 /* Device-to-device copy of a level field into d_dst (dst_bytes capacity). */
 amg_status amg_export_field(amg_handle h, int level, int field, void* d_dst, size_t dst_bytes, hipStream_t stream);
 
+/* ---- measurement (diagnostics; no effect on results) ----
+ * Kernel ids for amg_instrument / amg_kernel_bytes. */
+enum {
+  AMG_KERNEL_SPMV_DOT = 0,   /* q = A p fused with <p,q> (level 0) */
+  AMG_KERNEL_PRE = 1,        /* pre-smoothing from zero fused with the residual */
+  AMG_KERNEL_POST = 2,       /* post-smoothing sweep (level 0: writes z, reduces <r,z>) */
+  AMG_KERNEL_RESTRICT = 3,   /* b_{l+1} = R_l r_l */
+  AMG_KERNEL_PROLONG = 4,    /* x_l += P_l x_{l+1} */
+  AMG_KERNEL_CG_UPDATE = 5,  /* x += alpha p, r -= alpha q, <r,r> */
+  AMG_KERNEL_XPAY = 6,       /* p = z + beta p */
+  AMG_KERNEL_COARSE = 7      /* dense coarsest solve */
+};
+
+/* Time every launch of one kernel at one level (level -1: all levels)
+ * inside subsequent solves with HIP event pairs on the solve stream
+ * (kernel -1 switches it off).  Resets the record. */
+amg_status amg_instrument(amg_handle h, int kernel, int level);
+
+/* Synchronises on the recorded events; returns the number of timed launches
+ * and their total, minimum and maximum durations in ms. */
+amg_status amg_instrument_read(amg_handle h, int* launches, double* total_ms, double* min_ms, double* max_ms);
+
+/* Algorithmic bytes of one launch of `kernel` at `level` (every matrix
+ * array streamed once, every vector operand read once, every output written
+ * once); kernel -1: one whole PCG iteration.  flexible: 1 if the solve uses
+ * the flexible beta (adds the read of q to the level-0 post-smoother). */
+amg_status amg_kernel_bytes(amg_handle h, int kernel, int level, int flexible, double* bytes);
+
 /* Releases the caller's reference; the hierarchy is freed when neither a
  * caller nor the cache holds it. */
 amg_status amg_destroy(amg_handle h);

@@ -36,8 +36,11 @@ FIELDS = {
 EXPORTS = [
     "amg_params_default", "amg_setup", "amg_update_values", "amg_solve", "amg_solve_adjoint", "amg_pattern_grad",
     "amg_apply_vcycle", "amg_hierarchy_stats", "amg_field_info", "amg_export_field", "amg_destroy", "amg_finalize",
-    "amg_cache_size", "amg_set_cache_capacity", "amg_status_string",
+    "amg_cache_size", "amg_set_cache_capacity", "amg_status_string", "amg_instrument", "amg_instrument_read",
+    "amg_kernel_bytes",
 ]
+
+KERNELS = {"spmv_dot": 0, "pre": 1, "post": 2, "restrict": 3, "prolong": 4, "cg_update": 5, "xpay": 6, "coarse": 7}
 
 
 class amg_params(C.Structure):
@@ -108,6 +111,9 @@ def load():
     L.amg_cache_size.argtypes = []
     L.amg_cache_size.restype = C.c_int
     L.amg_set_cache_capacity.argtypes = [C.c_int]
+    L.amg_instrument.argtypes = [vp, C.c_int, C.c_int]
+    L.amg_instrument_read.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
+    L.amg_kernel_bytes.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(dbl)]
     L.amg_status_string.argtypes = [C.c_int]
     L.amg_status_string.restype = C.c_char_p
     for name in EXPORTS:

@@ -59,6 +59,18 @@ struct DBuf {
 
 // ------------------------------------------------------------- hierarchy
 
+// Launch shape of a CSR sweep over one matrix.  stream: a workgroup stages
+// rows_per_block rows (row pointers and products in LDS) and sums each row
+// with `g` lanes; vec (fallback for very long rows): `g` lanes per row read
+// the row directly.
+struct Shape {
+  int stream = 1;
+  int g = 1;
+  int rows_per_block = 256;
+  int grid = 1;
+  int max_block_nnz = 0;
+};
+
 struct Level {
   int n = 0;
   int64_t nnz = 0;
@@ -90,8 +102,8 @@ struct Level {
   // cycle work vectors (FP64 and FP32)
   DBuf<double> x64, b64, r64, xs64, rs64;
   DBuf<float> x32, b32, r32, xs32, rs32;
-  // kernel shapes
-  int gA = 8, gP = 4, gR = 8;
+  // kernel shapes (see choose_shapes)
+  Shape shA, shP, shR;
 };
 
 struct Coarse {
@@ -118,8 +130,22 @@ struct Ctl {
   unsigned int ticket[8];
 };
 
+// Kernels that can be timed inside real solves (event pairs around every
+// launch of one kernel at one level).
+enum KernelId {
+  KID_SPMV_DOT = 0, KID_PRE = 1, KID_POST = 2, KID_RESTRICT = 3, KID_PROLONG = 4,
+  KID_CG_UPDATE = 5, KID_XPAY = 6, KID_COARSE = 7, KID_COUNT = 8
+};
+
+struct Instr {
+  int kernel = -1, level = -1;
+  std::vector<hipEvent_t> ev;  // begin/end pairs
+  int used = 0;
+};
+
 struct Hierarchy {
   amg_params prm{};
+  Instr inst;
   int n = 0;
   int64_t nnz = 0;
   std::vector<Level> lv;
@@ -166,11 +192,18 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
 void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s);
 void pattern_grad(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, hipStream_t s);
 void choose_shapes(Hierarchy& H);
+double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible);
+double iteration_bytes(const Hierarchy& H, int flexible);
+void set_instrument(Hierarchy& H, int kid, int level);
+void read_instrument(Hierarchy& H, int* launches, double* total_ms, double* min_ms, double* max_ms);
 
 // ------------------------------------------------------- device helpers
 
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
-constexpr int kMaxGrid = 2048;     // blocks of the reducing kernels (= partial sums)
+constexpr int kMaxGrid = 2048;     // blocks of grid-stride kernels
+constexpr int kStreamCap = 2048;   // nonzeros a stream workgroup stages in LDS
+constexpr int kVecPer = 4;         // vector elements per thread in BLAS1 kernels
+constexpr int kFinBlock = 1024;    // threads of the single-workgroup finalize kernels
 
 __host__ __device__ inline int pow2_ceil(int x) {
   int g = 1;

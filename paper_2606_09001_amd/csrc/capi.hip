@@ -28,6 +28,7 @@ namespace amg {
 Hierarchy::~Hierarchy() {
   if (h_ctl) (void)hipHostFree(h_ctl);
   if (h_flags) (void)hipHostFree(h_flags);
+  for (hipEvent_t e : inst.ev) (void)hipEventDestroy(e);
 }
 
 namespace {
@@ -267,9 +268,9 @@ amg_status amg_hierarchy_stats(amg_handle h, amg_hier_stats* out) {
     out->rho[l] = L.rho;
     out->omega_p[l] = L.omegaP;
     out->mis_rounds[l] = L.mis_rounds;
-    out->group_a[l] = L.gA;
-    out->group_p[l] = L.gP;
-    out->group_r[l] = L.gR;
+    out->group_a[l] = L.shA.g;
+    out->group_p[l] = L.shP.g;
+    out->group_r[l] = L.shR.g;
     tot += (double)L.nnz;
   }
   out->operator_complexity = tot / (double)H.lv[0].nnz;
@@ -363,6 +364,34 @@ amg_status amg_set_cache_capacity(int capacity) {
     evict_to(capacity);
     return AMG_OK;
   });
+}
+
+amg_status amg_instrument(amg_handle h, int kernel, int level) {
+  return guarded([&]() -> amg_status {
+    if (!h || kernel < -1 || kernel >= KID_COUNT) return AMG_ERR_INVALID_ARG;
+    set_instrument(*h->H, kernel, level);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_instrument_read(amg_handle h, int* launches, double* total_ms, double* min_ms, double* max_ms) {
+  return guarded([&]() -> amg_status {
+    if (!h || !launches || !total_ms || !min_ms || !max_ms) return AMG_ERR_INVALID_ARG;
+    read_instrument(*h->H, launches, total_ms, min_ms, max_ms);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_kernel_bytes(amg_handle h, int kernel, int level, int flexible, double* bytes) {
+  if (!h || !bytes) return AMG_ERR_INVALID_ARG;
+  const Hierarchy& H = *h->H;
+  if (kernel == -1) {
+    *bytes = iteration_bytes(H, flexible);
+    return AMG_OK;
+  }
+  if (kernel < 0 || kernel >= KID_COUNT || level < 0 || level >= (int)H.lv.size()) return AMG_ERR_INVALID_ARG;
+  *bytes = kernel_bytes(H, kernel, level, flexible);
+  return AMG_OK;
 }
 
 const char* amg_status_string(amg_status s) {

@@ -1,27 +1,32 @@
 // Solve phase: preconditioned CG with one smoothed-aggregation V-cycle per
-// iteration, all on the GPU.  Every kernel here streams CSR data (HBM-bound):
-//   - a group of G lanes per row (G = 1..64, G = 64 is a wavefront per row),
-//     chosen per matrix from its row length; consecutive rows of a block are
-//     consecutive in memory, so column/value streams are coalesced;
-//   - rows are dealt to workgroups in contiguous chunks, and workgroups are
-//     renumbered so that each XCD (workgroups are dispatched round-robin over
-//     the 8 XCDs) works on one contiguous range, which keeps neighbour
-//     gathers in that XCD's L2;
-//   - dot products are fused into the producing kernel and reduced
-//     deterministically (fixed tree + last-workgroup fold, no float atomics);
-//   - CG scalars stay on the device; the host only reads a done flag every
-//     few iterations.
+// iteration, all on the GPU.  Every sweep over a CSR matrix is HBM-bound and
+// uses one of two kernel templates around a small operator (per-entry
+// product, per-row epilogue):
+//   - k_stream (rows of moderate length): a workgroup stages the row
+//     pointers of a block of rows in LDS, loads all of the block's nonzeros
+//     at once (kStreamCap/kBlock independent loads per thread, coalesced
+//     column/value streams), stores the products in LDS and sums each row
+//     there; with one lane per row the sum is the sequential fold in stored
+//     order;
+//   - k_vec (fallback for rows too long to stage): a group of G lanes per
+//     row (G = 64 is a wavefront per row).
+// Workgroups are renumbered so that each XCD (round-robin dispatch over the
+// 8 XCDs) owns one contiguous range of rows, which keeps neighbour gathers
+// in that XCD's L2.  Dot products are fused into the producing sweep as one
+// partial per workgroup (plain stores); a single-workgroup finalize kernel
+// folds the partials in a fixed order and forms the CG scalars on the
+// device, so there are no float atomics and no device-wide fences.
 // Method: PCG from x0 = 0 with recursive-residual stopping, true-residual
 // verification and restart; damped-Jacobi/L1 V(nu_pre, nu_post) cycle with
-// R = P^T and an exact coarsest solve (the oracle states the same algorithm
-// step by step).  The FP32 cycle keeps CG vectors, dot products and updates
-// in FP64 and runs the cycle on FP32 copies (bf16-stored P and R optional);
-// the flexible (Polak-Ribiere) beta keeps CG consistent with that inexact
-// preconditioner.
+// R = P^T and an exact coarsest solve.  The FP32 cycle keeps CG vectors, dot
+// products and updates in FP64 and runs the cycle on FP32 copies (bf16-stored
+// P and R optional); the flexible (Polak-Ribiere) beta keeps CG consistent
+// with that inexact preconditioner.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "amg_internal.hpp"
 
@@ -31,199 +36,244 @@ namespace {
 // ------------------------------------------------------------ geometry
 
 // Workgroup index remapped so that XCD k (round-robin dispatch) owns the
-// contiguous logical range [k*G/8, (k+1)*G/8).
+// contiguous logical range [k*G/8, (k+1)*G/8) when G is a multiple of 8.
 __device__ inline int logical_block() {
   const int g = gridDim.x;
   if ((g & 7) == 0) return (blockIdx.x & 7) * (g >> 3) + (blockIdx.x >> 3);
   return blockIdx.x;
 }
 
-// Contiguous chunk range [c0, c1) of this workgroup; a chunk is kBlock/G rows.
-template <int G>
-__device__ inline void chunk_range(int n, int& c0, int& c1) {
-  constexpr int rpp = kBlock / G;
-  const int64_t chunks = ((int64_t)n + rpp - 1) / rpp;
-  const int lb = logical_block();
-  c0 = (int)(chunks * lb / gridDim.x);
-  c1 = (int)(chunks * (lb + 1) / gridDim.x);
-}
-
-inline int stream_grid(int64_t n, int G) {
-  const int64_t rpp = kBlock / G;
-  int64_t chunks = (n + rpp - 1) / rpp;
-  int64_t g = std::min<int64_t>(chunks, kMaxGrid);
-  if (g >= 64) g = g / 8 * 8;
+// Grid of `blocks` workgroups rounded up to a multiple of 8 (surplus
+// workgroups find no rows and exit), so the XCD remap applies.
+inline int round8(int64_t g) {
+  if (g >= 64) g = (g + 7) / 8 * 8;
   return (int)std::max<int64_t>(g, 1);
 }
 
-template <class T>
-__device__ inline T ld(const T* p) {
-  return *p;
-}
+// ----------------------------------------------------------- operators
+// An operator supplies
+//   PT prod(k, j)              product for stored entry k (column j)
+//   void epi(row, s, d[])      consumes the row sum s; d[] collects dot partials
+//   static constexpr int NRED  number of dot products reduced
 
-// Sum over the row of A: sum_j a_ij * f(j), lanes of a group stride the row.
-#define ROW_SUM(G, rp, row, lane, body)                                          \
-  do {                                                                           \
-    for (int k_ = (rp)[row] + (lane); k_ < (rp)[(row) + 1]; k_ += (G)) { body; } \
-  } while (0)
+// q = A p, <p, q>
+struct OpSpmvDot {
+  using PT = double;
+  static constexpr int NRED = 1;
+  const double* v;
+  const double* p;
+  double* q;
+  __device__ PT prod(int k, int j) const { return v[k] * p[j]; }
+  __device__ void epi(int row, PT s, double* d) const {
+    q[row] = s;
+    d[0] += p[row] * s;
+  }
+};
 
-// --------------------------------------------------------- V-cycle kernels
+// r = b - A x, ||r||^2
+struct OpTrueResid {
+  using PT = double;
+  static constexpr int NRED = 1;
+  const double* v;
+  const double* x;
+  const double* b;
+  double* r;
+  __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
+  __device__ void epi(int row, PT s, double* d) const {
+    const double ri = b[row] - s;
+    r[row] = ri;
+    d[0] += ri * ri;
+  }
+};
 
 // Pre-smoothing from zero fused with the residual:
 //   x_i = sw_i b_i ;  r_i = b_i - sum_j a_ij (sw_j b_j).
-template <int G, class VT, class BT, class T>
-__global__ void __launch_bounds__(kBlock) k_pre(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                const VT* __restrict__ v, const T* __restrict__ sw,
-                                                const BT* __restrict__ b, T* __restrict__ x, T* __restrict__ r,
-                                                const Ctl* __restrict__ ctl) {
-  if (ctl && ctl->done) return;
-  int c0, c1;
-  chunk_range<G>(n, c0, c1);
-  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  for (int c = c0; c < c1; ++c) {
-    const int row = c * (kBlock / G) + grp;
-    T s = 0;
-    if (row < n) {
-      ROW_SUM(G, rp, row, lane, {
-        const int j = ci[k_];
-        s += (T)v[k_] * (sw[j] * (T)b[j]);
-      });
-    }
-    s = group_sum<G>(s);
-    if (row < n && group_leader<G>()) {
-      const T bi = (T)b[row];
-      x[row] = sw[row] * bi;
-      r[row] = bi - s;
-    }
+template <class T, class BT>
+struct OpPre {
+  using PT = T;
+  static constexpr int NRED = 0;
+  const T* v;
+  const T* sw;
+  const BT* b;
+  T* x;
+  T* r;
+  __device__ PT prod(int k, int j) const { return v[k] * (sw[j] * (T)b[j]); }
+  __device__ void epi(int row, PT s, double*) const {
+    const T bi = (T)b[row];
+    x[row] = sw[row] * bi;
+    r[row] = bi - s;
   }
-}
+};
 
-// One further Jacobi sweep in residual form, fused with the new residual:
+// Further Jacobi sweep in residual form, fused with the new residual:
 //   x'_i = x_i + sw_i r_i ;  r'_i = b_i - sum_j a_ij (x_j + sw_j r_j).
-template <int G, class VT, class BT, class T>
-__global__ void __launch_bounds__(kBlock) k_sweep(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                  const VT* __restrict__ v, const T* __restrict__ sw,
-                                                  const BT* __restrict__ b, const T* __restrict__ x,
-                                                  const T* __restrict__ r, T* __restrict__ x2, T* __restrict__ r2,
-                                                  const Ctl* __restrict__ ctl) {
-  if (ctl && ctl->done) return;
-  int c0, c1;
-  chunk_range<G>(n, c0, c1);
-  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  for (int c = c0; c < c1; ++c) {
-    const int row = c * (kBlock / G) + grp;
-    T s = 0;
-    if (row < n) {
-      ROW_SUM(G, rp, row, lane, {
-        const int j = ci[k_];
-        s += (T)v[k_] * (x[j] + sw[j] * r[j]);
-      });
-    }
-    s = group_sum<G>(s);
-    if (row < n && group_leader<G>()) {
-      x2[row] = x[row] + sw[row] * r[row];
-      r2[row] = (T)b[row] - s;
+template <class T, class BT>
+struct OpSweep {
+  using PT = T;
+  static constexpr int NRED = 0;
+  const T* v;
+  const T* sw;
+  const BT* b;
+  const T* x;
+  const T* r;
+  T* x2;
+  T* r2;
+  __device__ PT prod(int k, int j) const { return v[k] * (x[j] + sw[j] * r[j]); }
+  __device__ void epi(int row, PT s, double*) const {
+    x2[row] = x[row] + sw[row] * r[row];
+    r2[row] = (T)b[row] - s;
+  }
+};
+
+// Post-smoothing out_i = x_i + sw_i (b_i - sum_j a_ij x_j); RED >= 1 also
+// <b, out>, RED == 2 also <out, q> (level 0 of CG: b = r, out = z).
+template <class T, class BT, class OT, int RED>
+struct OpPost {
+  using PT = T;
+  static constexpr int NRED = RED;
+  const T* v;
+  const T* sw;
+  const BT* b;
+  const T* x;
+  OT* out;
+  const double* q;
+  __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
+  __device__ void epi(int row, PT s, double* d) const {
+    const T bi = (T)b[row];
+    const T o = x[row] + sw[row] * (bi - s);
+    const OT oo = (OT)o;
+    out[row] = oo;
+    if constexpr (RED >= 1) d[0] += (double)b[row] * (double)oo;
+    if constexpr (RED >= 2) d[1] += (double)oo * q[row];
+  }
+};
+
+// y = R x (restriction); R values of type RT (double, float or bf16 bits).
+template <class RT, class T>
+struct OpRestrict {
+  using PT = T;
+  static constexpr int NRED = 0;
+  const RT* v;
+  const T* x;
+  T* y;
+  __device__ PT prod(int k, int j) const { return (T)ValCvt<RT>::f(v[k]) * x[j]; }
+  __device__ void epi(int row, PT s, double*) const { y[row] = s; }
+};
+
+// x += P xc (prolongation and coarse-grid correction).
+template <class RT, class T>
+struct OpProlong {
+  using PT = T;
+  static constexpr int NRED = 0;
+  const RT* v;
+  const T* xc;
+  T* x;
+  __device__ PT prod(int k, int j) const { return (T)ValCvt<RT>::f(v[k]) * xc[j]; }
+  __device__ void epi(int row, PT s, double*) const { x[row] = x[row] + s; }
+};
+
+template <int NRED>
+__device__ inline void publish_partials(double (&d)[NRED > 0 ? NRED : 1], double* partials) {
+  if constexpr (NRED > 0) {
+    block_sum<NRED>(d);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int m = 0; m < NRED; ++m) partials[m * gridDim.x + blockIdx.x] = d[m];
     }
   }
 }
 
-// Post-smoothing sweep out_i = x_i + sw_i (b_i - sum_j a_ij x_j).  RED = 1
-// also reduces <b, out>; RED = 2 also <out, q> (level 0 of CG: b = r,
-// out = z).
-template <int G, class VT, class BT, class XT, class OT, int RED>
-__global__ void __launch_bounds__(kBlock) k_post(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                 const VT* __restrict__ v, const XT* __restrict__ sw,
-                                                 const BT* __restrict__ b, const XT* __restrict__ x,
-                                                 OT* __restrict__ out, const double* __restrict__ q,
-                                                 Ctl* __restrict__ ctl, double* __restrict__ partials, int first) {
+// ------------------------------------------------------------ CSR sweeps
+
+template <int G3, class Op>
+__global__ void __launch_bounds__(kBlock) k_stream(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   Op op, const Ctl* __restrict__ ctl,
+                                                   double* __restrict__ partials) {
   if (ctl && ctl->done) return;
-  int c0, c1;
-  chunk_range<G>(n, c0, c1);
-  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  double d0 = 0.0, d1 = 0.0;
-  for (int c = c0; c < c1; ++c) {
-    const int row = c * (kBlock / G) + grp;
-    XT s = 0;
-    if (row < n) {
-      ROW_SUM(G, rp, row, lane, { s += (XT)v[k_] * x[ci[k_]]; });
-    }
-    s = group_sum<G>(s);
-    if (row < n && group_leader<G>()) {
-      const XT bi = (XT)b[row];
-      const XT o = x[row] + sw[row] * (bi - s);
-      out[row] = (OT)o;
-      if constexpr (RED >= 1) d0 += (double)b[row] * (double)(OT)o;
-      if constexpr (RED >= 2) d1 += (double)(OT)o * q[row];
-    }
+  constexpr int RB = kBlock / G3;
+  constexpr int U = kStreamCap / kBlock;
+  using PT = typename Op::PT;
+  __shared__ int s_rp[RB + 1];
+  __shared__ PT s_p[kStreamCap];
+  const int r0 = logical_block() * RB;
+  for (int t = threadIdx.x; t <= RB; t += kBlock) s_rp[t] = rp[min(r0 + t, n)];
+  __syncthreads();
+  const int k0 = s_rp[0];
+  const int nk = s_rp[RB] - k0;
+  int col[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = threadIdx.x + u * kBlock;
+    col[u] = j < nk ? ci[k0 + j] : 0;
   }
-  if constexpr (RED >= 1) {
-    double vals[2] = {d0, d1};
-    if (grid_sum<2>(vals, partials, &ctl->ticket[2]) && threadIdx.x == 0) {
-      const double rzn = vals[0];
-      if (first) {
-        ctl->rz = rzn;
-        ctl->beta = 0.0;
-      } else if (ctl->flexible) {
-        // Polak-Ribiere: beta = <z, r - r_old>/<z_old, r_old> = -<z, q>/<p, q>
-        ctl->beta = -vals[1] / ctl->pq;
-        ctl->rz = rzn;
-      } else {
-        ctl->beta = rzn / ctl->rz;
-        ctl->rz = rzn;
-      }
-      ctl->rzn = rzn;
-      ctl->zq = vals[1];
-      if (!(rzn > 0.0)) {
-        ctl->state = -1;
-        ctl->done = 1;
-      }
-    }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = threadIdx.x + u * kBlock;
+    if (j < nk) s_p[j] = op.prod(k0 + j, col[u]);
   }
+  __syncthreads();
+  const int lr = threadIdx.x / G3, lane = threadIdx.x & (G3 - 1);
+  const int row = r0 + lr;
+  PT s = 0;
+  if (row < n) {
+    const int e = s_rp[lr + 1] - k0;
+    for (int k = s_rp[lr] - k0 + lane; k < e; k += G3) s += s_p[k];
+  }
+  s = group_sum<G3>(s);
+  double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  if (row < n && group_leader<G3>()) op.epi(row, s, d);
+  publish_partials<Op::NRED>(d, partials);
 }
 
-// b_c = R r (restriction), R stored as CSR with n_c rows.
-template <int G, class RT, class XT, class YT>
-__global__ void __launch_bounds__(kBlock) k_restrict(int nc, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                     const RT* __restrict__ v, const XT* __restrict__ x,
-                                                     YT* __restrict__ y, const Ctl* __restrict__ ctl) {
+template <int G, class Op>
+__global__ void __launch_bounds__(kBlock) k_vec(int n, const int* __restrict__ rp, const int* __restrict__ ci, Op op,
+                                                const Ctl* __restrict__ ctl, double* __restrict__ partials) {
   if (ctl && ctl->done) return;
-  int c0, c1;
-  chunk_range<G>(nc, c0, c1);
-  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  using CT = decltype(ValCvt<RT>::f(RT()));
-  for (int c = c0; c < c1; ++c) {
-    const int row = c * (kBlock / G) + grp;
-    CT s = 0;
-    if (row < nc) {
-      ROW_SUM(G, rp, row, lane, { s += ValCvt<RT>::f(v[k_]) * (CT)x[ci[k_]]; });
-    }
+  using PT = typename Op::PT;
+  constexpr int RB = kBlock / G;
+  const int lr = threadIdx.x / G, lane = threadIdx.x & (G - 1);
+  double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  for (int r0 = logical_block() * RB; r0 < n; r0 += gridDim.x * RB) {
+    const int row = r0 + lr;
+    PT s = 0;
+    if (row < n)
+      for (int k = rp[row] + lane; k < rp[row + 1]; k += G) s += op.prod(k, ci[k]);
     s = group_sum<G>(s);
-    if (row < nc && group_leader<G>()) y[row] = (YT)s;
+    if (row < n && group_leader<G>()) op.epi(row, s, d);
   }
+  publish_partials<Op::NRED>(d, partials);
 }
 
-// x += P x_c (prolongation and coarse-grid correction).
-template <int G, class PT, class T>
-__global__ void __launch_bounds__(kBlock) k_prolong(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                    const PT* __restrict__ v, const T* __restrict__ xc,
-                                                    T* __restrict__ x, const Ctl* __restrict__ ctl) {
-  if (ctl && ctl->done) return;
-  int c0, c1;
-  chunk_range<G>(n, c0, c1);
-  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  for (int c = c0; c < c1; ++c) {
-    const int row = c * (kBlock / G) + grp;
-    T s = 0;
-    if (row < n) {
-      ROW_SUM(G, rp, row, lane, { s += (T)ValCvt<PT>::f(v[k_]) * xc[ci[k_]]; });
-    }
-    s = group_sum<G>(s);
-    if (row < n && group_leader<G>()) x[row] = x[row] + s;
+#define AMG_DISPATCH_G(g, ...)                             \
+  switch (g) {                                             \
+    case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int G = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int G = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int G = 32; __VA_ARGS__; } break; \
+    default: { constexpr int G = 64; __VA_ARGS__; } break; \
   }
+
+// One sweep over a CSR matrix with operator `op`; returns the grid size
+// (= number of partials written per reduced value).
+template <class Op>
+int sweep(const Shape& sh, int n, const int* rp, const int* ci, const Op& op, const Ctl* ctl, double* partials,
+          hipStream_t s) {
+  if (sh.stream) {
+    AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_stream<G, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl,
+                                            partials));
+  } else {
+    AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_vec<G, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl,
+                                            partials));
+  }
+  return sh.grid;
 }
 
-// Coarsest solve x = A_L^-1 b with the explicit (symmetric) inverse:
-// thread i reads column i = row i, coalesced across threads.
+// ------------------------------------------------------- dense coarse solve
+
+// x = A_L^-1 b with the explicit (symmetric) inverse: thread i reads
+// column i = row i, coalesced across threads.
 template <class T, class BT, class OT>
 __global__ void __launch_bounds__(kBlock) k_coarse(int n, int m, const T* __restrict__ inv, const BT* __restrict__ b,
                                                    OT* __restrict__ x, const Ctl* __restrict__ ctl) {
@@ -243,144 +293,65 @@ __global__ void __launch_bounds__(kBlock) k_coarse(int n, int m, const T* __rest
   if (i < n) x[i] = (OT)s;
 }
 
-// <r, z> and <z, q> after a single-level (direct) preconditioner.
-__global__ void __launch_bounds__(kBlock) k_dots_rz(int n, const double* __restrict__ r, const double* __restrict__ z,
-                                                    const double* __restrict__ q, Ctl* __restrict__ ctl,
-                                                    double* __restrict__ partials, int first) {
-  if (ctl->done) return;
-  double d0 = 0.0, d1 = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    d0 += r[i] * z[i];
-    d1 += z[i] * q[i];
-  }
-  double vals[2] = {d0, d1};
-  if (grid_sum<2>(vals, partials, &ctl->ticket[2]) && threadIdx.x == 0) {
-    const double rzn = vals[0];
-    if (first) {
-      ctl->rz = rzn;
-      ctl->beta = 0.0;
-    } else if (ctl->flexible) {
-      ctl->beta = -vals[1] / ctl->pq;
-      ctl->rz = rzn;
-    } else {
-      ctl->beta = rzn / ctl->rz;
-      ctl->rz = rzn;
-    }
-    ctl->rzn = rzn;
-    ctl->zq = vals[1];
-    if (!(rzn > 0.0)) {
-      ctl->state = -1;
-      ctl->done = 1;
-    }
-  }
-}
+// ------------------------------------------------------- BLAS1 (FP64)
 
-// ------------------------------------------------------------ CG kernels
+inline int vec_grid(int n) { return round8(((int64_t)n + kBlock * kVecPer - 1) / (kBlock * kVecPer)); }
 
-// r = b, x = 0, <b, b>; the last workgroup initialises the control block.
+// Element range of this workgroup: kBlock*kVecPer consecutive entries.
+__device__ inline int vec_base() { return logical_block() * (kBlock * kVecPer); }
+
+// r = b, x = 0, partial <b, b>.
 __global__ void __launch_bounds__(kBlock) k_cg_init(int n, const double* __restrict__ b, double* __restrict__ r,
-                                                    double* __restrict__ x, Ctl* __restrict__ ctl,
-                                                    double* __restrict__ partials, double tol, int maxiter,
-                                                    int flexible) {
-  double bb = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double bi = b[i];
-    r[i] = bi;
-    x[i] = 0.0;
-    bb += bi * bi;
+                                                    double* __restrict__ x, double* __restrict__ partials) {
+  const int base = vec_base();
+  double bv[kVecPer];
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    bv[u] = i < n ? b[i] : 0.0;
   }
-  double vals[1] = {bb};
-  if (grid_sum<1>(vals, partials, &ctl->ticket[0]) && threadIdx.x == 0) {
-    const double t = vals[0];
-    ctl->bb = t;
-    ctl->thresh = (tol * tol) * t;
-    ctl->iters = 0;
-    ctl->maxiter = maxiter;
-    ctl->flexible = flexible;
-    ctl->state = 0;
-    ctl->done = 0;
-    ctl->trr = 0.0;
-    if (t == 0.0) {
-      ctl->state = 3;  // zero right-hand side: x = 0
-      ctl->done = 1;
-    } else if (!(t == t)) {
-      ctl->state = -1;
-      ctl->done = 1;
-    } else if (maxiter <= 0) {
-      ctl->state = 2;
-      ctl->done = 1;
+  double d[1] = {0.0};
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) {
+      r[i] = bv[u];
+      x[i] = 0.0;
+      d[0] += bv[u] * bv[u];
     }
   }
+  publish_partials<1>(d, partials);
 }
 
-// q = A p fused with <p, q>; the last workgroup forms alpha.
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_spmv_dot(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                     const double* __restrict__ v, const double* __restrict__ p,
-                                                     double* __restrict__ q, Ctl* __restrict__ ctl,
-                                                     double* __restrict__ partials) {
-  if (ctl->done) return;
-  int c0, c1;
-  chunk_range<G>(n, c0, c1);
-  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  double d = 0.0;
-  for (int c = c0; c < c1; ++c) {
-    const int row = c * (kBlock / G) + grp;
-    double s = 0.0;
-    if (row < n) {
-      ROW_SUM(G, rp, row, lane, { s += v[k_] * p[ci[k_]]; });
-    }
-    s = group_sum<G>(s);
-    if (row < n && group_leader<G>()) {
-      q[row] = s;
-      d += p[row] * s;
-    }
-  }
-  double vals[1] = {d};
-  if (grid_sum<1>(vals, partials, &ctl->ticket[0]) && threadIdx.x == 0) {
-    const double pq = vals[0];
-    ctl->pq = pq;
-    if (!(pq > 0.0)) {
-      ctl->state = -1;
-      ctl->done = 1;
-    } else {
-      ctl->alpha = ctl->rz / pq;
-    }
-  }
-}
-
-// x += alpha p ; r -= alpha q ; <r, r>; the last workgroup tests convergence.
+// x += alpha p ; r -= alpha q ; partial <r, r>.
 __global__ void __launch_bounds__(kBlock) k_cg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                       const double* __restrict__ p, const double* __restrict__ q,
-                                                      Ctl* __restrict__ ctl, double* __restrict__ partials) {
+                                                      const Ctl* __restrict__ ctl, double* __restrict__ partials) {
   if (ctl->done) return;
   const double alpha = ctl->alpha;
-  double rr = 0.0;
-  int c0, c1;
-  chunk_range<1>(n, c0, c1);
-  const int i0 = c0 * kBlock, i1 = min(n, c1 * kBlock);
-  for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-    x[i] = x[i] + alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    rr += ri * ri;
+  const int base = vec_base();
+  double xv[kVecPer], rv[kVecPer], pv[kVecPer], qv[kVecPer];
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    const bool ok = i < n;
+    xv[u] = ok ? x[i] : 0.0;
+    rv[u] = ok ? r[i] : 0.0;
+    pv[u] = ok ? p[i] : 0.0;
+    qv[u] = ok ? q[i] : 0.0;
   }
-  double vals[1] = {rr};
-  if (grid_sum<1>(vals, partials, &ctl->ticket[1]) && threadIdx.x == 0) {
-    const double t = vals[0];
-    ctl->rr = t;
-    ctl->iters += 1;
-    if (t <= ctl->thresh) {
-      ctl->state = 1;
-      ctl->done = 1;
-    } else if (!(t == t)) {
-      ctl->state = -1;
-      ctl->done = 1;
-    } else if (ctl->iters >= ctl->maxiter) {
-      ctl->state = 2;
-      ctl->done = 1;
+  double d[1] = {0.0};
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) {
+      x[i] = xv[u] + alpha * pv[u];
+      const double ri = rv[u] - alpha * qv[u];
+      r[i] = ri;
+      d[0] += ri * ri;
     }
   }
+  publish_partials<1>(d, partials);
 }
 
 // p = z + beta p  (p = z on the first iteration of a (re)start).
@@ -388,40 +359,175 @@ __global__ void __launch_bounds__(kBlock) k_xpay(int n, const double* __restrict
                                                  const Ctl* __restrict__ ctl, int first) {
   if (ctl->done) return;
   const double beta = ctl->beta;
-  int c0, c1;
-  chunk_range<1>(n, c0, c1);
-  const int i0 = c0 * kBlock, i1 = min(n, c1 * kBlock);
-  if (first)
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) p[i] = z[i];
-  else
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) p[i] = z[i] + beta * p[i];
+  const int base = vec_base();
+  double zv[kVecPer], pv[kVecPer];
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    const bool ok = i < n;
+    zv[u] = ok ? z[i] : 0.0;
+    pv[u] = (ok && !first) ? p[i] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) p[i] = first ? zv[u] : zv[u] + beta * pv[u];
+  }
 }
 
-// r = b - A x and ||r||^2 (true residual, FP64).
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_true_resid(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       const double* __restrict__ v, const double* __restrict__ b,
-                                                       const double* __restrict__ x, double* __restrict__ r,
-                                                       Ctl* __restrict__ ctl, double* __restrict__ partials) {
-  int c0, c1;
-  chunk_range<G>(n, c0, c1);
-  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  double d = 0.0;
-  for (int c = c0; c < c1; ++c) {
-    const int row = c * (kBlock / G) + grp;
-    double s = 0.0;
-    if (row < n) {
-      ROW_SUM(G, rp, row, lane, { s += v[k_] * x[ci[k_]]; });
-    }
-    s = group_sum<G>(s);
-    if (row < n && group_leader<G>()) {
-      const double ri = b[row] - s;
-      r[row] = ri;
-      d += ri * ri;
+// <r, z> and <z, q> partials after a single-level (direct) preconditioner.
+__global__ void __launch_bounds__(kBlock) k_dots_rz(int n, const double* __restrict__ r, const double* __restrict__ z,
+                                                    const double* __restrict__ q, const Ctl* __restrict__ ctl,
+                                                    double* __restrict__ partials) {
+  if (ctl->done) return;
+  const int base = vec_base();
+  double d[2] = {0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) {
+      d[0] += r[i] * z[i];
+      d[1] += z[i] * q[i];
     }
   }
-  double vals[1] = {d};
-  if (grid_sum<1>(vals, partials, &ctl->ticket[3]) && threadIdx.x == 0) ctl->trr = vals[0];
+  publish_partials<2>(d, partials);
+}
+
+// grad_val[k] = -(lambda[row k] * x[col k]): a group of 8 lanes per row.
+__global__ void __launch_bounds__(kBlock) k_pattern_grad(int n, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci, const double* __restrict__ lam,
+                                                         const double* __restrict__ x, double* __restrict__ g) {
+  constexpr int G = 8;
+  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int lane = threadIdx.x & (G - 1);
+  if (row >= n) return;
+  const double li = lam[row];
+  for (int k = rp[row] + lane; k < rp[row + 1]; k += G) g[k] = -(li * x[ci[k]]);
+}
+
+// ------------------------------------------------------- finalize kernels
+
+// Fixed-order fold of gridDim-sized partial arrays by one workgroup; the
+// totals are valid in thread 0.
+template <int NV>
+__device__ inline void fold_partials(const double* __restrict__ partials, int np, double (&tot)[NV]) {
+  __shared__ double red[NV][kFinBlock / 64];
+  double acc[NV];
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < np; b += kFinBlock) s += partials[m * np + b];
+    acc[m] = wave_sum(s);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) red[m][w] = acc[m];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      double s = red[m][0];
+      for (int k = 1; k < kFinBlock / 64; ++k) s += red[m][k];
+      tot[m] = s;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kFinBlock) k_fin_init(Ctl* ctl, const double* __restrict__ partials, int np,
+                                                        double tol, int maxiter, int flexible) {
+  double t[1];
+  fold_partials<1>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double bb = t[0];
+  ctl->bb = bb;
+  ctl->thresh = (tol * tol) * bb;
+  ctl->iters = 0;
+  ctl->maxiter = maxiter;
+  ctl->flexible = flexible;
+  ctl->state = 0;
+  ctl->done = 0;
+  ctl->trr = 0.0;
+  ctl->rr = bb;
+  if (bb == 0.0) {
+    ctl->state = 3;  // zero right-hand side: x = 0
+    ctl->done = 1;
+  } else if (!(bb == bb)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  } else if (maxiter <= 0) {
+    ctl->state = 2;
+    ctl->done = 1;
+  }
+}
+
+__global__ void __launch_bounds__(kFinBlock) k_fin_alpha(Ctl* ctl, const double* __restrict__ partials, int np) {
+  if (ctl->done) return;
+  double t[1];
+  fold_partials<1>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double pq = t[0];
+  ctl->pq = pq;
+  if (!(pq > 0.0)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  } else {
+    ctl->alpha = ctl->rz / pq;
+  }
+}
+
+__global__ void __launch_bounds__(kFinBlock) k_fin_update(Ctl* ctl, const double* __restrict__ partials, int np) {
+  if (ctl->done) return;
+  double t[1];
+  fold_partials<1>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double rr = t[0];
+  ctl->rr = rr;
+  ctl->iters += 1;
+  if (rr <= ctl->thresh) {
+    ctl->state = 1;
+    ctl->done = 1;
+  } else if (!(rr == rr)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  } else if (ctl->iters >= ctl->maxiter) {
+    ctl->state = 2;
+    ctl->done = 1;
+  }
+}
+
+// beta: standard <r,z>/<r_old,z_old>; flexible (Polak-Ribiere)
+// <z, r - r_old>/<z_old, r_old> = -<z, q>/<p, q>.
+template <int NV>
+__global__ void __launch_bounds__(kFinBlock) k_fin_beta(Ctl* ctl, const double* __restrict__ partials, int np,
+                                                        int first) {
+  if (ctl->done) return;
+  double t[NV];
+  fold_partials<NV>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double rzn = t[0];
+  const double zq = NV > 1 ? t[NV - 1] : 0.0;
+  if (first) {
+    ctl->beta = 0.0;
+  } else if (ctl->flexible) {
+    ctl->beta = -zq / ctl->pq;
+  } else {
+    ctl->beta = rzn / ctl->rz;
+  }
+  ctl->rz = rzn;
+  ctl->rzn = rzn;
+  ctl->zq = zq;
+  if (!(rzn > 0.0)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  }
+}
+
+__global__ void __launch_bounds__(kFinBlock) k_fin_trr(Ctl* ctl, const double* __restrict__ partials, int np) {
+  double t[1];
+  fold_partials<1>(partials, np, t);
+  if (threadIdx.x == 0) ctl->trr = t[0];
 }
 
 __global__ void k_ctl_restart(Ctl* ctl) {
@@ -429,35 +535,30 @@ __global__ void k_ctl_restart(Ctl* ctl) {
   ctl->state = 0;
 }
 
-// grad_val[k] = -(lambda[row k] * x[col k]).
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_pattern_grad(int n, const int* __restrict__ rp,
-                                                         const int* __restrict__ ci, const double* __restrict__ lam,
-                                                         const double* __restrict__ x, double* __restrict__ g) {
-  int c0, c1;
-  chunk_range<G>(n, c0, c1);
-  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
-  for (int c = c0; c < c1; ++c) {
-    const int row = c * (kBlock / G) + grp;
-    if (row < n) {
-      const double li = lam[row];
-      for (int k = rp[row] + lane; k < rp[row + 1]; k += G) g[k] = -(li * x[ci[k]]);
-    }
-  }
+void launch_fin_beta(Ctl* ctl, double* partials, int np, int first, int nv, hipStream_t s) {
+  if (nv == 2) hipLaunchKernelGGL(k_fin_beta<2>, dim3(1), dim3(kFinBlock), 0, s, ctl, partials, np, first);
+  else hipLaunchKernelGGL(k_fin_beta<1>, dim3(1), dim3(kFinBlock), 0, s, ctl, partials, np, first);
 }
 
-// --------------------------------------------------------- dispatch
+// ------------------------------------------------------------ V-cycle
 
-#define AMG_DISPATCH_G(g, ...)                      \
-  switch (g) {                                      \
-    case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
-    case 2: { constexpr int G = 2; __VA_ARGS__; } break;   \
-    case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
-    case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
-    case 16: { constexpr int G = 16; __VA_ARGS__; } break; \
-    case 32: { constexpr int G = 32; __VA_ARGS__; } break; \
-    default: { constexpr int G = 64; __VA_ARGS__; } break; \
+// Records an event pair around a launch when (kernel, level) is instrumented.
+struct InstScope {
+  Hierarchy& H;
+  hipStream_t s;
+  bool on;
+  InstScope(Hierarchy& h, int kid, int level, hipStream_t st) : H(h), s(st) {
+    on = H.inst.kernel == kid && (H.inst.level == level || H.inst.level < 0) &&
+         2 * (H.inst.used + 1) <= (int)H.inst.ev.size();
+    if (on) AMG_HIP(hipEventRecord(H.inst.ev[2 * H.inst.used], s));
   }
+  ~InstScope() {
+    if (on) {
+      (void)hipEventRecord(H.inst.ev[2 * H.inst.used + 1], s);
+      ++H.inst.used;
+    }
+  }
+};
 
 struct CycleArgs {
   const double* r0;   // level-0 right-hand side (CG residual), FP64
@@ -477,10 +578,10 @@ struct Bufs<double> {
   static double* x(Level& L) { return L.x64.p; }
   static double* b(Level& L) { return L.b64.p; }
   static double* r(Level& L) { return L.r64.p; }
-  static const double* v(Level& L) { return L.v.p; }
-  static const double* sw(Level& L) { return L.sw.p; }
   static double* xs(Level& L) { return L.xs64.p; }
   static double* rs(Level& L) { return L.rs64.p; }
+  static const double* v(Level& L) { return L.v.p; }
+  static const double* sw(Level& L) { return L.sw.p; }
   static const double* inv(Coarse& C) { return C.inv.p; }
 };
 template <>
@@ -488,74 +589,55 @@ struct Bufs<float> {
   static float* x(Level& L) { return L.x32.p; }
   static float* b(Level& L) { return L.b32.p; }
   static float* r(Level& L) { return L.r32.p; }
-  static const float* v(Level& L) { return L.v32.p; }
-  static const float* sw(Level& L) { return L.sw32.p; }
   static float* xs(Level& L) { return L.xs32.p; }
   static float* rs(Level& L) { return L.rs32.p; }
+  static const float* v(Level& L) { return L.v32.p; }
+  static const float* sw(Level& L) { return L.sw32.p; }
   static const float* inv(Coarse& C) { return C.inv32.p; }
 };
 
-template <class T, class BT>
-void launch_pre(Level& L, const BT* b, T* x, T* r, const Ctl* ctl, hipStream_t s) {
-  AMG_DISPATCH_G(L.gA, hipLaunchKernelGGL((k_pre<G, T, BT, T>), dim3(stream_grid(L.n, G)), dim3(kBlock), 0, s, L.n,
-                                          L.rp.p, L.ci.p, Bufs<T>::v(L), Bufs<T>::sw(L), b, x, r, ctl));
-}
-
-template <class T, class BT>
-void launch_sweep(Level& L, const BT* b, const T* x, const T* r, T* x2, T* r2, const Ctl* ctl, hipStream_t s) {
-  AMG_DISPATCH_G(L.gA, hipLaunchKernelGGL((k_sweep<G, T, BT, T>), dim3(stream_grid(L.n, G)), dim3(kBlock), 0, s,
-                                          L.n, L.rp.p, L.ci.p, Bufs<T>::v(L), Bufs<T>::sw(L), b, x, r, x2, r2, ctl));
-}
-
-template <class T, class BT, class OT, int RED>
-void launch_post(Level& L, const BT* b, const T* x, OT* out, const CycleArgs& a, hipStream_t s) {
-  AMG_DISPATCH_G(L.gA, hipLaunchKernelGGL((k_post<G, T, BT, T, OT, RED>), dim3(stream_grid(L.n, G)), dim3(kBlock), 0,
-                                          s, L.n, L.rp.p, L.ci.p, Bufs<T>::v(L), Bufs<T>::sw(L), b, x, out, a.q,
-                                          a.ctl, a.partials, a.first));
-}
-
-template <class T, class XT>
-void launch_restrict(Hierarchy& H, Level& L, const XT* r, T* bc, const Ctl* ctl, hipStream_t s) {
-  const int nc = L.nagg;
+template <class T>
+void launch_restrict(Hierarchy& H, Level& L, const T* r, T* bc, const Ctl* ctl, hipStream_t s) {
   if constexpr (std::is_same<T, double>::value) {
-    AMG_DISPATCH_G(L.gR, hipLaunchKernelGGL((k_restrict<G, double, XT, T>), dim3(stream_grid(nc, G)), dim3(kBlock),
-                                            0, s, nc, L.rrp.p, L.rci.p, L.rv.p, r, bc, ctl));
+    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<double, T>{L.rv.p, r, bc}, ctl, nullptr, s);
   } else if (H.bf16()) {
-    AMG_DISPATCH_G(L.gR, hipLaunchKernelGGL((k_restrict<G, uint16_t, XT, T>), dim3(stream_grid(nc, G)),
-                                            dim3(kBlock), 0, s, nc, L.rrp.p, L.rci.p, L.rbf.p, r, bc, ctl));
+    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<uint16_t, T>{L.rbf.p, r, bc}, ctl, nullptr, s);
   } else {
-    AMG_DISPATCH_G(L.gR, hipLaunchKernelGGL((k_restrict<G, float, XT, T>), dim3(stream_grid(nc, G)), dim3(kBlock),
-                                            0, s, nc, L.rrp.p, L.rci.p, L.rv32.p, r, bc, ctl));
+    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<float, T>{L.rv32.p, r, bc}, ctl, nullptr, s);
   }
 }
 
 template <class T>
 void launch_prolong(Hierarchy& H, Level& L, const T* xc, T* x, const Ctl* ctl, hipStream_t s) {
   if constexpr (std::is_same<T, double>::value) {
-    AMG_DISPATCH_G(L.gP, hipLaunchKernelGGL((k_prolong<G, double, T>), dim3(stream_grid(L.n, G)), dim3(kBlock), 0, s,
-                                            L.n, L.prp.p, L.pci.p, L.pv.p, xc, x, ctl));
+    sweep(L.shP, L.n, L.prp.p, L.pci.p, OpProlong<double, T>{L.pv.p, xc, x}, ctl, nullptr, s);
   } else if (H.bf16()) {
-    AMG_DISPATCH_G(L.gP, hipLaunchKernelGGL((k_prolong<G, uint16_t, T>), dim3(stream_grid(L.n, G)), dim3(kBlock), 0,
-                                            s, L.n, L.prp.p, L.pci.p, L.pbf.p, xc, x, ctl));
+    sweep(L.shP, L.n, L.prp.p, L.pci.p, OpProlong<uint16_t, T>{L.pbf.p, xc, x}, ctl, nullptr, s);
   } else {
-    AMG_DISPATCH_G(L.gP, hipLaunchKernelGGL((k_prolong<G, float, T>), dim3(stream_grid(L.n, G)), dim3(kBlock), 0, s,
-                                            L.n, L.prp.p, L.pci.p, L.pv32.p, xc, x, ctl));
+    sweep(L.shP, L.n, L.prp.p, L.pci.p, OpProlong<float, T>{L.pv32.p, xc, x}, ctl, nullptr, s);
   }
 }
 
 // One V-cycle on level-0 rhs a.r0 -> a.z0 (FP64 at the boundary, T inside).
-// Extra smoothing sweeps (nu > 1) ping-pong through the level's spare buffers.
+// With a.red, the level-0 post-smoother emits the <r,z> (and <z,q>) partials
+// and the finalize kernel forms beta.  Extra smoothing sweeps (nu > 1)
+// ping-pong through the level's spare buffers.
 template <class T>
 void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
   const int nl = (int)H.lv.size();
   Coarse& C = H.co;
-  const Ctl* ectl = a.ctl;
+  Ctl* ctl = a.ctl;
   if (nl == 1) {
-    hipLaunchKernelGGL((k_coarse<double, double, double>), dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       C.n, C.m, C.inv.p, a.r0, a.z0, ectl);
-    if (a.red)
-      hipLaunchKernelGGL(k_dots_rz, dim3(stream_grid(C.n, 1)), dim3(kBlock), 0, s, C.n, a.r0, a.z0,
-                         a.q ? a.q : a.z0, a.ctl, a.partials, a.first);
+    {
+      InstScope is(H, KID_COARSE, 0, s);
+      hipLaunchKernelGGL((k_coarse<double, double, double>), dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                         C.n, C.m, C.inv.p, a.r0, a.z0, ctl);
+    }
+    if (a.red) {
+      const int g = vec_grid(C.n);
+      hipLaunchKernelGGL(k_dots_rz, dim3(g), dim3(kBlock), 0, s, C.n, a.r0, a.z0, a.q ? a.q : a.z0, ctl, a.partials);
+      launch_fin_beta(ctl, a.partials, g, a.first, 2, s);
+    }
     return;
   }
   T* cx[AMG_MAX_LEVELS];
@@ -569,39 +651,76 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
     cr[l] = Bufs<T>::r(L);
     sx[l] = Bufs<T>::xs(L);
     sr[l] = Bufs<T>::rs(L);
-    if (l == 0) launch_pre<T, double>(L, a.r0, cx[l], cr[l], ectl, s);
-    else launch_pre<T, T>(L, Bufs<T>::b(L), cx[l], cr[l], ectl, s);
+    {
+      InstScope is(H, KID_PRE, l, s);
+      if (l == 0)
+        sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPre<T, double>{Bufs<T>::v(L), Bufs<T>::sw(L), a.r0, cx[l], cr[l]}, ctl,
+              nullptr, s);
+      else
+        sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPre<T, T>{Bufs<T>::v(L), Bufs<T>::sw(L), Bufs<T>::b(L), cx[l], cr[l]},
+              ctl, nullptr, s);
+    }
     for (int k = 1; k < npre; ++k) {
-      if (l == 0) launch_sweep<T, double>(L, a.r0, cx[l], cr[l], sx[l], sr[l], ectl, s);
-      else launch_sweep<T, T>(L, Bufs<T>::b(L), cx[l], cr[l], sx[l], sr[l], ectl, s);
+      if (l == 0)
+        sweep(L.shA, L.n, L.rp.p, L.ci.p,
+              OpSweep<T, double>{Bufs<T>::v(L), Bufs<T>::sw(L), a.r0, cx[l], cr[l], sx[l], sr[l]}, ctl, nullptr, s);
+      else
+        sweep(L.shA, L.n, L.rp.p, L.ci.p,
+              OpSweep<T, T>{Bufs<T>::v(L), Bufs<T>::sw(L), Bufs<T>::b(L), cx[l], cr[l], sx[l], sr[l]}, ctl, nullptr,
+              s);
       std::swap(cx[l], sx[l]);
       std::swap(cr[l], sr[l]);
     }
-    launch_restrict<T, T>(H, L, cr[l], Bufs<T>::b(H.lv[l + 1]), ectl, s);
+    {
+      InstScope is(H, KID_RESTRICT, l, s);
+      launch_restrict<T>(H, L, cr[l], Bufs<T>::b(H.lv[l + 1]), ctl, s);
+    }
   }
   T* res;
   {
     Level& Lc = H.lv[nl - 1];
+    InstScope is(H, KID_COARSE, nl - 1, s);
     hipLaunchKernelGGL((k_coarse<T, T, T>), dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C.n, C.m,
-                       Bufs<T>::inv(C), Bufs<T>::b(Lc), Bufs<T>::x(Lc), ectl);
+                       Bufs<T>::inv(C), Bufs<T>::b(Lc), Bufs<T>::x(Lc), ctl);
     res = Bufs<T>::x(Lc);
   }
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = H.lv[l];
-    launch_prolong<T>(H, L, res, cx[l], ectl, s);
-    // free T buffers of this level after restriction: cr[l] and, with nu_pre > 1, sx[l]
+    {
+      InstScope is(H, KID_PROLONG, l, s);
+      launch_prolong<T>(H, L, res, cx[l], ctl, s);
+    }
+    // free T buffers of this level after restriction: cr[l] and sx[l]
     T* cur = cx[l];
     T* spare[2] = {cr[l], sx[l]};
     for (int k = 0; k < npost; ++k) {
       const bool last = (k == npost - 1);
+      const T* vv = Bufs<T>::v(L);
+      const T* sw = Bufs<T>::sw(L);
       if (l == 0 && last) {
-        if (a.red == 2) launch_post<T, double, double, 2>(L, a.r0, cur, a.z0, a, s);
-        else if (a.red == 1) launch_post<T, double, double, 1>(L, a.r0, cur, a.z0, a, s);
-        else launch_post<T, double, double, 0>(L, a.r0, cur, a.z0, a, s);
+        int np = 0;
+        {
+          InstScope is(H, KID_POST, l, s);
+          if (a.red == 2)
+            np = sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, double, 2>{vv, sw, a.r0, cur, a.z0, a.q}, ctl,
+                       a.partials, s);
+          else if (a.red == 1)
+            np = sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, double, 1>{vv, sw, a.r0, cur, a.z0, a.q}, ctl,
+                       a.partials, s);
+          else
+            sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, double, 0>{vv, sw, a.r0, cur, a.z0, nullptr}, ctl,
+                  nullptr, s);
+        }
+        if (a.red) launch_fin_beta(ctl, a.partials, np, a.first, a.red, s);
       } else {
         T* dst = spare[k & 1];
-        if (l == 0) launch_post<T, double, T, 0>(L, a.r0, cur, dst, a, s);
-        else launch_post<T, T, T, 0>(L, Bufs<T>::b(L), cur, dst, a, s);
+        InstScope is(H, KID_POST, l, s);
+        if (l == 0)
+          sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, T, 0>{vv, sw, a.r0, cur, dst, nullptr}, ctl, nullptr,
+                s);
+        else
+          sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, T, T, 0>{vv, sw, Bufs<T>::b(L), cur, dst, nullptr}, ctl,
+                nullptr, s);
         spare[k & 1] = cur;
         cur = dst;
       }
@@ -621,23 +740,50 @@ void read_ctl(Hierarchy& H, hipStream_t s) {
   AMG_HIP(hipStreamSynchronize(s));
 }
 
+// Launch shape of a sweep over a CSR matrix with `n` rows (host row
+// pointers): the most rows per workgroup whose nonzeros fit the staging
+// buffer, with enough lanes per row for the in-LDS sums of long rows.
+Shape make_shape(const std::vector<int>& rp, int n) {
+  Shape sh;
+  const double avg = n > 0 ? (double)(rp[n] - rp[0]) / n : 1.0;
+  for (int rb = kBlock; rb >= kBlock / 64; rb >>= 1) {
+    const int lanes = kBlock / rb;
+    if (lanes < avg / 16.0 && rb > kBlock / 64) continue;
+    int mx = 0;
+    for (int r0 = 0; r0 < n; r0 += rb) mx = std::max(mx, rp[std::min(r0 + rb, n)] - rp[r0]);
+    if (mx <= kStreamCap) {
+      sh.stream = 1;
+      sh.g = lanes;
+      sh.rows_per_block = rb;
+      sh.max_block_nnz = mx;
+      sh.grid = round8(((int64_t)n + rb - 1) / rb);
+      return sh;
+    }
+  }
+  sh.stream = 0;
+  sh.g = 64;
+  sh.rows_per_block = kBlock / 64;
+  sh.grid = round8(std::min<int64_t>(((int64_t)n + sh.rows_per_block - 1) / sh.rows_per_block, kMaxGrid));
+  return sh;
+}
+
+std::vector<int> host_copy(const DBuf<int>& d, int64_t count) {
+  std::vector<int> h((size_t)count);
+  if (count) AMG_HIP(hipMemcpy(h.data(), d.p, sizeof(int) * count, hipMemcpyDeviceToHost));
+  return h;
+}
+
 }  // namespace
 
 // ================================================================ public
 
 void choose_shapes(Hierarchy& H) {
-  auto pick = [](int64_t nnz, int64_t rows) {
-    if (rows <= 0) return 1;
-    double avg = (double)nnz / (double)rows;
-    int g = pow2_ceil((int)std::ceil(avg));
-    return std::min(64, std::max(1, g));
-  };
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level& L = H.lv[l];
-    L.gA = pick(L.nnz, L.n);
+    L.shA = make_shape(host_copy(L.rp, L.n + 1), L.n);
     if (l + 1 < H.lv.size()) {
-      L.gP = pick(L.pnnz, L.n);
-      L.gR = pick(L.pnnz, L.nagg);
+      L.shP = make_shape(host_copy(L.prp, L.n + 1), L.n);
+      L.shR = make_shape(host_copy(L.rrp, L.nagg + 1), L.nagg);
     }
   }
 }
@@ -648,7 +794,9 @@ void alloc_solve_workspace(Hierarchy& H) {
   H.z.alloc(n);
   H.p.alloc(n);
   H.q.alloc(n);
-  H.partials.alloc((int64_t)kMaxGrid * 4);
+  int64_t np = std::max<int64_t>(vec_grid(n), H.lv[0].shA.grid);
+  np = std::max<int64_t>(np, vec_grid(H.co.n));
+  H.partials.alloc(np * 4 + 64);
   if (!H.ctl.p) {
     H.ctl.alloc(1);
     AMG_HIP(hipMemset(H.ctl.p, 0, sizeof(Ctl)));
@@ -663,6 +811,82 @@ void alloc_solve_workspace(Hierarchy& H) {
   }
 }
 
+// Algorithmic bytes of one launch: each matrix array streamed once, each
+// distinct vector operand read once (neighbour gathers counted once), each
+// output written once.
+double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible) {
+  const int nl = (int)H.lv.size();
+  if (level < 0 || level >= nl) return 0.0;
+  const Level& L = H.lv[level];
+  const double v = H.fp32() ? 4.0 : 8.0;                        // cycle vector/value bytes
+  const double pw = H.fp32() ? (H.bf16() ? 2.0 : 4.0) : 8.0;   // transfer value bytes
+  const double n = L.n, nnz = (double)L.nnz;
+  auto M = [](double nz, double rows, double w) { return nz * (w + 4.0) + 4.0 * (rows + 1.0); };
+  const double bw = level == 0 ? 8.0 : v;                       // rhs of the level
+  switch (kid) {
+    case KID_SPMV_DOT: return M(nnz, n, 8.0) + 16.0 * n;
+    case KID_PRE: return M(nnz, n, v) + (bw + 3.0 * v) * n;
+    case KID_POST: {
+      const double ow = level == 0 ? 8.0 : v;
+      return M(nnz, n, v) + (bw + 2.0 * v + ow) * n + (level == 0 && flexible ? 8.0 * n : 0.0);
+    }
+    case KID_RESTRICT:
+      if (level == nl - 1) return 0.0;
+      return M((double)L.pnnz, (double)L.nagg, pw) + v * n + v * (double)L.nagg;
+    case KID_PROLONG:
+      if (level == nl - 1) return 0.0;
+      return M((double)L.pnnz, n, pw) + v * (double)L.nagg + 2.0 * v * n;
+    case KID_CG_UPDATE: return 48.0 * n;
+    case KID_XPAY: return 24.0 * n;
+    case KID_COARSE: {
+      const double nc = H.co.n;
+      return nc * nc * (nl == 1 ? 8.0 : v) + 2.0 * nc * (nl == 1 ? 8.0 : v);
+    }
+  }
+  return 0.0;
+}
+
+// Bytes of one PCG iteration (SpMV+dot, update, V-cycle, direction update).
+double iteration_bytes(const Hierarchy& H, int flexible) {
+  const int nl = (int)H.lv.size();
+  double b = kernel_bytes(H, KID_SPMV_DOT, 0, flexible) + kernel_bytes(H, KID_CG_UPDATE, 0, flexible) +
+             kernel_bytes(H, KID_XPAY, 0, flexible) + kernel_bytes(H, KID_COARSE, nl - 1, flexible);
+  for (int l = 0; l < nl - 1; ++l) {
+    const double n = H.lv[l].n;
+    const double v = H.fp32() ? 4.0 : 8.0;
+    b += kernel_bytes(H, KID_PRE, l, flexible) + kernel_bytes(H, KID_RESTRICT, l, flexible) +
+         kernel_bytes(H, KID_PROLONG, l, flexible) + H.prm.nu_post * kernel_bytes(H, KID_POST, l, flexible);
+    b += (H.prm.nu_pre - 1) * (kernel_bytes(H, KID_PRE, l, flexible) + 2.0 * v * n);
+  }
+  return b;
+}
+
+void set_instrument(Hierarchy& H, int kid, int level) {
+  if (H.inst.ev.empty()) {
+    H.inst.ev.resize(2 * 8192);
+    for (auto& e : H.inst.ev) AMG_HIP(hipEventCreate(&e));
+  }
+  H.inst.kernel = kid;
+  H.inst.level = level;
+  H.inst.used = 0;
+}
+
+void read_instrument(Hierarchy& H, int* launches, double* total_ms, double* min_ms, double* max_ms) {
+  double tot = 0.0, mn = 1e300, mx = 0.0;
+  for (int i = 0; i < H.inst.used; ++i) {
+    AMG_HIP(hipEventSynchronize(H.inst.ev[2 * i + 1]));
+    float ms = 0.f;
+    AMG_HIP(hipEventElapsedTime(&ms, H.inst.ev[2 * i], H.inst.ev[2 * i + 1]));
+    tot += ms;
+    mn = std::min(mn, (double)ms);
+    mx = std::max(mx, (double)ms);
+  }
+  *launches = H.inst.used;
+  *total_ms = tot;
+  *min_ms = H.inst.used ? mn : 0.0;
+  *max_ms = mx;
+}
+
 void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s) {
   CycleArgs a{d_r, d_z, nullptr, nullptr, nullptr, 0, 0};
   vcycle(H, a, s);
@@ -671,8 +895,8 @@ void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s) {
 
 void pattern_grad(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, hipStream_t s) {
   Level& L = H.lv[0];
-  AMG_DISPATCH_G(L.gA, hipLaunchKernelGGL((k_pattern_grad<G>), dim3(stream_grid(L.n, G)), dim3(kBlock), 0, s, L.n,
-                                          L.rp.p, L.ci.p, d_lam, d_x, d_g));
+  const int grid = (int)(((int64_t)L.n + kBlock / 8 - 1) / (kBlock / 8));
+  hipLaunchKernelGGL(k_pattern_grad, dim3(grid), dim3(kBlock), 0, s, L.n, L.rp.p, L.ci.p, d_lam, d_x, d_g);
   AMG_HIP(hipGetLastError());
 }
 
@@ -685,42 +909,78 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
   const int flexible = o.flexible < 0 ? (H.fp32() ? 1 : 0) : o.flexible;
   Ctl* ctl = H.ctl.p;
   double* part = H.partials.p;
-  const int gcg = stream_grid(n, 1);
-  hipLaunchKernelGGL(k_cg_init, dim3(gcg), dim3(kBlock), 0, s, n, d_b, H.r.p, d_x, ctl, part, tol, o.maxiter,
-                     flexible);
+  const int gv = vec_grid(n);
+  hipLaunchKernelGGL(k_cg_init, dim3(gv), dim3(kBlock), 0, s, n, d_b, H.r.p, d_x, part);
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv, tol, o.maxiter, flexible);
   AMG_HIP(hipGetLastError());
-  const int chunk = o.check_every > 0 ? o.check_every : 4;
   int restarts = 0;
   amg_status st = AMG_OK;
   for (;;) {
     // (re)start: z = M^-1 r, rz = <r, z>, p = z
     CycleArgs a0{H.r.p, H.z.p, H.q.p, ctl, part, 1, 1};
     vcycle(H, a0, s);
-    hipLaunchKernelGGL(k_xpay, dim3(gcg), dim3(kBlock), 0, s, n, H.z.p, H.p.p, ctl, 1);
+    {
+      InstScope is(H, KID_XPAY, 0, s);
+      hipLaunchKernelGGL(k_xpay, dim3(gv), dim3(kBlock), 0, s, n, H.z.p, H.p.p, ctl, 1);
+    }
+    // Iterations are queued in chunks; between chunks the host reads the
+    // control block and sizes the next chunk from the observed decay of
+    // ||r||^2 so that few iterations are queued past convergence (those
+    // return at once on the done flag).
+    int chunk = o.check_every > 0 ? o.check_every : 4;
+    int it_prev = -1;
+    double rr_prev = 0.0;
     for (;;) {
       for (int it = 0; it < chunk; ++it) {
-        AMG_DISPATCH_G(L0.gA, hipLaunchKernelGGL((k_spmv_dot<G>), dim3(stream_grid(n, G)), dim3(kBlock), 0, s, n,
-                                                 L0.rp.p, L0.ci.p, L0.v.p, H.p.p, H.q.p, ctl, part));
-        hipLaunchKernelGGL(k_cg_update, dim3(gcg), dim3(kBlock), 0, s, n, d_x, H.r.p, H.p.p, H.q.p, ctl, part);
+        int np;
+        {
+          InstScope is(H, KID_SPMV_DOT, 0, s);
+          np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpSpmvDot{L0.v.p, H.p.p, H.q.p}, ctl, part, s);
+        }
+        hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinBlock), 0, s, ctl, part, np);
+        {
+          InstScope is(H, KID_CG_UPDATE, 0, s);
+          hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(kBlock), 0, s, n, d_x, H.r.p, H.p.p, H.q.p, ctl, part);
+        }
+        hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv);
         CycleArgs a{H.r.p, H.z.p, H.q.p, ctl, part, flexible ? 2 : 1, 0};
         vcycle(H, a, s);
-        hipLaunchKernelGGL(k_xpay, dim3(gcg), dim3(kBlock), 0, s, n, H.z.p, H.p.p, ctl, 0);
+        {
+          InstScope is(H, KID_XPAY, 0, s);
+          hipLaunchKernelGGL(k_xpay, dim3(gv), dim3(kBlock), 0, s, n, H.z.p, H.p.p, ctl, 0);
+        }
       }
       AMG_HIP(hipGetLastError());
       read_ctl(H, s);
       if (H.h_ctl->done) break;
+      if (o.check_every <= 0) {
+        const Ctl& c = *H.h_ctl;
+        if (it_prev < 0) {  // decay measured from ||r_0||^2 = ||b||^2
+          it_prev = 0;
+          rr_prev = c.bb;
+        }
+        int next = 4;
+        if (c.thresh <= 0.0) {
+          next = 32;
+        } else if (c.iters > it_prev && rr_prev > 0.0 && c.rr > 0.0) {
+          const double rate = std::log(c.rr / rr_prev) / (double)(c.iters - it_prev);
+          if (rate < -1e-3) next = (int)std::min(64.0, std::ceil(std::log(c.thresh / c.rr) / rate));
+        }
+        it_prev = c.iters;
+        rr_prev = c.rr;
+        next = std::min(next, std::max(1, c.maxiter - c.iters));
+        chunk = std::max(1, std::min(next, 32));
+      }
     }
     const int state = H.h_ctl->state;
-    if (state == 3) {  // b = 0
-      break;
-    }
+    if (state == 3) break;  // b = 0
     if (state < 0) {
       st = AMG_ERR_BREAKDOWN;
       break;
     }
     // true residual r = b - A x
-    AMG_DISPATCH_G(L0.gA, hipLaunchKernelGGL((k_true_resid<G>), dim3(stream_grid(n, G)), dim3(kBlock), 0, s, n,
-                                             L0.rp.p, L0.ci.p, L0.v.p, d_b, d_x, H.r.p, ctl, part));
+    const int np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpTrueResid{L0.v.p, d_x, d_b, H.r.p}, nullptr, part, s);
+    hipLaunchKernelGGL(k_fin_trr, dim3(1), dim3(kFinBlock), 0, s, ctl, part, np);
     read_ctl(H, s);
     const Ctl& c = *H.h_ctl;
     if (c.trr <= c.thresh) {

@@ -141,6 +141,26 @@ class AmgHierarchy:
         _lib.check(self._L.amg_apply_vcycle(self._h, r.data_ptr(), z.data_ptr(), _stream()), "amg_apply_vcycle")
         return z
 
+    def instrument(self, kernel: str | None, level: int = 0):
+        """Time every launch of `kernel` at `level` inside later solves (HIP events)."""
+        kid = -1 if kernel is None else _lib.KERNELS[kernel]
+        _lib.check(self._L.amg_instrument(self._h, kid, level), "amg_instrument")
+
+    def instrument_read(self) -> dict:
+        n = C.c_int(0)
+        tot, mn, mx = C.c_double(0), C.c_double(0), C.c_double(0)
+        _lib.check(self._L.amg_instrument_read(self._h, C.byref(n), C.byref(tot), C.byref(mn), C.byref(mx)),
+                   "amg_instrument_read")
+        return dict(launches=n.value, total_ms=tot.value, min_ms=mn.value, max_ms=mx.value,
+                    avg_ms=tot.value / n.value if n.value else 0.0)
+
+    def kernel_bytes(self, kernel: str | None, level: int = 0, flexible: bool = False) -> float:
+        """Algorithmic bytes of one launch (kernel None: one PCG iteration)."""
+        kid = -1 if kernel is None else _lib.KERNELS[kernel]
+        b = C.c_double(0)
+        _lib.check(self._L.amg_kernel_bytes(self._h, kid, level, int(flexible), C.byref(b)), "amg_kernel_bytes")
+        return b.value
+
     def stats(self) -> dict:
         s = _lib.amg_hier_stats()
         _lib.check(self._L.amg_hierarchy_stats(self._h, C.byref(s)), "amg_hierarchy_stats")
