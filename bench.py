@@ -146,7 +146,7 @@ def main():
     st = H.stats()
     kernels = {}
     for name, lvl in (("spmv_dot", 0), ("pre", 0), ("post", 0), ("restrict", 0), ("prolong", 0),
-                      ("cg_update", 0), ("xpay", 0), ("pre", 1), ("post", 1)):
+                      ("cg_update", 0), ("pre", 1), ("post", 1), ("restrict", 1), ("prolong", 1)):
         H.instrument(name, lvl)
         for _ in range(max(2, args.steps // 2)):
             H.solve(d_b, args.tol, out=x)

@@ -182,13 +182,13 @@ amg_status amg_export_field(amg_handle h, int level, int field, void* d_dst, siz
 /* ---- measurement (diagnostics; no effect on results) ----
  * Kernel ids for amg_instrument / amg_kernel_bytes. */
 enum {
-  AMG_KERNEL_SPMV_DOT = 0,   /* q = A p fused with <p,q> (level 0) */
-  AMG_KERNEL_PRE = 1,        /* pre-smoothing from zero fused with the residual */
+  AMG_KERNEL_SPMV_DOT = 0,   /* p = z + beta p, q = A p, <p,q> (level 0, one fused sweep) */
+  AMG_KERNEL_PRE = 1,        /* residual of the pre-smoothed iterate x = sw o b */
   AMG_KERNEL_POST = 2,       /* post-smoothing sweep (level 0: writes z, reduces <r,z>) */
   AMG_KERNEL_RESTRICT = 3,   /* b_{l+1} = R_l r_l */
   AMG_KERNEL_PROLONG = 4,    /* x_l += P_l x_{l+1} */
-  AMG_KERNEL_CG_UPDATE = 5,  /* x += alpha p, r -= alpha q, <r,r> */
-  AMG_KERNEL_XPAY = 6,       /* p = z + beta p */
+  AMG_KERNEL_CG_UPDATE = 5,  /* x += alpha p, r -= alpha q, <r,r>, x0 = sw o r */
+  AMG_KERNEL_XPAY = 6,       /* (fused into AMG_KERNEL_SPMV_DOT; never launched) */
   AMG_KERNEL_COARSE = 7      /* dense coarsest solve */
 };
 

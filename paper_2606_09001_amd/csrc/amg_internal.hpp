@@ -151,7 +151,7 @@ struct Hierarchy {
   std::vector<Level> lv;
   Coarse co;
   // solve workspace (level 0, FP64)
-  DBuf<double> r, z, p, q, bcopy;
+  DBuf<double> r, z, p, z2, q;
   DBuf<double> partials;
   DBuf<Ctl> ctl;
   Ctl* h_ctl = nullptr;  // pinned host mirror

@@ -56,17 +56,27 @@ inline int round8(int64_t g) {
 //   void epi(row, s, d[])      consumes the row sum s; d[] collects dot partials
 //   static constexpr int NRED  number of dot products reduced
 
-// q = A p, <p, q>
-struct OpSpmvDot {
+// Direction update fused with the product: p' = z + beta p (p' = z on the
+// first iteration of a (re)start), q = A p', <p', q>; p' goes to a second
+// buffer because neighbouring rows still gather the old p.  beta is read
+// from the device control block.
+struct OpSpmvXpayDev {
   using PT = double;
   static constexpr int NRED = 1;
   const double* v;
+  const double* z;
   const double* p;
+  double* pn;
   double* q;
-  __device__ PT prod(int k, int j) const { return v[k] * p[j]; }
+  const Ctl* ctl;
+  int first;
+  __device__ double dir(int j, double beta) const { return first ? z[j] : z[j] + beta * p[j]; }
+  __device__ PT prod(int k, int j) const { return v[k] * dir(j, ctl->beta); }
   __device__ void epi(int row, PT s, double* d) const {
+    const double pr = dir(row, ctl->beta);
+    pn[row] = pr;
     q[row] = s;
-    d[0] += p[row] * s;
+    d[0] += pr * s;
   }
 };
 
@@ -103,6 +113,20 @@ struct OpPre {
     x[row] = sw[row] * bi;
     r[row] = bi - s;
   }
+};
+
+// Residual of the pre-smoothed iterate when x = sw o b was already written
+// by the producer of b:  r_i = b_i - sum_j a_ij x_j.
+template <class T, class BT>
+struct OpResid {
+  using PT = T;
+  static constexpr int NRED = 0;
+  const T* v;
+  const BT* b;
+  const T* x;
+  T* r;
+  __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
+  __device__ void epi(int row, PT s, double*) const { r[row] = (T)b[row] - s; }
 };
 
 // Further Jacobi sweep in residual form, fused with the new residual:
@@ -149,6 +173,7 @@ struct OpPost {
 };
 
 // y = R x (restriction); R values of type RT (double, float or bf16 bits).
+// Also writes the coarse level's pre-smoothed iterate xc = swc o y.
 template <class RT, class T>
 struct OpRestrict {
   using PT = T;
@@ -156,8 +181,13 @@ struct OpRestrict {
   const RT* v;
   const T* x;
   T* y;
+  const T* swc;
+  T* xc;
   __device__ PT prod(int k, int j) const { return (T)ValCvt<RT>::f(v[k]) * x[j]; }
-  __device__ void epi(int row, PT s, double*) const { y[row] = s; }
+  __device__ void epi(int row, PT s, double*) const {
+    y[row] = s;
+    if (xc) xc[row] = swc[row] * s;
+  }
 };
 
 // x += P xc (prolongation and coarse-grid correction).
@@ -323,14 +353,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(int n, const double* __restr
   publish_partials<1>(d, partials);
 }
 
-// x += alpha p ; r -= alpha q ; partial <r, r>.
+// x += alpha p ; r -= alpha q ; partial <r, r>; also the level-0
+// pre-smoothed iterate x0 = sw o r of the next V-cycle (cycle precision T).
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_cg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                      const T* __restrict__ sw, T* __restrict__ x0,
                                                       const Ctl* __restrict__ ctl, double* __restrict__ partials) {
   if (ctl->done) return;
   const double alpha = ctl->alpha;
   const int base = vec_base();
   double xv[kVecPer], rv[kVecPer], pv[kVecPer], qv[kVecPer];
+  T wv[kVecPer];
 #pragma unroll
   for (int u = 0; u < kVecPer; ++u) {
     const int i = base + threadIdx.x + u * kBlock;
@@ -339,6 +373,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int n, double* __restrict_
     rv[u] = ok ? r[i] : 0.0;
     pv[u] = ok ? p[i] : 0.0;
     qv[u] = ok ? q[i] : 0.0;
+    wv[u] = ok ? sw[i] : (T)0;
   }
   double d[1] = {0.0};
 #pragma unroll
@@ -348,30 +383,23 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int n, double* __restrict_
       x[i] = xv[u] + alpha * pv[u];
       const double ri = rv[u] - alpha * qv[u];
       r[i] = ri;
+      x0[i] = wv[u] * (T)ri;
       d[0] += ri * ri;
     }
   }
   publish_partials<1>(d, partials);
 }
 
-// p = z + beta p  (p = z on the first iteration of a (re)start).
-__global__ void __launch_bounds__(kBlock) k_xpay(int n, const double* __restrict__ z, double* __restrict__ p,
-                                                 const Ctl* __restrict__ ctl, int first) {
-  if (ctl->done) return;
-  const double beta = ctl->beta;
+// x0 = sw o r (first V-cycle of a solve or restart).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_sw_mul(int n, const T* __restrict__ sw, const double* __restrict__ r,
+                                                   T* __restrict__ x0, const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
   const int base = vec_base();
-  double zv[kVecPer], pv[kVecPer];
 #pragma unroll
   for (int u = 0; u < kVecPer; ++u) {
     const int i = base + threadIdx.x + u * kBlock;
-    const bool ok = i < n;
-    zv[u] = ok ? z[i] : 0.0;
-    pv[u] = (ok && !first) ? p[i] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < kVecPer; ++u) {
-    const int i = base + threadIdx.x + u * kBlock;
-    if (i < n) p[i] = first ? zv[u] : zv[u] + beta * pv[u];
+    if (i < n) x0[i] = sw[i] * (T)r[i];
   }
 }
 
@@ -412,11 +440,21 @@ __global__ void __launch_bounds__(kBlock) k_pattern_grad(int n, const int* __res
 template <int NV>
 __device__ inline void fold_partials(const double* __restrict__ partials, int np, double (&tot)[NV]) {
   __shared__ double red[NV][kFinBlock / 64];
+  constexpr int UF = 8;
   double acc[NV];
 #pragma unroll
   for (int m = 0; m < NV; ++m) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < np; b += kFinBlock) s += partials[m * np + b];
+    for (int b0 = 0; b0 < np; b0 += kFinBlock * UF) {
+      double t[UF];
+#pragma unroll
+      for (int u = 0; u < UF; ++u) {
+        const int b = b0 + threadIdx.x + u * kFinBlock;
+        t[u] = b < np ? partials[m * np + b] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UF; ++u) s += t[u];
+    }
     acc[m] = wave_sum(s);
   }
   const int w = threadIdx.x >> 6;
@@ -568,6 +606,7 @@ struct CycleArgs {
   double* partials;
   int red;            // 0 none, 1 <r,z>, 2 <r,z> and <z,q>
   int first;
+  int x0_ready;       // level-0 x = sw o r0 already written
 };
 
 template <class T>
@@ -597,13 +636,13 @@ struct Bufs<float> {
 };
 
 template <class T>
-void launch_restrict(Hierarchy& H, Level& L, const T* r, T* bc, const Ctl* ctl, hipStream_t s) {
+void launch_restrict(Hierarchy& H, Level& L, const T* r, T* bc, const T* swc, T* xc, const Ctl* ctl, hipStream_t s) {
   if constexpr (std::is_same<T, double>::value) {
-    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<double, T>{L.rv.p, r, bc}, ctl, nullptr, s);
+    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<double, T>{L.rv.p, r, bc, swc, xc}, ctl, nullptr, s);
   } else if (H.bf16()) {
-    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<uint16_t, T>{L.rbf.p, r, bc}, ctl, nullptr, s);
+    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<uint16_t, T>{L.rbf.p, r, bc, swc, xc}, ctl, nullptr, s);
   } else {
-    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<float, T>{L.rv32.p, r, bc}, ctl, nullptr, s);
+    sweep(L.shR, L.nagg, L.rrp.p, L.rci.p, OpRestrict<float, T>{L.rv32.p, r, bc, swc, xc}, ctl, nullptr, s);
   }
 }
 
@@ -652,13 +691,17 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
     sx[l] = Bufs<T>::xs(L);
     sr[l] = Bufs<T>::rs(L);
     {
+      // pre-smoothing from zero: x = sw o b was written by the producer of b
+      // (CG update on level 0, restriction below), so only r = b - A x remains
       InstScope is(H, KID_PRE, l, s);
-      if (l == 0)
+      if (l == 0 && !a.x0_ready)
         sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPre<T, double>{Bufs<T>::v(L), Bufs<T>::sw(L), a.r0, cx[l], cr[l]}, ctl,
               nullptr, s);
+      else if (l == 0)
+        sweep(L.shA, L.n, L.rp.p, L.ci.p, OpResid<T, double>{Bufs<T>::v(L), a.r0, cx[l], cr[l]}, ctl, nullptr, s);
       else
-        sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPre<T, T>{Bufs<T>::v(L), Bufs<T>::sw(L), Bufs<T>::b(L), cx[l], cr[l]},
-              ctl, nullptr, s);
+        sweep(L.shA, L.n, L.rp.p, L.ci.p, OpResid<T, T>{Bufs<T>::v(L), Bufs<T>::b(L), cx[l], cr[l]}, ctl, nullptr,
+              s);
     }
     for (int k = 1; k < npre; ++k) {
       if (l == 0)
@@ -673,7 +716,10 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
     }
     {
       InstScope is(H, KID_RESTRICT, l, s);
-      launch_restrict<T>(H, L, cr[l], Bufs<T>::b(H.lv[l + 1]), ctl, s);
+      Level& Ln = H.lv[l + 1];
+      const bool coarsest = (l + 1 == nl - 1);
+      launch_restrict<T>(H, L, cr[l], Bufs<T>::b(Ln), coarsest ? nullptr : Bufs<T>::sw(Ln),
+                         coarsest ? nullptr : Bufs<T>::x(Ln), ctl, s);
     }
   }
   T* res;
@@ -793,6 +839,7 @@ void alloc_solve_workspace(Hierarchy& H) {
   H.r.alloc(n);
   H.z.alloc(n);
   H.p.alloc(n);
+  H.z2.alloc(n);
   H.q.alloc(n);
   int64_t np = std::max<int64_t>(vec_grid(n), H.lv[0].shA.grid);
   np = std::max<int64_t>(np, vec_grid(H.co.n));
@@ -823,21 +870,28 @@ double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible) {
   const double n = L.n, nnz = (double)L.nnz;
   auto M = [](double nz, double rows, double w) { return nz * (w + 4.0) + 4.0 * (rows + 1.0); };
   const double bw = level == 0 ? 8.0 : v;                       // rhs of the level
+  const bool has_next = level + 1 < nl;
+  const bool next_coarsest = level + 2 == nl;
   switch (kid) {
-    case KID_SPMV_DOT: return M(nnz, n, 8.0) + 16.0 * n;
-    case KID_PRE: return M(nnz, n, v) + (bw + 3.0 * v) * n;
+    // direction update fused with the product: gathers z and old p, writes new p and q
+    case KID_SPMV_DOT: return M(nnz, n, 8.0) + 32.0 * n;
+    // residual of the pre-smoothed iterate: reads b, gathers x, writes r
+    case KID_PRE: return M(nnz, n, v) + (bw + 2.0 * v) * n;
     case KID_POST: {
       const double ow = level == 0 ? 8.0 : v;
       return M(nnz, n, v) + (bw + 2.0 * v + ow) * n + (level == 0 && flexible ? 8.0 * n : 0.0);
     }
-    case KID_RESTRICT:
-      if (level == nl - 1) return 0.0;
-      return M((double)L.pnnz, (double)L.nagg, pw) + v * n + v * (double)L.nagg;
+    case KID_RESTRICT: {
+      if (!has_next) return 0.0;
+      const double nc = (double)L.nagg;
+      return M((double)L.pnnz, nc, pw) + v * n + v * nc + (next_coarsest ? 0.0 : 2.0 * v * nc);
+    }
     case KID_PROLONG:
-      if (level == nl - 1) return 0.0;
+      if (!has_next) return 0.0;
       return M((double)L.pnnz, n, pw) + v * (double)L.nagg + 2.0 * v * n;
-    case KID_CG_UPDATE: return 48.0 * n;
-    case KID_XPAY: return 24.0 * n;
+    // x, r, p, q read; x, r written; sw read and x0 = sw o r written in cycle precision
+    case KID_CG_UPDATE: return 48.0 * n + 2.0 * v * n;
+    case KID_XPAY: return 0.0;  // fused into KID_SPMV_DOT
     case KID_COARSE: {
       const double nc = H.co.n;
       return nc * nc * (nl == 1 ? 8.0 : v) + 2.0 * nc * (nl == 1 ? 8.0 : v);
@@ -888,7 +942,7 @@ void read_instrument(Hierarchy& H, int* launches, double* total_ms, double* min_
 }
 
 void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s) {
-  CycleArgs a{d_r, d_z, nullptr, nullptr, nullptr, 0, 0};
+  CycleArgs a{d_r, d_z, nullptr, nullptr, nullptr, 0, 0, 0};
   vcycle(H, a, s);
   AMG_HIP(hipGetLastError());
 }
@@ -900,12 +954,27 @@ void pattern_grad(Hierarchy& H, const double* d_lam, const double* d_x, double* 
   AMG_HIP(hipGetLastError());
 }
 
+template <class T>
+void launch_cg_update(Hierarchy& H, int n, double* d_x, const double* p, Ctl* ctl, double* part, hipStream_t s) {
+  Level& L0 = H.lv[0];
+  hipLaunchKernelGGL((k_cg_update<T>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, d_x, H.r.p, p, H.q.p,
+                     Bufs<T>::sw(L0), Bufs<T>::x(L0), ctl, part);
+}
+
+template <class T>
+void launch_sw_mul(Hierarchy& H, int n, const Ctl* ctl, hipStream_t s) {
+  Level& L0 = H.lv[0];
+  hipLaunchKernelGGL((k_sw_mul<T>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, Bufs<T>::sw(L0), H.r.p,
+                     Bufs<T>::x(L0), ctl);
+}
+
 amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int nrhs,
                      amg_info* info, hipStream_t s) {
   if (nrhs != 1) throw Error(AMG_ERR_INVALID_ARG, "this entry point takes one right-hand side");
   auto t0 = std::chrono::steady_clock::now();
   Level& L0 = H.lv[0];
   const int n = H.n;
+  const bool multi = H.lv.size() > 1;
   const int flexible = o.flexible < 0 ? (H.fp32() ? 1 : 0) : o.flexible;
   Ctl* ctl = H.ctl.p;
   double* part = H.partials.p;
@@ -913,16 +982,21 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
   hipLaunchKernelGGL(k_cg_init, dim3(gv), dim3(kBlock), 0, s, n, d_b, H.r.p, d_x, part);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv, tol, o.maxiter, flexible);
   AMG_HIP(hipGetLastError());
+  // search directions alternate between two buffers (the fused direction
+  // update writes the new p while neighbours still gather the old one)
+  double* pb[2] = {H.p.p, H.z2.p};
+  int cur = 0;
   int restarts = 0;
   amg_status st = AMG_OK;
   for (;;) {
-    // (re)start: z = M^-1 r, rz = <r, z>, p = z
-    CycleArgs a0{H.r.p, H.z.p, H.q.p, ctl, part, 1, 1};
-    vcycle(H, a0, s);
-    {
-      InstScope is(H, KID_XPAY, 0, s);
-      hipLaunchKernelGGL(k_xpay, dim3(gv), dim3(kBlock), 0, s, n, H.z.p, H.p.p, ctl, 1);
+    // (re)start: z = M^-1 r, rz = <r, z>; the first direction is p = z
+    if (multi) {
+      if (H.fp32()) launch_sw_mul<float>(H, n, ctl, s);
+      else launch_sw_mul<double>(H, n, ctl, s);
     }
+    CycleArgs a0{H.r.p, H.z.p, H.q.p, ctl, part, 1, 1, multi ? 1 : 0};
+    vcycle(H, a0, s);
+    int first = 1;
     // Iterations are queued in chunks; between chunks the host reads the
     // control block and sizes the next chunk from the observed decay of
     // ||r||^2 so that few iterations are queued past convergence (those
@@ -933,22 +1007,23 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
     for (;;) {
       for (int it = 0; it < chunk; ++it) {
         int np;
+        double* pn = pb[cur ^ 1];
         {
           InstScope is(H, KID_SPMV_DOT, 0, s);
-          np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpSpmvDot{L0.v.p, H.p.p, H.q.p}, ctl, part, s);
+          np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpSpmvXpayDev{L0.v.p, H.z.p, pb[cur], pn, H.q.p, ctl, first}, ctl,
+                     part, s);
         }
+        cur ^= 1;
+        first = 0;
         hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinBlock), 0, s, ctl, part, np);
         {
           InstScope is(H, KID_CG_UPDATE, 0, s);
-          hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(kBlock), 0, s, n, d_x, H.r.p, H.p.p, H.q.p, ctl, part);
+          if (H.fp32()) launch_cg_update<float>(H, n, d_x, pb[cur], ctl, part, s);
+          else launch_cg_update<double>(H, n, d_x, pb[cur], ctl, part, s);
         }
         hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv);
-        CycleArgs a{H.r.p, H.z.p, H.q.p, ctl, part, flexible ? 2 : 1, 0};
+        CycleArgs a{H.r.p, H.z.p, H.q.p, ctl, part, flexible ? 2 : 1, 0, multi ? 1 : 0};
         vcycle(H, a, s);
-        {
-          InstScope is(H, KID_XPAY, 0, s);
-          hipLaunchKernelGGL(k_xpay, dim3(gv), dim3(kBlock), 0, s, n, H.z.p, H.p.p, ctl, 0);
-        }
       }
       AMG_HIP(hipGetLastError());
       read_ctl(H, s);
