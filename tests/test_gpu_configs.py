@@ -1,0 +1,160 @@
+"""Full-size workloads on the GPU, checked against the FP64 oracle.
+
+3D Poisson 128^3 (the benchmark workload), 3D lognormal diffusion 192^3
+with a cached setup and new right-hand sides, and the 2D 512^2 adjoint
+(forward solve, adjoint solve, pattern gradient chained to the log-
+coefficient field through torch autograd).  Sizes and seeds follow the
+workload recipe in the design doc.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2606_09001_amd import matrices as M
+from gpu_util import dev, host, pair, assert_hierarchy_bitexact
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_solves(rp, ci, v, H, O, b, tol, fp32=False):
+    import oracle
+    x, info = H.solve(dev(b), tol)
+    rr = oracle.rel_residual(rp, ci, v, b, host(x))
+    xo, io = O.pcg(b, tol=tol)
+    print(f"[solve] fp32={fp32} gpu iters={info['iters']} oracle iters={io['iters']} rel_resid={rr:.3e} "
+          f"err_vs_oracle={np.linalg.norm(host(x) - xo) / np.linalg.norm(xo):.3e}", flush=True)
+    assert info["status"] == 0 and rr <= tol
+    if not fp32:
+        assert abs(info["iters"] - io["iters"]) <= 1
+    return x, info, xo, io
+
+
+def test_poisson_128_full():
+    rp, ci, v = M.poisson(128, 3)
+    b = M.rhs_normal(len(rp) - 1, 1)
+    H, O = pair(rp, ci, v)
+    assert_hierarchy_bitexact(H, O)
+    x, info, xo, io = _check_solves(rp, ci, v, H, O, b, 1e-8)
+    # iterate parity at the oracle's iteration count
+    k = io["iters"]
+    Hk, _ = pair(rp, ci, v, maxiter=k)
+    xk, ik = Hk.solve(dev(b), 0.0)
+    xok, _ = O.pcg(b, tol=0.0, maxiter=k)
+    err = np.linalg.norm(host(xk) - xok) / np.linalg.norm(xok)
+    print(f"[iterate parity] k={k} err={err:.3e}", flush=True)
+    assert ik["iters"] == k and err <= 1e-9
+    # FP32 cycle inside FP64 CG (bf16 transfers)
+    H32, _ = pair(rp, ci, v, vcycle_prec="fp32")
+    assert_hierarchy_bitexact(H32, O, mixed=True)
+    _check_solves(rp, ci, v, H32, O, b, 1e-8, fp32=True)
+
+
+def test_lognormal_diffusion_192_cached_setup():
+    import oracle
+    N = 192
+    k = np.exp(M.grf(N, 3, seed=2))
+    rp, ci, v = M.diffusion(k)
+    n = len(rp) - 1
+    H, O = pair(rp, ci, v)
+    assert_hierarchy_bitexact(H, O)
+    H32, _ = pair(rp, ci, v, vcycle_prec="fp32")
+    for seed in range(100, 110):
+        b = M.rhs_normal(n, seed)
+        x, info = H.solve(dev(b), 1e-8)
+        assert info["status"] == 0 and info["cache_event"] in (0, 1)
+        assert oracle.rel_residual(rp, ci, v, b, host(x)) <= 1e-8
+        x32, info32 = H32.solve(dev(b), 1e-8)
+        assert info32["status"] == 0 and oracle.rel_residual(rp, ci, v, b, host(x32)) <= 1e-8
+        if seed == 100:
+            xo, io = O.pcg(b, tol=1e-8)
+            print(f"[c3] gpu iters={info['iters']} fp32 iters={info32['iters']} oracle iters={io['iters']}",
+                  flush=True)
+            assert abs(info["iters"] - io["iters"]) <= 1
+
+
+def _c4_problem(N):
+    import oracle
+    theta = M.grf(N, 2, seed=41)
+    theta_true = M.grf(N, 2, seed=42)
+    rp, ci, vt = M.diffusion(np.exp(theta_true))
+    b = np.ones(N * N)
+    u_obs, _ = oracle.OracleHierarchy(rp, ci, vt).pcg(b, tol=1e-12)
+    return theta, rp, ci, b, u_obs
+
+
+def _gpu_grad(theta, rp, ci, b, u_obs, tol, **params):
+    from paper_2606_09001_amd.solver import amg_solve
+    th = torch.tensor(theta, device="cuda", requires_grad=True)
+    val = M.diffusion_values_torch(torch.exp(th))
+    x = amg_solve(dev(rp), dev(ci), val, dev(b), tol, **params)
+    loss = 0.5 * torch.sum((x - dev(u_obs)) ** 2)
+    loss.backward()
+    return float(loss), host(th.grad), host(x)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_512_vs_oracle_gradient(prec):
+    import oracle
+    N = 512
+    theta, rp, ci, b, u_obs = _c4_problem(N)
+    L, g, xg = _gpu_grad(theta, rp, ci, b, u_obs, 1e-10, vcycle_prec=prec)
+    k = np.exp(theta)
+    _, _, v = M.diffusion(k)
+    O = oracle.OracleHierarchy(rp, ci, v)
+    xo, _ = O.pcg(b, tol=1e-10)
+    lo, _ = O.solve_adjoint(xo - u_obs, tol=1e-10)
+    go = oracle.diffusion_theta_grad(k, rp, ci, O.pattern_grad(lo, xo))
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print(f"[c4 {prec}] loss={L:.6e} grad rel err vs oracle={rel:.3e}", flush=True)
+    assert rel <= 1e-5
+    # directional central differences of the oracle's loss (tol 1e-12)
+    for seed in (7, 8, 9):
+        d = np.random.default_rng(seed).standard_normal(theta.shape)
+        eps = 1e-4
+
+        def loss_at(th):
+            _, _, vv = M.diffusion(np.exp(th))
+            xx, _ = oracle.OracleHierarchy(rp, ci, vv).pcg(b, tol=1e-12)
+            return 0.5 * np.sum((xx - u_obs) ** 2)
+
+        fd = (loss_at(theta + eps * d) - loss_at(theta - eps * d)) / (2 * eps)
+        an = float(np.sum(g * d))
+        print(f"[c4 {prec}] direction {seed}: fd={fd:.10e} adjoint={an:.10e} rel={abs(fd - an) / abs(fd):.2e}",
+              flush=True)
+        assert abs(fd - an) <= 1e-5 * abs(fd)
+
+
+def test_adjoint_small_full_fd_gpu():
+    # every entry of theta on a small grid: GPU gradient vs central differences of GPU solves
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    N = 8
+    theta, rp, ci, b, u_obs = _c4_problem(N)
+    _, g, _ = _gpu_grad(theta, rp, ci, b, u_obs, 1e-13)
+    eps = 1e-5
+
+    def loss(th):
+        _, _, vv = M.diffusion(np.exp(th))
+        H = AmgHierarchy(dev(rp), dev(ci), dev(vv))
+        x, _ = H.solve(dev(b), 1e-13)
+        return 0.5 * float(np.sum((host(x) - u_obs) ** 2))
+
+    fd = np.zeros_like(theta)
+    for idx in np.ndindex(theta.shape):
+        tp, tm = theta.copy(), theta.copy()
+        tp[idx] += eps
+        tm[idx] -= eps
+        fd[idx] = (loss(tp) - loss(tm)) / (2 * eps)
+    assert np.max(np.abs(fd - g)) <= 1e-6 * np.abs(g).max()
+
+
+def test_autograd_rhs_gradient_is_lambda():
+    from paper_2606_09001_amd.solver import AmgHierarchy, amg_solve
+    rp, ci, v = M.diffusion(np.exp(M.grf(40, 2, seed=5)))
+    n = len(rp) - 1
+    bt = torch.tensor(M.rhs_normal(n, 1), device="cuda", requires_grad=True)
+    w = dev(M.rhs_normal(n, 2))
+    x = amg_solve(dev(rp), dev(ci), dev(v), bt, 1e-12)
+    (x * w).sum().backward()
+    H = AmgHierarchy(dev(rp), dev(ci), dev(v))
+    lam, _ = H.solve_adjoint(w, 1e-12)
+    assert torch.allclose(bt.grad, lam, rtol=1e-9, atol=1e-12)
