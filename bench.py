@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=512,
                     help="size of a plain device copy run once (PMC calibration of FETCH/WRITE_SIZE)")
+    ap.add_argument("--no-kernel-table", action="store_true",
+                    help="skip the per-kernel timing passes (used for counter-collection runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solve path is single-GPU "
@@ -91,12 +93,22 @@ def main():
     d_b = torch.from_numpy(b).to(dev)
     x = torch.empty_like(d_b)
 
-    # calibration copy for PMC byte counters (known size: read + write)
+    # plain device copy of known size: PMC byte-counter calibration and the
+    # on-box streaming ceiling (read + write bytes / time)
+    copy_gbs = None
     if args.calib_copy_mib > 0:
         src = torch.empty(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log(f"device copy {args.calib_copy_mib} MiB: {copy_gbs:.0f} GB/s (read+write)")
         del src, dst
 
     res = {}
@@ -147,6 +159,8 @@ def main():
     kernels = {}
     for name, lvl in (("spmv_dot", 0), ("pre", 0), ("post", 0), ("restrict", 0), ("prolong", 0),
                       ("cg_update", 0), ("pre", 1), ("post", 1), ("restrict", 1), ("prolong", 1)):
+        if args.no_kernel_table:
+            continue
         H.instrument(name, lvl)
         for _ in range(max(2, args.steps // 2)):
             H.solve(d_b, args.tol, out=x)
@@ -163,14 +177,16 @@ def main():
     for k, d in kernels.items():
         log(f"kernel {k}: avg {d['avg_us']:.1f} us, min {d['min_us']:.1f} us, "
             f"{d['bytes_per_launch'] / 1e6:.1f} MB -> {d['gbs_avg']:.0f} GB/s avg, {d['gbs_best']:.0f} best")
-    dom_name = max(("spmv_dot_L0", "pre_L0", "post_L0"), key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
-    dom = kernels[dom_name]
-    src_hash = kernel_source_hash()
-    traffic = traffic_from_profiles(f"poisson3d_{N}_{dom_name}", src_hash)
-    roofline = {"bound": "hbm", "achieved": round(dom["gbs_avg"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom["gbs_avg"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom_name,
-                "bytes_per_launch": dom["bytes_per_launch"], "avg_us": round(dom["avg_us"], 2),
-                "launches_timed": dom["launches"]}
+    roofline = None
+    if kernels:
+        dom_name = max(("spmv_dot_L0", "pre_L0", "post_L0"), key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
+        dom = kernels[dom_name]
+        src_hash = kernel_source_hash()
+        traffic = traffic_from_profiles(f"poisson3d_{N}_{dom_name}", src_hash)
+        roofline = {"bound": "hbm", "achieved": round(dom["gbs_avg"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(dom["gbs_avg"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom_name,
+                    "bytes_per_launch": dom["bytes_per_launch"], "avg_us": round(dom["avg_us"], 2),
+                    "launches_timed": dom["launches"], "copy_ceiling_gbs": round(copy_gbs, 1) if copy_gbs else None}
 
     cpu = None
     if not args.no_cpu_baseline:
