@@ -76,6 +76,10 @@ typedef struct {
   int flexible;        /* -1 (default): flexible beta iff the cycle is not FP64; 0 standard; 1 flexible */
   int symmetric;       /* 1 (default): A = A^T, the adjoint reuses A's hierarchy; 0 is rejected */
   int check_every;     /* PCG iterations queued between convergence checks (default 0 = automatic) */
+  int use_graphs;      /* 1 (default): replay HIP-graph captured iterations (on a library stream
+                          joined to the caller's stream by events); 0: launch every kernel */
+  int autotune;        /* 1: time candidate kernel shapes per matrix at setup and keep the fastest
+                          (cached across runs in $AMG_TUNE_CACHE if set); 0 (default): row-length rule */
 } amg_params;
 
 typedef struct {
@@ -138,7 +142,10 @@ void amg_params_default(amg_params* p);
  * hierarchy is returned.  Hit with new values: the values are refreshed in
  * place (aggregates and all patterns kept).  The handle holds one reference
  * (release with amg_destroy); the cache holds another.
- * n_systems must be 1.  *out is written only on success. */
+ * n_systems = S >= 1 (at most 64): S systems share the pattern and d_val
+ * holds their values interleaved, entry k of system s at [k*S + s]; the
+ * aggregation is pattern-only (theta must be 0) and each system gets its own
+ * numeric hierarchy.  *out is written only on success. */
 amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
                      const int32_t* d_col, const double* d_val, int32_t n_systems, hipStream_t stream,
                      amg_handle* out);
@@ -147,8 +154,13 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
  * from d_val (nnz entries) and keeps aggregates and patterns. */
 amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stream);
 
-/* PCG solve A X = B from X0 = 0 for nrhs >= 1 columns (row-major blocks),
- * preconditioned by one V-cycle per iteration.  Stops when
+/* PCG solve A X = B from X0 = 0 for nrhs >= 1 columns (row-major blocks,
+ * nrhs <= 64), preconditioned by one V-cycle per iteration.  With n_systems
+ * S > 1, nrhs must equal S and column s is solved with system s.  Columns are
+ * independent CG iterations run in one batched launch per step (not block
+ * CG); converged columns are frozen.  Batched solves need at least two
+ * levels and V(1,1); info reports the maximum iteration count and residual
+ * over the columns and the worst status (see amg_solve_columns).  Stops when
  * ||r||_2 <= tol ||b||_2 for the recursive residual, then verifies the true
  * residual in FP64 and restarts from it (at most 5 times) if it misses.
  * tol = 0 runs exactly params.maxiter iterations.  info may be null. */
@@ -161,10 +173,22 @@ amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, i
 amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, double tol, int32_t nrhs,
                              amg_info* info, hipStream_t stream);
 
+/* Per-column outcome of the handle's last batched solve (ncols = its width):
+ * iterations, true relative residual and status of every column. */
+amg_status amg_solve_columns(amg_handle h, int32_t ncols, int* iters, double* rel_resid, int* status);
+
 /* Pattern gradient (Eq. (2)): grad_val[k] = -(lambda[row k] * x[col k]) for
  * every stored entry k of the level-0 matrix; dL/db is lambda itself. */
 amg_status amg_pattern_grad(amg_handle h, const double* d_lambda, const double* d_x, double* d_grad_val,
                             hipStream_t stream);
+
+/* Batched pattern gradient for ncols columns ([n][ncols] lambda and x):
+ * with S systems, grad_val is [nnz][S] (per system); with one matrix and
+ * ncols right-hand sides, grad_val[k] sums -(lambda_c[row k] x_c[col k]) over
+ * the columns in ascending order (the gradient with respect to the shared
+ * values of a loss over all columns). */
+amg_status amg_pattern_grad_batched(amg_handle h, const double* d_lambda, const double* d_x, int32_t ncols,
+                                    double* d_grad_val, hipStream_t stream);
 
 /* One V-cycle z = M^-1 r on the fine level (FP64 in and out, the handle's
  * cycle precision inside): the preconditioner as an operator. */

@@ -37,7 +37,7 @@ EXPORTS = [
     "amg_params_default", "amg_setup", "amg_update_values", "amg_solve", "amg_solve_adjoint", "amg_pattern_grad",
     "amg_apply_vcycle", "amg_hierarchy_stats", "amg_field_info", "amg_export_field", "amg_destroy", "amg_finalize",
     "amg_cache_size", "amg_set_cache_capacity", "amg_status_string", "amg_instrument", "amg_instrument_read",
-    "amg_kernel_bytes",
+    "amg_kernel_bytes", "amg_pattern_grad_batched", "amg_solve_columns",
 ]
 
 KERNELS = {"spmv_dot": 0, "pre": 1, "post": 2, "restrict": 3, "prolong": 4, "cg_update": 5, "xpay": 6, "coarse": 7}
@@ -48,7 +48,7 @@ class amg_params(C.Structure):
         ("vcycle_prec", C.c_int), ("transfer_bf16", C.c_int), ("theta", C.c_double), ("max_coarse", C.c_int),
         ("max_levels", C.c_int), ("smoother", C.c_int), ("omega", C.c_double), ("nu_pre", C.c_int),
         ("nu_post", C.c_int), ("maxiter", C.c_int), ("flexible", C.c_int), ("symmetric", C.c_int),
-        ("check_every", C.c_int),
+        ("check_every", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int),
     ]
 
 
@@ -114,6 +114,8 @@ def load():
     L.amg_instrument.argtypes = [vp, C.c_int, C.c_int]
     L.amg_instrument_read.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
     L.amg_kernel_bytes.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(dbl)]
+    L.amg_pattern_grad_batched.argtypes = [vp, vp, vp, i32, vp, vp]
+    L.amg_solve_columns.argtypes = [vp, i32, vp, vp, vp]
     L.amg_status_string.argtypes = [C.c_int]
     L.amg_status_string.restype = C.c_char_p
     for name in EXPORTS:

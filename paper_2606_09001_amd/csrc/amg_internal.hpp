@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -88,7 +89,8 @@ struct Level {
   DBuf<int> agg;
   int nagg = 0;
   int mis_rounds = 0;
-  double rho = 0.0, omegaP = 0.0;
+  double rho = 0.0, omegaP = 0.0;            // system 0
+  std::vector<double> rhoS, omegaPS;         // per system
   // prolongator / restriction
   int64_t pnnz = 0;
   DBuf<int> prp, pci, rrp, rci, rperm;
@@ -143,9 +145,56 @@ struct Instr {
   int used = 0;
 };
 
+// Batched solves: W columns (right-hand sides of one matrix, or systems
+// sharing a pattern), each an independent CG with its own scalars.
+struct WCtl {
+  double bb, thresh, rz, pq, rr, alpha, beta, trr, zq;
+  int iters, state, done, first, restarts, pad_;
+};
+struct BatchHead {
+  int ndone;     // columns finished (converged, iteration limit or breakdown)
+  int W;
+  int maxiter;
+  int flexible;
+};
+struct BatchLevel {
+  DBuf<double> x64, b64, r64;
+  DBuf<float> x32, b32, r32;
+};
+struct Batch {
+  int W = 0;
+  DBuf<double> r, z, p, p2, q, partials;
+  DBuf<WCtl> ctl;
+  DBuf<BatchHead> head;
+  DBuf<int> mask;
+  WCtl* h_ctl = nullptr;
+  BatchHead* h_head = nullptr;
+  int* h_mask = nullptr;
+  std::vector<BatchLevel> lv;
+  std::vector<int> col_iters, col_status;
+  std::vector<double> col_relres;
+};
+
+// Captured PCG iterations.  Graph solves run on a library stream joined to
+// the caller's stream by events (the caller's stream may be the legacy
+// default stream, which cannot be captured).
+struct Graphs {
+  hipStream_t gs = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};   // pair of iterations, by direction-buffer parity
+  const void* key_x = nullptr;
+  int key_flex = -1;
+  int key_w = 0;
+  void reset();
+  ~Graphs();
+};
+
 struct Hierarchy {
   amg_params prm{};
   Instr inst;
+  Batch bt;
+  Graphs gr;
+  int S = 1;   // systems sharing the pattern (values interleaved [nnz][S])
   int n = 0;
   int64_t nnz = 0;
   std::vector<Level> lv;
@@ -173,6 +222,7 @@ struct SolveOpts {
   int maxiter;
   int flexible;     // -1 auto
   int check_every;  // 0 auto
+  int use_graphs;   // replay captured iterations
 };
 
 // setup.hip
@@ -191,7 +241,13 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
                      amg_info* info, hipStream_t s);
 void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s);
 void pattern_grad(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, hipStream_t s);
-void choose_shapes(Hierarchy& H);
+void graph_stream(Hierarchy& H);
+void capture_graph(hipStream_t s, hipGraphExec_t& ex, const std::function<void()>& body);
+// batch.hip
+amg_status pcg_solve_wide(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int W,
+                          amg_info* info, hipStream_t s);
+void pattern_grad_wide(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, int W, hipStream_t s);
+void choose_shapes(Hierarchy& H, hipStream_t s);
 double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible);
 double iteration_bytes(const Hierarchy& H, int flexible);
 void set_instrument(Hierarchy& H, int kid, int level);
@@ -204,6 +260,7 @@ constexpr int kMaxGrid = 2048;     // blocks of grid-stride kernels
 constexpr int kStreamCap = 2048;   // nonzeros a stream workgroup stages in LDS
 constexpr int kVecPer = 4;         // vector elements per thread in BLAS1 kernels
 constexpr int kFinBlock = 1024;    // threads of the single-workgroup finalize kernels
+constexpr int kMaxWidth = 64;      // columns of a batched solve (right-hand sides or systems)
 
 __host__ __device__ inline int pow2_ceil(int x) {
   int g = 1;

@@ -1,0 +1,852 @@
+// Batched solves: W columns in one launch per step, vectors stored row-major
+// [n][W].  Two forms share every kernel:
+//   - many right-hand sides of one matrix (SYS = false): matrix values,
+//     smoother weights and the coarse inverse are shared by all columns;
+//   - many systems with one sparsity pattern (SYS = true, W = S): value
+//     arrays are interleaved [entry][S], so column c reads its own values.
+// Each column is an independent PCG (its own alpha, beta, convergence and
+// restarts; converged columns are frozen), not block CG.
+//
+// Wide sweep kernel: a group of LW = 2^ceil(log2 W) lanes per row, lane =
+// column; every lane of the group reads the row's column indices (one
+// broadcast transaction), the gathers x[j][0..W) are contiguous, so each
+// nonzero costs one coalesced W-wide access.  Column-wise dot products are
+// reduced per workgroup in a fixed order and folded by a finalize kernel with
+// one workgroup per column.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "amg_internal.hpp"
+
+namespace amg {
+namespace {
+
+constexpr int kWGrid = 2048;  // workgroups of the wide sweeps (partials per column)
+constexpr int kWFin = 256;    // threads per finalize workgroup (one workgroup per column)
+
+__device__ inline int logical_block_w() {
+  const int g = gridDim.x;
+  if ((g & 7) == 0) return (blockIdx.x & 7) * (g >> 3) + (blockIdx.x >> 3);
+  return blockIdx.x;
+}
+
+inline int wide_grid(int64_t n, int LW) {
+  const int64_t rb = kBlock / LW;
+  int64_t g = std::min<int64_t>((n + rb - 1) / rb, kWGrid);
+  if (g >= 64) g = g / 8 * 8;
+  return (int)std::max<int64_t>(g, 1);
+}
+
+// Value of stored entry k for column c.
+template <bool SYS, class V>
+__device__ inline V val_at(const V* v, int k, int c, int W) {
+  if constexpr (SYS) return v[(int64_t)k * W + c];
+  else return v[k];
+}
+// Per-row quantity (smoother weight) for column c.
+template <bool SYS, class V>
+__device__ inline V row_at(const V* v, int i, int c, int W) {
+  if constexpr (SYS) return v[(int64_t)i * W + c];
+  else return v[i];
+}
+
+// ----------------------------------------------------------- operators
+
+// r = b - A x  (x = sw o b written by the producer of b)
+template <bool SYS, class T, class BT>
+struct WResid {
+  using PT = T;
+  static constexpr int NRED = 0;
+  const T* v;
+  const BT* b;
+  const T* x;
+  T* r;
+  int W;
+  __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
+  __device__ void epi(int row, int c, PT s, double*) const {
+    const int64_t e = (int64_t)row * W + c;
+    r[e] = (T)b[e] - s;
+  }
+};
+
+// y = R x ; xc = swc o y
+template <bool SYS, class RT, class T>
+struct WRestrict {
+  using PT = T;
+  static constexpr int NRED = 0;
+  const RT* v;
+  const T* x;
+  T* y;
+  const T* swc;
+  T* xc;
+  int W;
+  __device__ PT prod(int k, int j, int c) const {
+    return (T)ValCvt<RT>::f(val_at<SYS>(v, k, c, W)) * x[(int64_t)j * W + c];
+  }
+  __device__ void epi(int row, int c, PT s, double*) const {
+    const int64_t e = (int64_t)row * W + c;
+    y[e] = s;
+    if (xc) xc[e] = row_at<SYS>(swc, row, c, W) * s;
+  }
+};
+
+// x += P xc
+template <bool SYS, class RT, class T>
+struct WProlong {
+  using PT = T;
+  static constexpr int NRED = 0;
+  const RT* v;
+  const T* xc;
+  T* x;
+  int W;
+  __device__ PT prod(int k, int j, int c) const {
+    return (T)ValCvt<RT>::f(val_at<SYS>(v, k, c, W)) * xc[(int64_t)j * W + c];
+  }
+  __device__ void epi(int row, int c, PT s, double*) const {
+    const int64_t e = (int64_t)row * W + c;
+    x[e] = x[e] + s;
+  }
+};
+
+// out = x + sw o (b - A x); RED >= 1: <b, out>, RED == 2: <out, q> per column
+template <bool SYS, class T, class BT, class OT, int RED>
+struct WPost {
+  using PT = T;
+  static constexpr int NRED = RED;
+  const T* v;
+  const T* sw;
+  const BT* b;
+  const T* x;
+  OT* out;
+  const double* q;
+  int W;
+  __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
+  __device__ void epi(int row, int c, PT s, double* d) const {
+    const int64_t e = (int64_t)row * W + c;
+    const T bi = (T)b[e];
+    const T o = x[e] + row_at<SYS>(sw, row, c, W) * (bi - s);
+    const OT oo = (OT)o;
+    out[e] = oo;
+    if constexpr (RED >= 1) d[0] += (double)b[e] * (double)oo;
+    if constexpr (RED >= 2) d[1] += (double)oo * q[e];
+  }
+};
+
+// p' = z + beta_c p (p' = z for columns starting a (re)start), q = A p', <p', q>
+template <bool SYS>
+struct WSpmvXpay {
+  using PT = double;
+  static constexpr int NRED = 1;
+  const double* v;
+  const double* z;
+  const double* p;
+  double* pn;
+  double* q;
+  const WCtl* ctl;
+  int W;
+  __device__ double dir(int64_t e, int c) const {
+    const WCtl& cc = ctl[c];
+    return cc.first ? z[e] : z[e] + cc.beta * p[e];
+  }
+  __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * dir((int64_t)j * W + c, c); }
+  __device__ void epi(int row, int c, PT s, double* d) const {
+    const int64_t e = (int64_t)row * W + c;
+    const double pr = dir(e, c);
+    pn[e] = pr;
+    q[e] = s;
+    d[0] += pr * s;
+  }
+};
+
+// r = b - A x, ||r||^2 per column
+template <bool SYS>
+struct WTrueResid {
+  using PT = double;
+  static constexpr int NRED = 1;
+  const double* v;
+  const double* x;
+  const double* b;
+  double* r;
+  int W;
+  __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
+  __device__ void epi(int row, int c, PT s, double* d) const {
+    const int64_t e = (int64_t)row * W + c;
+    const double ri = b[e] - s;
+    r[e] = ri;
+    d[0] += ri * ri;
+  }
+};
+
+// Column-wise partial sums of one workgroup, folded over its rows in a
+// fixed order: partials[(m*W + c)*gridDim + block].
+template <int LW, int NRED>
+__device__ inline void publish_w(double (&d)[NRED > 0 ? NRED : 1], int W, double* partials) {
+  if constexpr (NRED > 0) {
+    constexpr int RB = kBlock / LW;
+    __shared__ double red[NRED][kBlock];
+#pragma unroll
+    for (int m = 0; m < NRED; ++m) red[m][threadIdx.x] = d[m];
+    __syncthreads();
+    if (threadIdx.x < LW && (int)threadIdx.x < W) {
+      const int c = threadIdx.x;
+#pragma unroll
+      for (int m = 0; m < NRED; ++m) {
+        double s = 0.0;
+        for (int r = 0; r < RB; ++r) s += red[m][r * LW + c];
+        partials[((int64_t)m * W + c) * gridDim.x + blockIdx.x] = s;
+      }
+    }
+  }
+}
+
+template <int LW, class Op>
+__global__ void __launch_bounds__(kBlock) k_wide(int n, int W, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci, Op op,
+                                                 const BatchHead* __restrict__ head, double* __restrict__ partials) {
+  if (head && head->ndone >= head->W) return;
+  using PT = typename Op::PT;
+  constexpr int RB = kBlock / LW;
+  constexpr int U = 8;
+  const int lr = threadIdx.x / LW, c = threadIdx.x & (LW - 1);
+  const int64_t groups = ((int64_t)n + RB - 1) / RB;
+  const int lb = logical_block_w();
+  const int g0 = (int)(groups * lb / gridDim.x), g1 = (int)(groups * (lb + 1) / gridDim.x);
+  double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * RB + lr;
+    PT s = 0;
+    if (row < n && c < W) {
+      const int k0 = rp[row], k1 = rp[row + 1];
+      for (int kb = k0; kb < k1; kb += U) {
+        int cols[U];
+#pragma unroll
+        for (int e = 0; e < U; ++e) cols[e] = kb + e < k1 ? ci[kb + e] : -1;
+        PT pr[U];
+#pragma unroll
+        for (int e = 0; e < U; ++e) pr[e] = cols[e] >= 0 ? op.prod(kb + e, cols[e], c) : (PT)0;
+#pragma unroll
+        for (int e = 0; e < U; ++e)
+          if (cols[e] >= 0) s += pr[e];
+      }
+      op.epi(row, c, s, d);
+    }
+  }
+  publish_w<LW, Op::NRED>(d, W, partials);
+}
+
+// ------------------------------------------------- elementwise (FP64 CG)
+
+// r = b, x = 0, <b, b> per column
+template <int LW>
+__global__ void __launch_bounds__(kBlock) k_winit(int n, int W, const double* __restrict__ b, double* __restrict__ r,
+                                                  double* __restrict__ x, double* __restrict__ partials) {
+  constexpr int RB = kBlock / LW;
+  const int lr = threadIdx.x / LW, c = threadIdx.x & (LW - 1);
+  const int64_t groups = ((int64_t)n + RB - 1) / RB;
+  const int lb = logical_block_w();
+  const int g0 = (int)(groups * lb / gridDim.x), g1 = (int)(groups * (lb + 1) / gridDim.x);
+  double d[1] = {0.0};
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * RB + lr;
+    if (row < n && c < W) {
+      const int64_t e = (int64_t)row * W + c;
+      const double bi = b[e];
+      r[e] = bi;
+      x[e] = 0.0;
+      d[0] += bi * bi;
+    }
+  }
+  publish_w<LW, 1>(d, W, partials);
+}
+
+// Active columns: x += alpha p, r -= alpha q, x0 = sw o r, <r, r>.
+template <int LW, bool SYS, class T>
+__global__ void __launch_bounds__(kBlock) k_wupdate(int n, int W, double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const T* __restrict__ sw, T* __restrict__ x0,
+                                                    const WCtl* __restrict__ ctl, const BatchHead* __restrict__ head,
+                                                    double* __restrict__ partials) {
+  if (head->ndone >= head->W) return;
+  constexpr int RB = kBlock / LW;
+  const int lr = threadIdx.x / LW, c = threadIdx.x & (LW - 1);
+  const int64_t groups = ((int64_t)n + RB - 1) / RB;
+  const int lb = logical_block_w();
+  const int g0 = (int)(groups * lb / gridDim.x), g1 = (int)(groups * (lb + 1) / gridDim.x);
+  const bool act = c < W && !ctl[c < W ? c : 0].done;
+  const double alpha = c < W ? ctl[c].alpha : 0.0;
+  double d[1] = {0.0};
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * RB + lr;
+    if (row < n && act) {
+      const int64_t e = (int64_t)row * W + c;
+      x[e] = x[e] + alpha * p[e];
+      const double ri = r[e] - alpha * q[e];
+      r[e] = ri;
+      x0[e] = row_at<SYS>(sw, row, c, W) * (T)ri;
+      d[0] += ri * ri;
+    }
+  }
+  publish_w<LW, 1>(d, W, partials);
+}
+
+// x0 = sw o r (start of a solve or restart)
+template <int LW, bool SYS, class T>
+__global__ void __launch_bounds__(kBlock) k_wswmul(int n, int W, const T* __restrict__ sw,
+                                                   const double* __restrict__ r, T* __restrict__ x0) {
+  constexpr int RB = kBlock / LW;
+  const int lr = threadIdx.x / LW, c = threadIdx.x & (LW - 1);
+  const int64_t groups = ((int64_t)n + RB - 1) / RB;
+  const int lb = logical_block_w();
+  const int g0 = (int)(groups * lb / gridDim.x), g1 = (int)(groups * (lb + 1) / gridDim.x);
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * RB + lr;
+    if (row < n && c < W) {
+      const int64_t e = (int64_t)row * W + c;
+      x0[e] = row_at<SYS>(sw, row, c, W) * (T)r[e];
+    }
+  }
+}
+
+// Dense coarsest solve per column: x[i][c] = sum_j inv_c[j][i] b[j][c].
+template <bool SYS, class T>
+__global__ void __launch_bounds__(kBlock) k_wcoarse(int n, int m, int W, const T* __restrict__ inv,
+                                                    const T* __restrict__ b, T* __restrict__ x,
+                                                    const BatchHead* __restrict__ head) {
+  if (head && head->ndone >= head->W) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * W) return;
+  const int i = (int)(t / W), c = (int)(t % W);
+  const T* iv = inv + (SYS ? (int64_t)c * m * m : 0);
+  T s = 0;
+  for (int j = 0; j < n; ++j) s += iv[(int64_t)j * m + i] * b[(int64_t)j * W + c];
+  x[t] = s;
+}
+
+// ----------------------------------------------------- finalize (per column)
+
+template <int NV>
+__device__ inline void wfold(const double* __restrict__ partials, int W, int np, int c, double (&tot)[NV]) {
+  __shared__ double red[NV][kWFin / 64];
+  double acc[NV];
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    const double* src = partials + ((int64_t)m * W + c) * np;
+    double s = 0.0;
+    for (int b0 = 0; b0 < np; b0 += kWFin * 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + threadIdx.x + u * kWFin;
+        t[u] = b < np ? src[b] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    acc[m] = wave_sum(s);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) red[m][w] = acc[m];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      double s = red[m][0];
+      for (int k = 1; k < kWFin / 64; ++k) s += red[m][k];
+      tot[m] = s;
+    }
+  }
+}
+
+__device__ inline void finish_column(WCtl& cc, BatchHead* head, int state) {
+  cc.state = state;
+  cc.done = 1;
+  atomicAdd(&head->ndone, 1);
+}
+
+__global__ void k_whead_reset(BatchHead* head, int W, int maxiter, int flexible) {
+  head->ndone = 0;
+  head->W = W;
+  head->maxiter = maxiter;
+  head->flexible = flexible;
+}
+
+__global__ void __launch_bounds__(kWFin) k_wfin_init(WCtl* ctl, BatchHead* head, const double* __restrict__ partials,
+                                                     int W, int np, double tol) {
+  const int c = blockIdx.x;
+  double t[1];
+  wfold<1>(partials, W, np, c, t);
+  if (threadIdx.x != 0) return;
+  WCtl& cc = ctl[c];
+  const double bb = t[0];
+  cc.bb = bb;
+  cc.thresh = (tol * tol) * bb;
+  cc.iters = 0;
+  cc.state = 0;
+  cc.done = 0;
+  cc.first = 1;
+  cc.restarts = 0;
+  cc.trr = 0.0;
+  cc.rr = bb;
+  cc.beta = 0.0;
+  if (bb == 0.0) finish_column(cc, head, 3);
+  else if (!(bb == bb)) finish_column(cc, head, -1);
+  else if (head->maxiter <= 0) finish_column(cc, head, 2);
+}
+
+__global__ void __launch_bounds__(kWFin) k_wfin_alpha(WCtl* ctl, BatchHead* head, const double* __restrict__ partials,
+                                                      int W, int np) {
+  if (head->ndone >= head->W) return;
+  const int c = blockIdx.x;
+  if (ctl[c].done) return;
+  double t[1];
+  wfold<1>(partials, W, np, c, t);
+  if (threadIdx.x != 0) return;
+  WCtl& cc = ctl[c];
+  const double pq = t[0];
+  cc.pq = pq;
+  cc.first = 0;
+  if (!(pq > 0.0)) finish_column(cc, head, -1);
+  else cc.alpha = cc.rz / pq;
+}
+
+__global__ void __launch_bounds__(kWFin) k_wfin_update(WCtl* ctl, BatchHead* head,
+                                                       const double* __restrict__ partials, int W, int np) {
+  if (head->ndone >= head->W) return;
+  const int c = blockIdx.x;
+  if (ctl[c].done) return;
+  double t[1];
+  wfold<1>(partials, W, np, c, t);
+  if (threadIdx.x != 0) return;
+  WCtl& cc = ctl[c];
+  const double rr = t[0];
+  cc.rr = rr;
+  cc.iters += 1;
+  if (rr <= cc.thresh) finish_column(cc, head, 1);
+  else if (!(rr == rr)) finish_column(cc, head, -1);
+  else if (cc.iters >= head->maxiter) finish_column(cc, head, 2);
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kWFin) k_wfin_beta(WCtl* ctl, BatchHead* head, const double* __restrict__ partials,
+                                                     int W, int np) {
+  if (head->ndone >= head->W) return;
+  const int c = blockIdx.x;
+  if (ctl[c].done) return;
+  double t[NV];
+  wfold<NV>(partials, W, np, c, t);
+  if (threadIdx.x != 0) return;
+  WCtl& cc = ctl[c];
+  const double rzn = t[0];
+  const double zq = NV > 1 ? t[NV - 1] : 0.0;
+  if (cc.first) cc.beta = 0.0;
+  else if (head->flexible) cc.beta = -zq / cc.pq;
+  else cc.beta = rzn / cc.rz;
+  cc.rz = rzn;
+  cc.zq = zq;
+  if (!(rzn > 0.0)) finish_column(cc, head, -1);
+}
+
+__global__ void __launch_bounds__(kWFin) k_wfin_trr(WCtl* ctl, const double* __restrict__ partials, int W, int np) {
+  const int c = blockIdx.x;
+  double t[1];
+  wfold<1>(partials, W, np, c, t);
+  if (threadIdx.x == 0) ctl[c].trr = t[0];
+}
+
+// Columns flagged in mask restart from their true residual.
+__global__ void k_wrestart(WCtl* ctl, BatchHead* head, const int* __restrict__ mask, int W) {
+  int nre = 0;
+  for (int c = 0; c < W; ++c)
+    if (mask[c]) {
+      ctl[c].done = 0;
+      ctl[c].state = 0;
+      ctl[c].first = 1;
+      ctl[c].restarts += 1;
+      ++nre;
+    }
+  head->ndone -= nre;
+}
+
+// Pattern gradients: systems -> per system; right-hand sides -> summed over
+// columns in ascending order (the gradient of a loss over all columns with
+// respect to the shared values).
+template <bool SYS>
+__global__ void __launch_bounds__(kBlock) k_wpattern_grad(int n, int W, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci, const double* __restrict__ lam,
+                                                          const double* __restrict__ x, double* __restrict__ g) {
+  const int row = blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  for (int k = rp[row]; k < rp[row + 1]; ++k) {
+    const int j = ci[k];
+    if constexpr (SYS) {
+      for (int c = lane; c < W; c += 64)
+        g[(int64_t)k * W + c] = -(lam[(int64_t)row * W + c] * x[(int64_t)j * W + c]);
+    } else {
+      if (lane == 0) {
+        double s = 0.0;
+        for (int c = 0; c < W; ++c) s += -(lam[(int64_t)row * W + c] * x[(int64_t)j * W + c]);
+        g[k] = s;
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- dispatch
+
+#define AMG_DISPATCH_LW(lw, ...)                            \
+  switch (lw) {                                             \
+    case 1: { constexpr int LW = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int LW = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int LW = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int LW = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int LW = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int LW = 32; __VA_ARGS__; } break; \
+    default: { constexpr int LW = 64; __VA_ARGS__; } break; \
+  }
+
+template <class Op>
+int wsweep(int LWv, int n, int W, const int* rp, const int* ci, const Op& op, const BatchHead* head,
+           double* partials, hipStream_t s) {
+  const int grid = wide_grid(n, LWv);
+  AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, rp, ci, op, head,
+                                          partials));
+  return grid;
+}
+
+template <class T>
+struct WB;
+template <>
+struct WB<double> {
+  static double* x(BatchLevel& B) { return B.x64.p; }
+  static double* b(BatchLevel& B) { return B.b64.p; }
+  static double* r(BatchLevel& B) { return B.r64.p; }
+  static const double* v(Level& L) { return L.v.p; }
+  static const double* sw(Level& L) { return L.sw.p; }
+  static const double* inv(Coarse& C) { return C.inv.p; }
+};
+template <>
+struct WB<float> {
+  static float* x(BatchLevel& B) { return B.x32.p; }
+  static float* b(BatchLevel& B) { return B.b32.p; }
+  static float* r(BatchLevel& B) { return B.r32.p; }
+  static const float* v(Level& L) { return L.v32.p; }
+  static const float* sw(Level& L) { return L.sw32.p; }
+  static const float* inv(Coarse& C) { return C.inv32.p; }
+};
+
+template <bool SYS, class T>
+void w_restrict(Hierarchy& H, Level& L, int LWv, int W, const T* r, T* bc, const T* swc, T* xc, hipStream_t s) {
+  const BatchHead* hd = H.bt.head.p;
+  if constexpr (std::is_same<T, double>::value) {
+    wsweep(LWv, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, double, T>{L.rv.p, r, bc, swc, xc, W}, hd, nullptr, s);
+  } else if (H.bf16()) {
+    wsweep(LWv, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, uint16_t, T>{L.rbf.p, r, bc, swc, xc, W}, hd, nullptr,
+           s);
+  } else {
+    wsweep(LWv, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, float, T>{L.rv32.p, r, bc, swc, xc, W}, hd, nullptr, s);
+  }
+}
+
+template <bool SYS, class T>
+void w_prolong(Hierarchy& H, Level& L, int LWv, int W, const T* xc, T* x, hipStream_t s) {
+  const BatchHead* hd = H.bt.head.p;
+  if constexpr (std::is_same<T, double>::value) {
+    wsweep(LWv, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, double, T>{L.pv.p, xc, x, W}, hd, nullptr, s);
+  } else if (H.bf16()) {
+    wsweep(LWv, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, uint16_t, T>{L.pbf.p, xc, x, W}, hd, nullptr, s);
+  } else {
+    wsweep(LWv, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, float, T>{L.pv32.p, xc, x, W}, hd, nullptr, s);
+  }
+}
+
+// One batched V(1,1) cycle: level-0 rhs r0 [n][W] (FP64) -> z0 (FP64), with
+// the level-0 pre-smoothed iterate already written; red = 1 or 2 emits the
+// per-column <r,z> (and <z,q>) partials and the beta finalize.
+template <bool SYS, class T>
+void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q, int red, hipStream_t s) {
+  Batch& B = H.bt;
+  const int LWv = pow2_ceil(W);
+  const int nl = (int)H.lv.size();
+  const BatchHead* hd = B.head.p;
+  double* part = B.partials.p;
+  Coarse& C = H.co;
+  for (int l = 0; l < nl - 1; ++l) {
+    Level& L = H.lv[l];
+    BatchLevel& BL = B.lv[l];
+    if (l == 0)
+      wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, double>{WB<T>::v(L), r0, WB<T>::x(BL), WB<T>::r(BL), W}, hd,
+             nullptr, s);
+    else
+      wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W},
+             hd, nullptr, s);
+    Level& Ln = H.lv[l + 1];
+    BatchLevel& BN = B.lv[l + 1];
+    const bool coarsest = (l + 1 == nl - 1);
+    w_restrict<SYS, T>(H, L, LWv, W, WB<T>::r(BL), WB<T>::b(BN), coarsest ? nullptr : WB<T>::sw(Ln),
+                       coarsest ? nullptr : WB<T>::x(BN), s);
+  }
+  {
+    BatchLevel& BC = B.lv[nl - 1];
+    const int64_t nt = (int64_t)C.n * W;
+    hipLaunchKernelGGL((k_wcoarse<SYS, T>), dim3((int)((nt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, C.n, C.m,
+                       W, WB<T>::inv(C), WB<T>::b(BC), WB<T>::x(BC), hd);
+  }
+  T* res = WB<T>::x(B.lv[nl - 1]);
+  for (int l = nl - 2; l >= 0; --l) {
+    Level& L = H.lv[l];
+    BatchLevel& BL = B.lv[l];
+    w_prolong<SYS, T>(H, L, LWv, W, res, WB<T>::x(BL), s);
+    const T* vv = WB<T>::v(L);
+    const T* sw = WB<T>::sw(L);
+    if (l == 0) {
+      int np = 0;
+      if (red == 2)
+        np = wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 2>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
+                    hd, part, s);
+      else if (red == 1)
+        np = wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 1>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
+                    hd, part, s);
+      else
+        wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 0>{vv, sw, r0, WB<T>::x(BL), z0, q, W}, hd,
+               nullptr, s);
+      if (red == 2)
+        hipLaunchKernelGGL(k_wfin_beta<2>, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, np);
+      else if (red == 1)
+        hipLaunchKernelGGL(k_wfin_beta<1>, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, np);
+    } else {
+      wsweep(LWv, L.n, W, L.rp.p, L.ci.p,
+             WPost<SYS, T, T, T, 0>{vv, sw, WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), nullptr, W}, hd, nullptr, s);
+      res = WB<T>::r(BL);
+    }
+  }
+  AMG_HIP(hipGetLastError());
+}
+
+void ensure_batch(Hierarchy& H, int W) {
+  Batch& B = H.bt;
+  if (B.W == W && B.ctl.p) return;
+  const int64_t n = H.n;
+  B.r.alloc(n * W);
+  B.z.alloc(n * W);
+  B.p.alloc(n * W);
+  B.p2.alloc(n * W);
+  B.q.alloc(n * W);
+  B.partials.alloc((int64_t)2 * W * kWGrid + 64);
+  B.ctl.alloc(W);
+  B.head.alloc(1);
+  B.mask.alloc(W);
+  if (B.h_ctl) AMG_HIP(hipHostFree(B.h_ctl));
+  if (!B.h_head) AMG_HIP(hipHostMalloc((void**)&B.h_head, sizeof(BatchHead), hipHostMallocDefault));
+  if (B.h_mask) AMG_HIP(hipHostFree(B.h_mask));
+  AMG_HIP(hipHostMalloc((void**)&B.h_ctl, sizeof(WCtl) * W, hipHostMallocDefault));
+  AMG_HIP(hipHostMalloc((void**)&B.h_mask, sizeof(int) * W, hipHostMallocDefault));
+  AMG_HIP(hipMemset(B.ctl.p, 0, sizeof(WCtl) * W));
+  B.lv.clear();
+  B.lv.resize(H.lv.size());
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    const int64_t nl = (int64_t)H.lv[l].n * W;
+    if (H.fp32()) {
+      B.lv[l].x32.alloc(nl);
+      B.lv[l].b32.alloc(nl);
+      B.lv[l].r32.alloc(nl);
+    } else {
+      B.lv[l].x64.alloc(nl);
+      B.lv[l].b64.alloc(nl);
+      B.lv[l].r64.alloc(nl);
+    }
+  }
+  B.W = W;
+}
+
+void read_batch(Hierarchy& H, int W, hipStream_t s) {
+  AMG_HIP(hipMemcpyAsync(H.bt.h_head, H.bt.head.p, sizeof(BatchHead), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipMemcpyAsync(H.bt.h_ctl, H.bt.ctl.p, sizeof(WCtl) * W, hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+template <bool SYS, class T>
+amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int W,
+                           amg_info* info, hipStream_t caller) {
+  auto t0 = std::chrono::steady_clock::now();
+  ensure_batch(H, W);
+  Batch& B = H.bt;
+  Level& L0 = H.lv[0];
+  const int n = H.n;
+  const int LWv = pow2_ceil(W);
+  const bool multi = H.lv.size() > 1;
+  const int flexible = o.flexible < 0 ? (H.fp32() ? 1 : 0) : o.flexible;
+  if (!multi) throw Error(AMG_ERR_INVALID_ARG, "batched solves need at least two levels");
+  const bool graphs = o.use_graphs != 0;
+  hipStream_t s = caller;
+  if (graphs) {
+    graph_stream(H);
+    AMG_HIP(hipEventRecord(H.gr.ev_in, caller));
+    AMG_HIP(hipStreamWaitEvent(H.gr.gs, H.gr.ev_in, 0));
+    s = H.gr.gs;
+    if (H.gr.key_x != d_x || H.gr.key_flex != flexible || H.gr.key_w != W) {
+      H.gr.reset();
+      H.gr.key_x = d_x;
+      H.gr.key_flex = flexible;
+      H.gr.key_w = W;
+    }
+  }
+  double* part = B.partials.p;
+  const int gw = wide_grid(n, LWv);
+  hipLaunchKernelGGL(k_whead_reset, dim3(1), dim3(1), 0, s, B.head.p, W, o.maxiter, flexible);
+  AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_winit<LW>), dim3(gw), dim3(kBlock), 0, s, n, W, d_b, B.r.p, d_x, part));
+  hipLaunchKernelGGL(k_wfin_init, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, gw, tol);
+  AMG_HIP(hipGetLastError());
+  double* pb[2] = {B.p.p, B.p2.p};
+  int cur = 0;
+  int restarts = 0;
+  amg_status st = AMG_OK;
+  T* x0 = WB<T>::x(B.lv[0]);
+  // one batched iteration (columns flagged `first` take p = z on device)
+  auto iteration = [&](int c, hipStream_t stq) {
+    const int np = wsweep(LWv, n, W, L0.rp.p, L0.ci.p, WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W},
+                          B.head.p, part, stq);
+    hipLaunchKernelGGL(k_wfin_alpha, dim3(W), dim3(kWFin), 0, stq, B.ctl.p, B.head.p, part, W, np);
+    AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wupdate<LW, SYS, T>), dim3(gw), dim3(kBlock), 0, stq, n, W, d_x,
+                                            B.r.p, pb[c ^ 1], B.q.p, WB<T>::sw(L0), x0, B.ctl.p, B.head.p, part));
+    hipLaunchKernelGGL(k_wfin_update, dim3(W), dim3(kWFin), 0, stq, B.ctl.p, B.head.p, part, W, gw);
+    wvcycle<SYS, T>(H, W, B.r.p, B.z.p, B.q.p, flexible ? 2 : 1, stq);
+  };
+  auto pair = [&](int c) {
+    hipGraphExec_t& ex = H.gr.exec[c];
+    if (!ex) capture_graph(s, ex, [&] {
+        iteration(c, s);
+        iteration(c ^ 1, s);
+      });
+    AMG_HIP(hipGraphLaunch(ex, s));
+  };
+  for (;;) {
+    AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wswmul<LW, SYS, T>), dim3(gw), dim3(kBlock), 0, s, n, W,
+                                            WB<T>::sw(L0), B.r.p, x0));
+    wvcycle<SYS, T>(H, W, B.r.p, B.z.p, B.q.p, 1, s);
+    int chunk = o.check_every > 0 ? o.check_every : 4;
+    int it_prev = -1;
+    std::vector<double> rr_prev(W, 0.0);
+    for (;;) {
+      int left = chunk;
+      if (graphs)
+        for (; left >= 2; left -= 2) pair(cur);
+      for (; left > 0; --left) {
+        iteration(cur, s);
+        cur ^= 1;
+      }
+      AMG_HIP(hipGetLastError());
+      read_batch(H, W, s);
+      if (B.h_head->ndone >= W) break;
+      if (o.check_every <= 0) {
+        // size the next chunk from the slowest active column's decay
+        int next = 1;
+        int maxit = 0;
+        for (int c = 0; c < W; ++c) {
+          const WCtl& cc = B.h_ctl[c];
+          maxit = std::max(maxit, cc.iters);
+          if (cc.done) continue;
+          const double prev = it_prev < 0 ? cc.bb : rr_prev[c];
+          const int i0 = it_prev < 0 ? 0 : it_prev;
+          int nc = 4;
+          if (cc.thresh <= 0.0) nc = 32;
+          else if (cc.iters > i0 && prev > 0.0 && cc.rr > 0.0) {
+            const double rate = std::log(cc.rr / prev) / (double)(cc.iters - i0);
+            if (rate < -1e-3) nc = (int)std::min(64.0, std::ceil(std::log(cc.thresh / cc.rr) / rate));
+          }
+          next = std::max(next, nc);
+        }
+        for (int c = 0; c < W; ++c) rr_prev[c] = B.h_ctl[c].rr;
+        it_prev = maxit;
+        next = std::min(next, std::max(1, o.maxiter - maxit));
+        chunk = std::max(1, std::min(next, 32));
+      }
+    }
+    // true residuals of every column
+    const int np = wsweep(LWv, n, W, L0.rp.p, L0.ci.p, WTrueResid<SYS>{L0.v.p, d_x, d_b, B.r.p, W}, nullptr, part, s);
+    hipLaunchKernelGGL(k_wfin_trr, dim3(W), dim3(kWFin), 0, s, B.ctl.p, part, W, np);
+    read_batch(H, W, s);
+    int nre = 0;
+    for (int c = 0; c < W; ++c) {
+      const WCtl& cc = B.h_ctl[c];
+      const bool again = cc.state == 1 && cc.trr > cc.thresh && cc.restarts < 5 && cc.iters < o.maxiter;
+      B.h_mask[c] = again ? 1 : 0;
+      nre += again;
+    }
+    if (nre == 0) break;
+    ++restarts;
+    AMG_HIP(hipMemcpyAsync(B.mask.p, B.h_mask, sizeof(int) * W, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_wrestart, dim3(1), dim3(1), 0, s, B.ctl.p, B.head.p, B.mask.p, W);
+  }
+  if (graphs) {
+    AMG_HIP(hipEventRecord(H.gr.ev_out, s));
+    AMG_HIP(hipStreamWaitEvent(caller, H.gr.ev_out, 0));
+  }
+  // per-column outcome
+  B.col_iters.assign(W, 0);
+  B.col_status.assign(W, AMG_OK);
+  B.col_relres.assign(W, 0.0);
+  int maxit = 0;
+  double maxrr = 0.0;
+  for (int c = 0; c < W; ++c) {
+    const WCtl& cc = B.h_ctl[c];
+    int cs;
+    if (cc.state < 0) cs = AMG_ERR_BREAKDOWN;
+    else if (cc.state == 3 || cc.trr <= cc.thresh) cs = AMG_OK;
+    else cs = AMG_NOT_CONVERGED;
+    const double rr = cc.state == 3 ? 0.0 : (cc.bb > 0 ? std::sqrt(cc.trr / cc.bb) : 0.0);
+    B.col_iters[c] = cc.iters;
+    B.col_status[c] = cs;
+    B.col_relres[c] = cs == AMG_ERR_BREAKDOWN ? NAN : rr;
+    maxit = std::max(maxit, cc.iters);
+    if (cs != AMG_ERR_BREAKDOWN) maxrr = std::max(maxrr, rr);
+    if (cs == AMG_ERR_BREAKDOWN) st = AMG_ERR_BREAKDOWN;
+    else if (cs == AMG_NOT_CONVERGED && st == AMG_OK) st = AMG_NOT_CONVERGED;
+  }
+  if (info) {
+    info->iters = maxit;
+    info->status = st;
+    info->restarts = restarts;
+    info->rel_resid = st == AMG_ERR_BREAKDOWN ? NAN : maxrr;
+    info->cache_event = H.cache_event;
+    info->setup_ms = H.setup_ms;
+    info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+}  // namespace
+
+amg_status pcg_solve_wide(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int W,
+                          amg_info* info, hipStream_t s) {
+  if (W < 1 || W > kMaxWidth) throw Error(AMG_ERR_INVALID_ARG, "batch width out of range");
+  if (H.prm.nu_pre != 1 || H.prm.nu_post != 1) throw Error(AMG_ERR_INVALID_ARG, "batched solves use V(1,1)");
+  const bool sys = H.S > 1;
+  if (sys && W != H.S) throw Error(AMG_ERR_INVALID_ARG, "one column per system");
+  if (sys) {
+    if (H.fp32()) return solve_wide_impl<true, float>(H, o, d_b, d_x, tol, W, info, s);
+    return solve_wide_impl<true, double>(H, o, d_b, d_x, tol, W, info, s);
+  }
+  if (H.fp32()) return solve_wide_impl<false, float>(H, o, d_b, d_x, tol, W, info, s);
+  return solve_wide_impl<false, double>(H, o, d_b, d_x, tol, W, info, s);
+}
+
+void pattern_grad_wide(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, int W, hipStream_t s) {
+  Level& L = H.lv[0];
+  const int grid = (L.n + kBlock / 64 - 1) / (kBlock / 64);
+  if (H.S > 1)
+    hipLaunchKernelGGL(k_wpattern_grad<true>, dim3(grid), dim3(kBlock), 0, s, L.n, W, L.rp.p, L.ci.p, d_lam, d_x,
+                       d_g);
+  else
+    hipLaunchKernelGGL(k_wpattern_grad<false>, dim3(grid), dim3(kBlock), 0, s, L.n, W, L.rp.p, L.ci.p, d_lam, d_x,
+                       d_g);
+  AMG_HIP(hipGetLastError());
+}
+
+}  // namespace amg

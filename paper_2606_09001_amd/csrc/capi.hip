@@ -25,10 +25,31 @@ struct amg_handle_s {
 
 namespace amg {
 
+void Graphs::reset() {
+  for (auto& e : exec)
+    if (e) {
+      (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
+  key_x = nullptr;
+  key_flex = -1;
+  key_w = 0;
+}
+
+Graphs::~Graphs() {
+  reset();
+  if (ev_in) (void)hipEventDestroy(ev_in);
+  if (ev_out) (void)hipEventDestroy(ev_out);
+  if (gs) (void)hipStreamDestroy(gs);
+}
+
 Hierarchy::~Hierarchy() {
   if (h_ctl) (void)hipHostFree(h_ctl);
   if (h_flags) (void)hipHostFree(h_flags);
   for (hipEvent_t e : inst.ev) (void)hipEventDestroy(e);
+  if (bt.h_ctl) (void)hipHostFree(bt.h_ctl);
+  if (bt.h_head) (void)hipHostFree(bt.h_head);
+  if (bt.h_mask) (void)hipHostFree(bt.h_mask);
 }
 
 namespace {
@@ -69,13 +90,14 @@ uint64_t params_hash(const amg_params& p) {
   h = mix(h, t);
   h = mix(h, (uint64_t)p.nu_pre);
   h = mix(h, (uint64_t)p.nu_post);
+  h = mix(h, (uint64_t)p.autotune);
   return h;
 }
 
 bool same_setup_params(const amg_params& a, const amg_params& b) {
   return a.vcycle_prec == b.vcycle_prec && a.transfer_bf16 == b.transfer_bf16 && a.theta == b.theta &&
          a.max_coarse == b.max_coarse && a.max_levels == b.max_levels && a.smoother == b.smoother &&
-         a.omega == b.omega && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post;
+         a.omega == b.omega && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post && a.autotune == b.autotune;
 }
 
 amg_status check_params(const amg_params& p) {
@@ -143,6 +165,8 @@ void amg_params_default(amg_params* p) {
   p->flexible = -1;
   p->symmetric = 1;
   p->check_every = 0;
+  p->use_graphs = 1;
+  p->autotune = 0;
 }
 
 amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
@@ -151,37 +175,43 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
   return guarded([&]() -> amg_status {
     if (!out || !d_row_ptr || !d_col || !d_val || n <= 0 || nnz < n || nnz >= (int64_t)INT32_MAX)
       return AMG_ERR_INVALID_ARG;
-    if (n_systems != 1) return AMG_ERR_INVALID_ARG;
+    if (n_systems < 1 || n_systems > kMaxWidth) return AMG_ERR_INVALID_ARG;
     amg_params prm;
     if (params) prm = *params;
     else amg_params_default(&prm);
     amg_status ps = check_params(prm);
     if (ps != AMG_OK) return ps;
+    // several systems share one pattern-only aggregation (theta = 0) and the
+    // one-sweep cycle of the batched kernels
+    if (n_systems > 1 && (prm.theta != 0.0 || prm.nu_pre != 1 || prm.nu_post != 1)) return AMG_ERR_INVALID_ARG;
     auto t0 = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lock(g_mu);
     ensure_global_flags();
     validate_csr(n, nnz, d_row_ptr, d_col, g_flags.d, g_flags.h, stream);
-    const uint64_t key = mix(mix(mix(pattern_hash(n, nnz, d_row_ptr, d_col, g_flags.d, g_flags.h, stream),
-                                     (uint64_t)n), (uint64_t)nnz), params_hash(prm));
+    const uint64_t key = mix(mix(mix(mix(pattern_hash(n, nnz, d_row_ptr, d_col, g_flags.d, g_flags.h, stream),
+                                         (uint64_t)n), (uint64_t)nnz), params_hash(prm)), (uint64_t)n_systems);
     for (auto it = g_lru.begin(); it != g_lru.end(); ++it) {
       Hierarchy* H = *it;
-      if (H->key != key || H->n != n || H->nnz != nnz || !same_setup_params(H->prm, prm)) continue;
+      if (H->key != key || H->n != n || H->nnz != nnz || H->S != n_systems || !same_setup_params(H->prm, prm))
+        continue;
       if (!pattern_equal(*H, d_row_ptr, d_col, g_flags.d, g_flags.h, stream)) continue;
       g_lru.splice(g_lru.begin(), g_lru, it);
       if (values_equal(*H, d_val, g_flags.d, g_flags.h, stream)) {
         H->cache_event = AMG_CACHE_HIT;
         H->setup_ms = ms_since(t0);
       } else {
+        H->gr.reset();
         refresh_hierarchy(*H, d_val, stream);
         H->cache_event = AMG_CACHE_REFRESH;
         H->setup_ms = ms_since(t0);
       }
       ++H->refs;
-      *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every}};
+      *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every, prm.use_graphs}};
       return AMG_OK;
     }
     Hierarchy* H = new Hierarchy;
     H->prm = prm;
+    H->S = n_systems;
     H->n = n;
     H->nnz = nnz;
     H->lv.reserve(AMG_MAX_LEVELS + 1);
@@ -204,7 +234,7 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
       g_lru.push_front(H);
       evict_to(g_capacity);
     }
-    *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every}};
+    *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every, prm.use_graphs}};
     return AMG_OK;
   });
 }
@@ -214,6 +244,7 @@ amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stre
     if (!h || !d_val) return AMG_ERR_INVALID_ARG;
     auto t0 = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lock(g_mu);
+    h->H->gr.reset();
     refresh_hierarchy(*h->H, d_val, stream);
     h->H->cache_event = AMG_CACHE_REFRESH;
     h->H->setup_ms = ms_since(t0);
@@ -224,8 +255,11 @@ amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stre
 amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, int32_t nrhs, amg_info* info,
                      hipStream_t stream) {
   return guarded([&]() -> amg_status {
-    if (!h || !d_b || !d_x || nrhs < 1 || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
-    return pcg_solve(*h->H, h->opts, d_b, d_x, tol, nrhs, info, stream);
+    if (!h || !d_b || !d_x || nrhs < 1 || nrhs > kMaxWidth || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
+    Hierarchy& H = *h->H;
+    if (H.S > 1 && nrhs != H.S) return AMG_ERR_INVALID_ARG;
+    if (nrhs > 1 || H.S > 1) return pcg_solve_wide(H, h->opts, d_b, d_x, tol, nrhs, info, stream);
+    return pcg_solve(H, h->opts, d_b, d_x, tol, nrhs, info, stream);
   });
 }
 
@@ -240,9 +274,34 @@ amg_status amg_pattern_grad(amg_handle h, const double* d_lambda, const double* 
                             hipStream_t stream) {
   return guarded([&]() -> amg_status {
     if (!h || !d_lambda || !d_x || !d_grad_val) return AMG_ERR_INVALID_ARG;
-    pattern_grad(*h->H, d_lambda, d_x, d_grad_val, stream);
+    if (h->H->S > 1) pattern_grad_wide(*h->H, d_lambda, d_x, d_grad_val, h->H->S, stream);
+    else pattern_grad(*h->H, d_lambda, d_x, d_grad_val, stream);
     return AMG_OK;
   });
+}
+
+amg_status amg_pattern_grad_batched(amg_handle h, const double* d_lambda, const double* d_x, int32_t ncols,
+                                    double* d_grad_val, hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!h || !d_lambda || !d_x || !d_grad_val || ncols < 1 || ncols > kMaxWidth) return AMG_ERR_INVALID_ARG;
+    Hierarchy& H = *h->H;
+    if (H.S > 1 && ncols != H.S) return AMG_ERR_INVALID_ARG;
+    if (ncols == 1 && H.S == 1) pattern_grad(H, d_lambda, d_x, d_grad_val, stream);
+    else pattern_grad_wide(H, d_lambda, d_x, d_grad_val, ncols, stream);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_solve_columns(amg_handle h, int32_t ncols, int* iters, double* rel_resid, int* status) {
+  if (!h) return AMG_ERR_INVALID_ARG;
+  const Batch& B = h->H->bt;
+  if (ncols != (int)B.col_iters.size() || ncols < 1) return AMG_ERR_INVALID_ARG;
+  for (int c = 0; c < ncols; ++c) {
+    if (iters) iters[c] = B.col_iters[c];
+    if (rel_resid) rel_resid[c] = B.col_relres[c];
+    if (status) status[c] = B.col_status[c];
+  }
+  return AMG_OK;
 }
 
 amg_status amg_apply_vcycle(amg_handle h, const double* d_r, double* d_z, hipStream_t stream) {
@@ -281,6 +340,7 @@ static amg_status field_ptr(const Hierarchy& H, int level, int field, const void
   if (level < 0 || level >= (int)H.lv.size()) return AMG_ERR_INVALID_ARG;
   const Level& L = H.lv[level];
   const bool coarsest = level + 1 == (int)H.lv.size();
+  const int64_t S = H.S;  // value fields hold S interleaved systems
   *p = nullptr;
   *count = 0;
   *eb = 0;
@@ -288,22 +348,22 @@ static amg_status field_ptr(const Hierarchy& H, int level, int field, const void
     case AMG_FIELD_AGG: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.agg.p; *count = L.n; *eb = 4; break;
     case AMG_FIELD_A_ROWPTR: *p = L.rp.p; *count = L.n + 1; *eb = 4; break;
     case AMG_FIELD_A_COL: *p = L.ci.p; *count = L.nnz; *eb = 4; break;
-    case AMG_FIELD_A_VAL: *p = L.v.p; *count = L.nnz; *eb = 8; break;
-    case AMG_FIELD_A_VAL32: if (!H.fp32()) return AMG_ERR_INVALID_ARG; *p = L.v32.p; *count = L.nnz; *eb = 4; break;
-    case AMG_FIELD_DINV: *p = L.dinv.p; *count = L.n; *eb = 8; break;
-    case AMG_FIELD_DINV32: if (!H.fp32()) return AMG_ERR_INVALID_ARG; *p = L.sw32.p; *count = L.n; *eb = 4; break;
+    case AMG_FIELD_A_VAL: *p = L.v.p; *count = L.nnz * S; *eb = 8; break;
+    case AMG_FIELD_A_VAL32: if (!H.fp32()) return AMG_ERR_INVALID_ARG; *p = L.v32.p; *count = L.nnz * S; *eb = 4; break;
+    case AMG_FIELD_DINV: *p = L.dinv.p; *count = L.n * S; *eb = 8; break;
+    case AMG_FIELD_DINV32: if (!H.fp32()) return AMG_ERR_INVALID_ARG; *p = L.sw32.p; *count = L.n * S; *eb = 4; break;
     case AMG_FIELD_P_ROWPTR: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.prp.p; *count = L.n + 1; *eb = 4; break;
     case AMG_FIELD_P_COL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.pci.p; *count = L.pnnz; *eb = 4; break;
-    case AMG_FIELD_P_VAL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.pv.p; *count = L.pnnz; *eb = 8; break;
-    case AMG_FIELD_P_BF16: if (coarsest || !H.bf16()) return AMG_ERR_INVALID_ARG; *p = L.pbf.p; *count = L.pnnz; *eb = 2; break;
+    case AMG_FIELD_P_VAL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.pv.p; *count = L.pnnz * S; *eb = 8; break;
+    case AMG_FIELD_P_BF16: if (coarsest || !H.bf16()) return AMG_ERR_INVALID_ARG; *p = L.pbf.p; *count = L.pnnz * S; *eb = 2; break;
     case AMG_FIELD_R_ROWPTR: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.rrp.p; *count = L.nagg + 1; *eb = 4; break;
     case AMG_FIELD_R_COL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.rci.p; *count = L.pnnz; *eb = 4; break;
-    case AMG_FIELD_R_VAL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.rv.p; *count = L.pnnz; *eb = 8; break;
-    case AMG_FIELD_R_BF16: if (coarsest || !H.bf16()) return AMG_ERR_INVALID_ARG; *p = L.rbf.p; *count = L.pnnz; *eb = 2; break;
+    case AMG_FIELD_R_VAL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.rv.p; *count = L.pnnz * S; *eb = 8; break;
+    case AMG_FIELD_R_BF16: if (coarsest || !H.bf16()) return AMG_ERR_INVALID_ARG; *p = L.rbf.p; *count = L.pnnz * S; *eb = 2; break;
     case AMG_FIELD_G_ROWPTR: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.grp.p; *count = L.n + 1; *eb = 4; break;
     case AMG_FIELD_G_COL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.gci.p; *count = L.gnnz; *eb = 4; break;
-    case AMG_FIELD_COARSE_FACTOR: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.L.p; *count = (int64_t)H.co.m * H.co.m; *eb = 8; break;
-    case AMG_FIELD_COARSE_INV: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.inv.p; *count = (int64_t)H.co.m * H.co.m; *eb = 8; break;
+    case AMG_FIELD_COARSE_FACTOR: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.L.p; *count = (int64_t)H.co.m * H.co.m * S; *eb = 8; break;
+    case AMG_FIELD_COARSE_INV: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.inv.p; *count = (int64_t)H.co.m * H.co.m * S; *eb = 8; break;
     default: return AMG_ERR_INVALID_ARG;
   }
   return AMG_OK;

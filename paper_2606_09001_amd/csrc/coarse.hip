@@ -25,10 +25,10 @@ __global__ void k_densify(int n, int m, double* __restrict__ W) {
 }
 
 __global__ void k_scatter(int n, int m, const int* __restrict__ rp, const int* __restrict__ ci,
-                          const double* __restrict__ v, double* __restrict__ W) {
+                          const double* __restrict__ v, int vs, double* __restrict__ W) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) W[(int64_t)i * m + ci[k]] = v[k];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) W[(int64_t)i * m + ci[k]] = v[(int64_t)k * vs];
 }
 
 // C_tile(I,J) += A_tile * B_tile^T over 16 columns [k0, k0+16) of row
@@ -163,30 +163,34 @@ void coarse_setup(Hierarchy& H, hipStream_t s) {
   C.n = L.n;
   C.m = (L.n + 15) / 16 * 16;
   const int m = C.m;
+  const int S = H.S;
   const int64_t mm = (int64_t)m * m;
-  C.L.alloc(mm);
-  C.inv.alloc(mm);
+  C.L.alloc(mm * S);
+  C.inv.alloc(mm * S);
   C.work.alloc(mm);
-  int grid = (int)std::min<int64_t>((mm + kBlock - 1) / kBlock, 4096);
-  hipLaunchKernelGGL(k_densify, dim3(grid), dim3(kBlock), 0, s, C.n, m, C.L.p);
-  hipLaunchKernelGGL(k_scatter, dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C.n, m, L.rp.p, L.ci.p,
-                     L.v.p, C.L.p);
+  const int grid = (int)std::min<int64_t>((mm + kBlock - 1) / kBlock, 4096);
+  const int T = m / 16;
   AMG_HIP(hipMemsetAsync(H.flags.p, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kCoBlock), 0, s, m, C.L.p, H.flags.p);
+  // one dense factorization (and inverse) per system sharing the pattern
+  for (int sy = 0; sy < S; ++sy) {
+    double* Ls = C.L.p + sy * mm;
+    double* Is = C.inv.p + sy * mm;
+    hipLaunchKernelGGL(k_densify, dim3(grid), dim3(kBlock), 0, s, C.n, m, Ls);
+    hipLaunchKernelGGL(k_scatter, dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C.n, m, L.rp.p, L.ci.p,
+                       L.v.p + sy, S, Ls);
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kCoBlock), 0, s, m, Ls, H.flags.p);
+    hipLaunchKernelGGL(k_tri_inverse, dim3((m + 63) / 64), dim3(64), 0, s, m, Ls, Is);
+    hipLaunchKernelGGL(k_transpose, dim3((int)((mm + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, m, Is, C.work.p);
+    hipLaunchKernelGGL(k_gram, dim3((T * T * 64 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m, C.work.p, Is);
+  }
   AMG_HIP(hipGetLastError());
   AMG_HIP(hipMemcpyAsync(H.h_flags, H.flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   if (H.h_flags[0]) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
-  // inverse = L^-T L^-1
-  hipLaunchKernelGGL(k_tri_inverse, dim3((m + 63) / 64), dim3(64), 0, s, m, C.L.p, C.inv.p);
-  hipLaunchKernelGGL(k_transpose, dim3((int)((mm + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, m, C.inv.p,
-                     C.work.p);
-  const int T = m / 16;
-  hipLaunchKernelGGL(k_gram, dim3((T * T * 64 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m, C.work.p, C.inv.p);
   if (H.fp32()) {
-    C.inv32.alloc(mm);
-    hipLaunchKernelGGL(k_inv_to_f32, dim3((int)((mm + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mm, C.inv.p,
-                       C.inv32.p);
+    C.inv32.alloc(mm * S);
+    hipLaunchKernelGGL(k_inv_to_f32, dim3((int)((mm * S + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mm * S,
+                       C.inv.p, C.inv32.p);
   }
   AMG_HIP(hipGetLastError());
   AMG_HIP(hipStreamSynchronize(s));

@@ -96,8 +96,11 @@ __global__ void k_diff_bits(int64_t count, const double* __restrict__ a, const d
 // ------------------------------------------------------- level numerics
 
 // Diagonal position, 1/a_ii and the smoother weight of every row.
+// Value arrays of several systems sharing the pattern are interleaved with
+// stride vs (entry k of system s at [k*vs + s]); callers pass the pointers
+// offset by s.
 __global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
-                       int* __restrict__ diagpos, double* __restrict__ dinv, double* __restrict__ sw,
+                       int vs, int* __restrict__ diagpos, double* __restrict__ dinv, double* __restrict__ sw,
                        float* __restrict__ sw32, double omega, int l1, int* flags) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -105,34 +108,36 @@ __global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict_
   double asum = 0.0;
   for (int k = s; k < e; ++k) {
     if (ci[k] == i) pos = k;
-    asum += fabs(v[k]);
+    asum += fabs(v[(int64_t)k * vs]);
   }
+  const int64_t io = (int64_t)i * vs;
   if (pos < 0) {
     atomicOr(flags, F_ZERO_DIAG);
     diagpos[i] = s;
-    dinv[i] = 0.0;
-    sw[i] = 0.0;
-    if (sw32) sw32[i] = 0.0f;
+    dinv[io] = 0.0;
+    sw[io] = 0.0;
+    if (sw32) sw32[io] = 0.0f;
     return;
   }
-  if (v[pos] == 0.0) atomicOr(flags, F_ZERO_DIAG);
+  const double a = v[(int64_t)pos * vs];
+  if (a == 0.0) atomicOr(flags, F_ZERO_DIAG);
   diagpos[i] = pos;
-  double d = 1.0 / v[pos];
-  dinv[i] = d;
+  double d = 1.0 / a;
+  dinv[io] = d;
   double w = l1 ? 1.0 / asum : omega * d;
-  sw[i] = w;
-  if (sw32) sw32[i] = (float)w;
+  sw[io] = w;
+  if (sw32) sw32[io] = (float)w;
 }
 
 // Gershgorin bound max_i (sum_j |a_ij|) / |a_ii|; positive doubles order like
 // their bit patterns, so an integer max is exact and order-free.
-__global__ void k_rho(int n, const int* __restrict__ rp, const double* __restrict__ v, const int* __restrict__ diagpos,
-                      unsigned long long* out) {
+__global__ void k_rho(int n, const int* __restrict__ rp, const double* __restrict__ v, int vs,
+                      const int* __restrict__ diagpos, unsigned long long* out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) s += fabs(v[k]);
-  double r = s / fabs(v[diagpos[i]]);
+  for (int k = rp[i]; k < rp[i + 1]; ++k) s += fabs(v[(int64_t)k * vs]);
+  double r = s / fabs(v[(int64_t)diagpos[i] * vs]);
   atomicMax(out, (unsigned long long)__double_as_longlong(r));
 }
 
@@ -328,11 +333,11 @@ __global__ void k_p_count(int n, const int* __restrict__ rp, const int* __restri
 // s_J = sum of a_ij over j in row i with agg(j) = J in stored order from
 // +0.0, w = omegaP / a_ii, P_iJ = [J == agg(i)] - w*s_J (unfused).
 __global__ void k_p_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
-                         const int* __restrict__ diagpos, const int* __restrict__ agg, double omegaP,
+                         int vs, const int* __restrict__ diagpos, const int* __restrict__ agg, double omegaP,
                          const int* __restrict__ prp, int* __restrict__ pci, double* __restrict__ pv) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double w = omegaP / v[diagpos[i]];
+  double w = omegaP / v[(int64_t)diagpos[i] * vs];
   int ai = agg[i];
   int pos = prp[i], prev = -1;
   for (;;) {
@@ -344,11 +349,11 @@ __global__ void k_p_fill(int n, const int* __restrict__ rp, const int* __restric
     if (nxt == INT_MAX) break;
     double sJ = 0.0;
     for (int k = rp[i]; k < rp[i + 1]; ++k)
-      if (agg[ci[k]] == nxt) sJ += v[k];
+      if (agg[ci[k]] == nxt) sJ += v[(int64_t)k * vs];
     double delta = (nxt == ai) ? 1.0 : 0.0;
     double ws = w * sJ;
-    pci[pos] = nxt;
-    pv[pos] = delta - ws;
+    if (pci) pci[pos] = nxt;
+    pv[(int64_t)pos * vs] = delta - ws;
     ++pos;
     prev = nxt;
   }
@@ -373,12 +378,12 @@ __global__ void k_col_count(int64_t m, const int* __restrict__ ci, int* __restri
 // R = P^T: entry t of R is entry perm[t] of P (stable sort by column keeps
 // source rows ascending inside each row of R).
 __global__ void k_r_fill(int64_t m, const int* __restrict__ perm, const int* __restrict__ rowid,
-                         const double* __restrict__ pv, int* __restrict__ rci, double* __restrict__ rv) {
+                         const double* __restrict__ pv, int vs, int* __restrict__ rci, double* __restrict__ rv) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= m) return;
   int k = perm[t];
   if (rci) rci[t] = rowid[k];
-  rv[t] = pv[k];
+  rv[t * vs] = pv[(int64_t)k * vs];
 }
 
 // ------------------------------------------------- canonical products
@@ -433,7 +438,7 @@ __global__ void k_spgemm_count(int nrows, const int* __restrict__ xrp, const int
 __global__ void k_spgemm_fill(int nrows, const int* __restrict__ xrp, const int* __restrict__ xci,
                               const double* __restrict__ xv, const int* __restrict__ yrp, const int* __restrict__ yci,
                               const double* __restrict__ yv, const int* __restrict__ crp, int* __restrict__ cci,
-                              double* __restrict__ cv) {
+                              double* __restrict__ cv, int vs) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nrows) return;
   int pos = crp[i], prev = -1;
@@ -449,12 +454,12 @@ __global__ void k_spgemm_fill(int nrows, const int* __restrict__ xrp, const int*
       int k = xci[a];
       int q = find_col(yci, yrp[k], yrp[k + 1], nxt);
       if (q >= 0) {
-        double prod = xv[a] * yv[q];
+        double prod = xv[(int64_t)a * vs] * yv[(int64_t)q * vs];
         acc = acc + prod;
       }
     }
     if (cci) cci[pos] = nxt;
-    cv[pos] = acc;
+    cv[(int64_t)pos * vs] = acc;
     ++pos;
     prev = nxt;
   }
@@ -497,14 +502,16 @@ int read_int(const int* d, hipStream_t s) {
 }
 
 void level_numerics(Hierarchy& H, Level& L, hipStream_t s) {
+  const int S = H.S;
   L.diagpos.alloc(L.n);
-  L.dinv.alloc(L.n);
-  L.sw.alloc(L.n);
-  if (H.fp32()) L.sw32.alloc(L.n);
+  L.dinv.alloc((int64_t)L.n * S);
+  L.sw.alloc((int64_t)L.n * S);
+  if (H.fp32()) L.sw32.alloc((int64_t)L.n * S);
   zero_flags(H.flags.p, 1, s);
-  hipLaunchKernelGGL(k_diag, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p,
-                     L.dinv.p, L.sw.p, H.fp32() ? L.sw32.p : nullptr, H.prm.omega,
-                     (int)(H.prm.smoother == AMG_SMOOTHER_L1), H.flags.p);
+  for (int sy = 0; sy < S; ++sy)
+    hipLaunchKernelGGL(k_diag, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.ci.p, L.v.p + sy, S,
+                       L.diagpos.p, L.dinv.p + sy, L.sw.p + sy, H.fp32() ? L.sw32.p + sy : nullptr, H.prm.omega,
+                       (int)(H.prm.smoother == AMG_SMOOTHER_L1), H.flags.p);
   AMG_HIP(hipGetLastError());
   sync_flags(H.flags.p, H.h_flags, 1, s);
   if (H.h_flags[0] & F_ZERO_DIAG) throw Error(AMG_ERR_ZERO_DIAG, "zero diagonal");
@@ -602,11 +609,11 @@ int aggregate(Hierarchy& H, Level& L, hipStream_t s) {
   return nagg;
 }
 
-double gershgorin(Hierarchy& H, Level& L, hipStream_t s) {
+double gershgorin(Hierarchy& H, Level& L, int sy, hipStream_t s) {
   DBuf<unsigned long long> r;
   r.alloc(1);
   AMG_HIP(hipMemsetAsync(r.p, 0, sizeof(unsigned long long), s));
-  hipLaunchKernelGGL(k_rho, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.v.p, L.diagpos.p, r.p);
+  hipLaunchKernelGGL(k_rho, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.rp.p, L.v.p + sy, H.S, L.diagpos.p, r.p);
   AMG_HIP(hipGetLastError());
   unsigned long long bits = 0;
   AMG_HIP(hipMemcpyAsync(&bits, r.p, sizeof(bits), hipMemcpyDeviceToHost, s));
@@ -621,9 +628,16 @@ double gershgorin(Hierarchy& H, Level& L, hipStream_t s) {
 void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s) {
   Level& L = H.lv[l];
   const int n = L.n;
+  const int S = H.S;
   const dim3 b(kBlock);
-  L.rho = gershgorin(H, L, s);
-  L.omegaP = (4.0 / 3.0) / L.rho;
+  L.rhoS.resize(S);
+  L.omegaPS.resize(S);
+  for (int sy = 0; sy < S; ++sy) {
+    L.rhoS[sy] = gershgorin(H, L, sy, s);
+    L.omegaPS[sy] = (4.0 / 3.0) / L.rhoS[sy];
+  }
+  L.rho = L.rhoS[0];
+  L.omegaP = L.omegaPS[0];
   // P
   if (symbolic) {
     DBuf<int> cnt;
@@ -633,10 +647,11 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     exclusive_scan(cnt.p, L.prp.p, n + 1, s);
     L.pnnz = read_int(L.prp.p + n, s);
     L.pci.alloc(L.pnnz);
-    L.pv.alloc(L.pnnz);
+    L.pv.alloc(L.pnnz * S);
   }
-  hipLaunchKernelGGL(k_p_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.agg.p, L.omegaP,
-                     L.prp.p, L.pci.p, L.pv.p);
+  for (int sy = 0; sy < S; ++sy)
+    hipLaunchKernelGGL(k_p_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p + sy, S, L.diagpos.p, L.agg.p,
+                       L.omegaPS[sy], L.prp.p, sy == 0 ? L.pci.p : (int*)nullptr, L.pv.p + sy);
   AMG_HIP(hipGetLastError());
   // R = P^T
   const int nc = L.nagg;
@@ -660,13 +675,15 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     L.rrp.alloc(nc + 1);
     exclusive_scan(cnt.p, L.rrp.p, nc + 1, s);
     L.rci.alloc(L.pnnz);
-    L.rv.alloc(L.pnnz);
-    hipLaunchKernelGGL(k_r_fill, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rperm.p, rowid.p, L.pv.p, L.rci.p,
-                       L.rv.p);
+    L.rv.alloc(L.pnnz * S);
+    for (int sy = 0; sy < S; ++sy)
+      hipLaunchKernelGGL(k_r_fill, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rperm.p, rowid.p, L.pv.p + sy, S,
+                         sy == 0 ? L.rci.p : (int*)nullptr, L.rv.p + sy);
     AMG_HIP(hipStreamSynchronize(s));
   } else {
-    hipLaunchKernelGGL(k_r_fill, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rperm.p, (const int*)nullptr, L.pv.p,
-                       (int*)nullptr, L.rv.p);
+    for (int sy = 0; sy < S; ++sy)
+      hipLaunchKernelGGL(k_r_fill, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rperm.p, (const int*)nullptr,
+                         L.pv.p + sy, S, (int*)nullptr, L.rv.p + sy);
   }
   AMG_HIP(hipGetLastError());
   // AP = A P
@@ -678,10 +695,11 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     exclusive_scan(cnt.p, L.aprp.p, n + 1, s);
     L.apnnz = read_int(L.aprp.p + n, s);
     L.apci.alloc(L.apnnz);
-    L.apv.alloc(L.apnnz);
+    L.apv.alloc(L.apnnz * S);
   }
-  hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p,
-                     L.aprp.p, symbolic ? L.apci.p : (int*)nullptr, L.apv.p);
+  for (int sy = 0; sy < S; ++sy)
+    hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p + sy, L.prp.p, L.pci.p,
+                       L.pv.p + sy, L.aprp.p, (symbolic && sy == 0) ? L.apci.p : (int*)nullptr, L.apv.p + sy, S);
   AMG_HIP(hipGetLastError());
   // A_{l+1} = R (A P)
   if (symbolic) {
@@ -699,10 +717,12 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     exclusive_scan(cnt.p, C.rp.p, nc + 1, s);
     C.nnz = read_int(C.rp.p + nc, s);
     C.ci.alloc(C.nnz);
-    C.v.alloc(C.nnz);
+    C.v.alloc(C.nnz * S);
   }
-  hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(nc)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.rv.p, Lr.aprp.p,
-                     Lr.apci.p, Lr.apv.p, C.rp.p, symbolic ? C.ci.p : (int*)nullptr, C.v.p);
+  for (int sy = 0; sy < S; ++sy)
+    hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(nc)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.rv.p + sy, Lr.aprp.p,
+                       Lr.apci.p, Lr.apv.p + sy, C.rp.p, (symbolic && sy == 0) ? C.ci.p : (int*)nullptr, C.v.p + sy,
+                       S);
   AMG_HIP(hipGetLastError());
 }
 
@@ -711,19 +731,20 @@ void precision_copies(Hierarchy& H, hipStream_t s) {
   const dim3 b(kBlock);
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level& L = H.lv[l];
-    L.v32.alloc(L.nnz);
-    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.nnz)), b, 0, s, L.nnz, L.v.p, L.v32.p);
+    const int64_t S = H.S;
+    L.v32.alloc(L.nnz * S);
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.nnz * S)), b, 0, s, L.nnz * S, L.v.p, L.v32.p);
     if (l + 1 == H.lv.size()) break;
     if (H.bf16()) {
-      L.pbf.alloc(L.pnnz);
-      L.rbf.alloc(L.pnnz);
-      hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.pv.p, L.pbf.p);
-      hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rv.p, L.rbf.p);
+      L.pbf.alloc(L.pnnz * S);
+      L.rbf.alloc(L.pnnz * S);
+      hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(L.pnnz * S)), b, 0, s, L.pnnz * S, L.pv.p, L.pbf.p);
+      hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(L.pnnz * S)), b, 0, s, L.pnnz * S, L.rv.p, L.rbf.p);
     } else {
-      L.pv32.alloc(L.pnnz);
-      L.rv32.alloc(L.pnnz);
-      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.pv.p, L.pv32.p);
-      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.rv.p, L.rv32.p);
+      L.pv32.alloc(L.pnnz * S);
+      L.rv32.alloc(L.pnnz * S);
+      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.pnnz * S)), b, 0, s, L.pnnz * S, L.pv.p, L.pv32.p);
+      hipLaunchKernelGGL(k_to_f32, dim3(grid_for(L.pnnz * S)), b, 0, s, L.pnnz * S, L.rv.p, L.rv32.p);
     }
   }
   AMG_HIP(hipGetLastError());
@@ -781,7 +802,7 @@ bool pattern_equal(const Hierarchy& H, const int* d_rp, const int* d_ci, int* d_
 bool values_equal(const Hierarchy& H, const double* d_val, int* d_flags, int* h_flags, hipStream_t s) {
   const Level& L = H.lv[0];
   zero_flags(d_flags, 1, s);
-  hipLaunchKernelGGL(k_diff_bits, dim3(1024), dim3(kBlock), 0, s, L.nnz, d_val, L.v.p, d_flags);
+  hipLaunchKernelGGL(k_diff_bits, dim3(1024), dim3(kBlock), 0, s, L.nnz * H.S, d_val, L.v.p, d_flags);
   AMG_HIP(hipGetLastError());
   sync_flags(d_flags, h_flags, 1, s);
   return !(h_flags[0] & F_MISMATCH);
@@ -796,7 +817,7 @@ void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const doubl
     L0.nnz = H.nnz;
     L0.rp.alloc(H.n + 1);
     L0.ci.alloc(H.nnz);
-    L0.v.alloc(H.nnz);
+    L0.v.alloc(H.nnz * H.S);
     AMG_HIP(hipMemcpyAsync(L0.rp.p, d_rp, L0.rp.bytes(), hipMemcpyDeviceToDevice, s));
     AMG_HIP(hipMemcpyAsync(L0.ci.p, d_ci, L0.ci.bytes(), hipMemcpyDeviceToDevice, s));
     AMG_HIP(hipMemcpyAsync(L0.v.p, d_val, L0.v.bytes(), hipMemcpyDeviceToDevice, s));
@@ -820,7 +841,7 @@ void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const doubl
   coarse_setup(H, s);
   precision_copies(H, s);
   alloc_cycle_vectors(H);
-  choose_shapes(H);
+  choose_shapes(H, s);
   alloc_solve_workspace(H);
   AMG_HIP(hipStreamSynchronize(s));
 }

@@ -26,6 +26,14 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "amg_internal.hpp"
@@ -823,15 +831,210 @@ std::vector<int> host_copy(const DBuf<int>& d, int64_t count) {
 
 // ================================================================ public
 
-void choose_shapes(Hierarchy& H) {
-  for (size_t l = 0; l < H.lv.size(); ++l) {
-    Level& L = H.lv[l];
-    L.shA = make_shape(host_copy(L.rp, L.n + 1), L.n);
-    if (l + 1 < H.lv.size()) {
-      L.shP = make_shape(host_copy(L.prp, L.n + 1), L.n);
-      L.shR = make_shape(host_copy(L.rrp, L.nagg + 1), L.nagg);
+namespace {
+
+// ------------------------------------------------------------- autotuner
+//
+// Candidate launch shapes of one matrix: every stream shape whose row blocks
+// fit the staging buffer (1..64 lanes per row in the in-LDS sums) and the
+// lanes-per-row fallback with 8..64 lanes.  Each is timed with HIP events on
+// the operator that runs on that matrix in the cycle; the fastest wins.
+// Choices are cached in memory and, when AMG_TUNE_CACHE names a file, in a
+// text file of "key stream lanes rows_per_block" lines, so that later runs
+// (and therefore their rounding) repeat the same choice.
+
+std::vector<Shape> candidate_shapes(const std::vector<int>& rp, int n) {
+  std::vector<Shape> out;
+  for (int rb = kBlock; rb >= kBlock / 64; rb >>= 1) {
+    int mx = 0;
+    for (int r0 = 0; r0 < n; r0 += rb) mx = std::max(mx, rp[std::min(r0 + rb, n)] - rp[r0]);
+    if (mx > kStreamCap) continue;
+    Shape sh;
+    sh.stream = 1;
+    sh.g = kBlock / rb;
+    sh.rows_per_block = rb;
+    sh.max_block_nnz = mx;
+    sh.grid = round8(((int64_t)n + rb - 1) / rb);
+    out.push_back(sh);
+  }
+  for (int g = 8; g <= 64; g <<= 1) {
+    Shape sh;
+    sh.stream = 0;
+    sh.g = g;
+    sh.rows_per_block = kBlock / g;
+    sh.grid = round8(std::min<int64_t>(((int64_t)n + sh.rows_per_block - 1) / sh.rows_per_block, kMaxGrid));
+    out.push_back(sh);
+  }
+  return out;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, Shape> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("AMG_TUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  std::string key;
+  Shape sh;
+  while (f >> key >> sh.stream >> sh.g >> sh.rows_per_block) g_tune[key] = sh;
+}
+
+void tune_store(const std::string& key, const Shape& sh) {
+  g_tune[key] = sh;
+  const char* path = std::getenv("AMG_TUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << ' ' << sh.stream << ' ' << sh.g << ' ' << sh.rows_per_block << '\n';
+}
+
+template <class Op>
+double time_shape(const Shape& sh, int n, const int* rp, const int* ci, const Op& op, hipStream_t s,
+                  hipEvent_t e0, hipEvent_t e1) {
+  for (int w = 0; w < 2; ++w) sweep(sh, n, rp, ci, op, nullptr, nullptr, s);
+  AMG_HIP(hipEventRecord(e0, s));
+  constexpr int reps = 5;
+  for (int w = 0; w < reps; ++w) sweep(sh, n, rp, ci, op, nullptr, nullptr, s);
+  AMG_HIP(hipEventRecord(e1, s));
+  AMG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  return ms / reps;
+}
+
+// Shape for one matrix: the tuned one when enabled, else the row-length rule.
+template <class MakeOp>
+Shape pick_shape(Hierarchy& H, const char* kind, int level, const DBuf<int>& rpd, const DBuf<int>& cid, int n,
+                 int ncols, MakeOp make_op, hipStream_t s) {
+  const std::vector<int> rp = host_copy(rpd, n + 1);
+  Shape rule = make_shape(rp, n);
+  if (!H.prm.autotune || n == 0) return rule;
+  int maxrow = 0;
+  for (int i = 0; i < n; ++i) maxrow = std::max(maxrow, rp[i + 1] - rp[i]);
+  char key[256];
+  std::snprintf(key, sizeof key, "%s:n%d:nnz%d:max%d:c%d:p%d:t%d:w%d", kind, n, rp[n], maxrow, ncols,
+                H.prm.vcycle_prec, H.fp32() && H.prm.transfer_bf16, H.S);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load();
+  auto it = g_tune.find(key);
+  if (it != g_tune.end()) {
+    Shape sh = it->second;
+    // recompute the grid for this matrix
+    for (const Shape& c : candidate_shapes(rp, n))
+      if (c.stream == sh.stream && c.g == sh.g) return c;
+  }
+  // representative operands: unit vectors of the cycle precision
+  const int64_t len = std::max<int64_t>(n, ncols) + 1;
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  Shape best = rule;
+  double tbest = 1e300;
+  {
+    auto op = make_op(len);
+    for (const Shape& c : candidate_shapes(rp, n)) {
+      const double t = time_shape(c, n, rpd.p, cid.p, op.op, s, e0, e1);
+      if (t < tbest) {
+        tbest = t;
+        best = c;
+      }
     }
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)level;
+  tune_store(key, best);
+  return best;
+}
+
+// Owns the scratch vectors of a timing operator.
+template <class Op, class T>
+struct TuneOp {
+  DBuf<T> a, b, c;
+  Op op;
+};
+
+}  // namespace
+
+void choose_shapes(Hierarchy& H, hipStream_t s) {
+  const bool f32 = H.fp32();
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    Level& L = H.lv[l];
+    const int nc = l + 1 < H.lv.size() ? L.nagg : 0;
+    if (f32) {
+      L.shA = pick_shape(H, "A", (int)l, L.rp, L.ci, L.n, nc, [&](int64_t len) {
+        auto t = std::make_unique<TuneOp<OpResid<float, float>, float>>();
+        t->a.alloc(len); t->b.alloc(len); t->c.alloc(len);
+        AMG_HIP(hipMemsetAsync(t->a.p, 0, t->a.bytes(), s));
+        AMG_HIP(hipMemsetAsync(t->b.p, 0, t->b.bytes(), s));
+        t->op = OpResid<float, float>{L.v32.p, t->a.p, t->b.p, t->c.p};
+        return std::move(*t);
+      }, s);
+    } else {
+      L.shA = pick_shape(H, "A", (int)l, L.rp, L.ci, L.n, nc, [&](int64_t len) {
+        TuneOp<OpResid<double, double>, double> t;
+        t.a.alloc(len); t.b.alloc(len); t.c.alloc(len);
+        AMG_HIP(hipMemsetAsync(t.a.p, 0, t.a.bytes(), s));
+        AMG_HIP(hipMemsetAsync(t.b.p, 0, t.b.bytes(), s));
+        t.op = OpResid<double, double>{L.v.p, t.a.p, t.b.p, t.c.p};
+        return t;
+      }, s);
+    }
+    if (l + 1 == H.lv.size()) continue;
+    if (f32 && H.bf16()) {
+      L.shP = pick_shape(H, "P", (int)l, L.prp, L.pci, L.n, nc, [&](int64_t len) {
+        TuneOp<OpProlong<uint16_t, float>, float> t;
+        t.a.alloc(len); t.b.alloc(len);
+        AMG_HIP(hipMemsetAsync(t.a.p, 0, t.a.bytes(), s));
+        AMG_HIP(hipMemsetAsync(t.b.p, 0, t.b.bytes(), s));
+        t.op = OpProlong<uint16_t, float>{L.pbf.p, t.a.p, t.b.p};
+        return t;
+      }, s);
+      L.shR = pick_shape(H, "R", (int)l, L.rrp, L.rci, L.nagg, L.n, [&](int64_t len) {
+        TuneOp<OpRestrict<uint16_t, float>, float> t;
+        t.a.alloc(len); t.b.alloc(len);
+        AMG_HIP(hipMemsetAsync(t.a.p, 0, t.a.bytes(), s));
+        t.op = OpRestrict<uint16_t, float>{L.rbf.p, t.a.p, t.b.p, nullptr, nullptr};
+        return t;
+      }, s);
+    } else if (f32) {
+      L.shP = pick_shape(H, "P", (int)l, L.prp, L.pci, L.n, nc, [&](int64_t len) {
+        TuneOp<OpProlong<float, float>, float> t;
+        t.a.alloc(len); t.b.alloc(len);
+        AMG_HIP(hipMemsetAsync(t.a.p, 0, t.a.bytes(), s));
+        AMG_HIP(hipMemsetAsync(t.b.p, 0, t.b.bytes(), s));
+        t.op = OpProlong<float, float>{L.pv32.p, t.a.p, t.b.p};
+        return t;
+      }, s);
+      L.shR = pick_shape(H, "R", (int)l, L.rrp, L.rci, L.nagg, L.n, [&](int64_t len) {
+        TuneOp<OpRestrict<float, float>, float> t;
+        t.a.alloc(len); t.b.alloc(len);
+        AMG_HIP(hipMemsetAsync(t.a.p, 0, t.a.bytes(), s));
+        t.op = OpRestrict<float, float>{L.rv32.p, t.a.p, t.b.p, nullptr, nullptr};
+        return t;
+      }, s);
+    } else {
+      L.shP = pick_shape(H, "P", (int)l, L.prp, L.pci, L.n, nc, [&](int64_t len) {
+        TuneOp<OpProlong<double, double>, double> t;
+        t.a.alloc(len); t.b.alloc(len);
+        AMG_HIP(hipMemsetAsync(t.a.p, 0, t.a.bytes(), s));
+        AMG_HIP(hipMemsetAsync(t.b.p, 0, t.b.bytes(), s));
+        t.op = OpProlong<double, double>{L.pv.p, t.a.p, t.b.p};
+        return t;
+      }, s);
+      L.shR = pick_shape(H, "R", (int)l, L.rrp, L.rci, L.nagg, L.n, [&](int64_t len) {
+        TuneOp<OpRestrict<double, double>, double> t;
+        t.a.alloc(len); t.b.alloc(len);
+        AMG_HIP(hipMemsetAsync(t.a.p, 0, t.a.bytes(), s));
+        t.op = OpRestrict<double, double>{L.rv.p, t.a.p, t.b.p, nullptr, nullptr};
+        return t;
+      }, s);
+    }
+  }
+  AMG_HIP(hipStreamSynchronize(s));
 }
 
 void alloc_solve_workspace(Hierarchy& H) {
@@ -968,14 +1171,63 @@ void launch_sw_mul(Hierarchy& H, int n, const Ctl* ctl, hipStream_t s) {
                      Bufs<T>::x(L0), ctl);
 }
 
+// Captures the launches made by `body` on stream s into an executable graph;
+// a failure ends the capture before the error propagates.
+template <class F>
+void capture_graph_impl(hipStream_t s, hipGraphExec_t& ex, F&& body) {
+  hipGraph_t g = nullptr;
+  AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  AMG_HIP(hipStreamEndCapture(s, &g));
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    ex = nullptr;
+    throw Error(AMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+}
+
+void capture_graph(hipStream_t s, hipGraphExec_t& ex, const std::function<void()>& body) {
+  capture_graph_impl(s, ex, body);
+}
+
+// Library stream and join events for graph solves.
+void graph_stream(Hierarchy& H) {
+  if (!H.gr.gs) {
+    AMG_HIP(hipStreamCreateWithFlags(&H.gr.gs, hipStreamNonBlocking));
+    AMG_HIP(hipEventCreateWithFlags(&H.gr.ev_in, hipEventDisableTiming));
+    AMG_HIP(hipEventCreateWithFlags(&H.gr.ev_out, hipEventDisableTiming));
+  }
+}
+
 amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int nrhs,
-                     amg_info* info, hipStream_t s) {
+                     amg_info* info, hipStream_t caller) {
   if (nrhs != 1) throw Error(AMG_ERR_INVALID_ARG, "this entry point takes one right-hand side");
   auto t0 = std::chrono::steady_clock::now();
   Level& L0 = H.lv[0];
   const int n = H.n;
   const bool multi = H.lv.size() > 1;
   const int flexible = o.flexible < 0 ? (H.fp32() ? 1 : 0) : o.flexible;
+  const bool graphs = o.use_graphs && H.inst.kernel < 0;
+  hipStream_t s = caller;
+  if (graphs) {
+    graph_stream(H);
+    AMG_HIP(hipEventRecord(H.gr.ev_in, caller));
+    AMG_HIP(hipStreamWaitEvent(H.gr.gs, H.gr.ev_in, 0));
+    s = H.gr.gs;
+    if (H.gr.key_x != d_x || H.gr.key_flex != flexible || H.gr.key_w != 1) {
+      H.gr.reset();
+      H.gr.key_x = d_x;
+      H.gr.key_flex = flexible;
+      H.gr.key_w = 1;
+    }
+  }
   Ctl* ctl = H.ctl.p;
   double* part = H.partials.p;
   const int gv = vec_grid(n);
@@ -986,6 +1238,33 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
   // update writes the new p while neighbours still gather the old one)
   double* pb[2] = {H.p.p, H.z2.p};
   int cur = 0;
+  // one PCG iteration: p = z + beta p and q = A p; alpha; x, r update; z = M^-1 r, beta
+  auto iteration = [&](int first, int c, hipStream_t st) {
+    int np;
+    {
+      InstScope is(H, KID_SPMV_DOT, 0, st);
+      np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpSpmvXpayDev{L0.v.p, H.z.p, pb[c], pb[c ^ 1], H.q.p, ctl, first},
+                 ctl, part, st);
+    }
+    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinBlock), 0, st, ctl, part, np);
+    {
+      InstScope is(H, KID_CG_UPDATE, 0, st);
+      if (H.fp32()) launch_cg_update<float>(H, n, d_x, pb[c ^ 1], ctl, part, st);
+      else launch_cg_update<double>(H, n, d_x, pb[c ^ 1], ctl, part, st);
+    }
+    hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(kFinBlock), 0, st, ctl, part, gv);
+    CycleArgs a{H.r.p, H.z.p, H.q.p, ctl, part, flexible ? 2 : 1, 0, multi ? 1 : 0};
+    vcycle(H, a, st);
+  };
+  // two iterations captured once per direction-buffer parity and replayed
+  auto pair = [&](int c) {
+    hipGraphExec_t& ex = H.gr.exec[c];
+    if (!ex) capture_graph(s, ex, [&] {
+        iteration(0, c, s);
+        iteration(0, c ^ 1, s);
+      });
+    AMG_HIP(hipGraphLaunch(ex, s));
+  };
   int restarts = 0;
   amg_status st = AMG_OK;
   for (;;) {
@@ -1005,25 +1284,18 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
     int it_prev = -1;
     double rr_prev = 0.0;
     for (;;) {
-      for (int it = 0; it < chunk; ++it) {
-        int np;
-        double* pn = pb[cur ^ 1];
-        {
-          InstScope is(H, KID_SPMV_DOT, 0, s);
-          np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpSpmvXpayDev{L0.v.p, H.z.p, pb[cur], pn, H.q.p, ctl, first}, ctl,
-                     part, s);
-        }
+      int left = chunk;
+      if (first) {
+        iteration(1, cur, s);
         cur ^= 1;
         first = 0;
-        hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinBlock), 0, s, ctl, part, np);
-        {
-          InstScope is(H, KID_CG_UPDATE, 0, s);
-          if (H.fp32()) launch_cg_update<float>(H, n, d_x, pb[cur], ctl, part, s);
-          else launch_cg_update<double>(H, n, d_x, pb[cur], ctl, part, s);
-        }
-        hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv);
-        CycleArgs a{H.r.p, H.z.p, H.q.p, ctl, part, flexible ? 2 : 1, 0, multi ? 1 : 0};
-        vcycle(H, a, s);
+        --left;
+      }
+      if (graphs)
+        for (; left >= 2; left -= 2) pair(cur);
+      for (; left > 0; --left) {
+        iteration(0, cur, s);
+        cur ^= 1;
       }
       AMG_HIP(hipGetLastError());
       read_ctl(H, s);
@@ -1069,6 +1341,10 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
     }
     st = AMG_NOT_CONVERGED;
     break;
+  }
+  if (graphs) {
+    AMG_HIP(hipEventRecord(H.gr.ev_out, s));
+    AMG_HIP(hipStreamWaitEvent(caller, H.gr.ev_out, 0));
   }
   const Ctl& c = *H.h_ctl;
   if (info) {

@@ -20,7 +20,7 @@ __all__ = ["AmgHierarchy", "solve", "amg_solve", "AmgSolve", "make_params", "fin
            "set_cache_capacity", "make_preconditioner"]
 
 _PARAM_KEYS = ("vcycle_prec", "transfer_bf16", "theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre",
-               "nu_post", "maxiter", "flexible", "symmetric", "check_every")
+               "nu_post", "maxiter", "flexible", "symmetric", "check_every", "use_graphs", "autotune")
 
 
 def make_params(**kw) -> _lib.amg_params:
@@ -65,7 +65,9 @@ class AmgHierarchy:
     """Handle on a cached smoothed-aggregation hierarchy of a CSR matrix.
 
     Construction calls amg_setup: a cold setup, a cache hit, or an in-place
-    value refresh when the same pattern arrives with new values.
+    value refresh when the same pattern arrives with new values.  A 2-D `val`
+    of shape (nnz, S) sets up S systems sharing the pattern (one column of a
+    batched solve per system).
     """
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, **params):
@@ -75,12 +77,13 @@ class AmgHierarchy:
         val = _dev_f64(val, "val")
         self.n = self.row_ptr.numel() - 1
         self.nnz = self.col.numel()
-        if val.numel() != self.nnz:
+        self.n_systems = 1 if val.dim() == 1 else val.shape[1]
+        if val.shape[0] != self.nnz:
             raise ValueError("val and col must have the same length")
         self.params = make_params(**params)
         h = C.c_void_p()
         st = self._L.amg_setup(C.byref(self.params), self.n, self.nnz, self.row_ptr.data_ptr(),
-                               self.col.data_ptr(), val.data_ptr(), 1, _stream(), C.byref(h))
+                               self.col.data_ptr(), val.data_ptr(), self.n_systems, _stream(), C.byref(h))
         _lib.check(st, "amg_setup")
         self._h = h
 
@@ -126,13 +129,32 @@ class AmgHierarchy:
         return self._solve(self._L.amg_solve_adjoint, g, tol, out)
 
     def pattern_grad(self, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
-        """dL/dA on the stored pattern: -(lambda_i x_j) per entry (Eq. (2))."""
+        """dL/dA on the stored pattern: -(lambda_i x_j) per entry (Eq. (2)).
+
+        Batched (n, k) inputs: (nnz, S) per system, or for k right-hand sides
+        of one matrix the sum over the columns."""
         lam = _dev_f64(lam, "lambda")
         x = _dev_f64(x, "x")
-        g = torch.empty(self.nnz, dtype=torch.float64, device=lam.device)
-        _lib.check(self._L.amg_pattern_grad(self._h, lam.data_ptr(), x.data_ptr(), g.data_ptr(), _stream()),
-                   "amg_pattern_grad")
+        if lam.dim() == 1:
+            g = torch.empty(self.nnz, dtype=torch.float64, device=lam.device)
+            _lib.check(self._L.amg_pattern_grad(self._h, lam.data_ptr(), x.data_ptr(), g.data_ptr(), _stream()),
+                       "amg_pattern_grad")
+            return g
+        k = lam.shape[1]
+        g = torch.empty((self.nnz, k) if self.n_systems > 1 else (self.nnz,), dtype=torch.float64,
+                        device=lam.device)
+        _lib.check(self._L.amg_pattern_grad_batched(self._h, lam.data_ptr(), x.data_ptr(), k, g.data_ptr(),
+                                                    _stream()), "amg_pattern_grad_batched")
         return g
+
+    def columns(self, k: int) -> dict:
+        """Per-column iterations, true relative residuals and statuses of the
+        last batched solve of width k."""
+        it = (C.c_int * k)()
+        rr = (C.c_double * k)()
+        st = (C.c_int * k)()
+        _lib.check(self._L.amg_solve_columns(self._h, k, it, rr, st), "amg_solve_columns")
+        return dict(iters=list(it), rel_resid=list(rr), status=list(st))
 
     def apply_vcycle(self, r: torch.Tensor) -> torch.Tensor:
         """z = M^-1 r, one V-cycle (the preconditioner as an operator)."""

@@ -229,3 +229,53 @@ def test_mixed_precision_residual():
     H32, _ = pair(rp, ci, v, vcycle_prec="fp32", transfer_bf16=0)
     x32, info32 = H32.solve(dev(b), 1e-8)
     assert oracle.rel_residual(rp, ci, v, b, host(x32)) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_match_eager(prec):
+    # captured iteration pairs, replayed many times with eager solves and
+    # synchronisations in between: every replay equals the eager result bitwise
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    rp, ci, v = M.diffusion(np.exp(M.grf(48, 2, seed=4)))
+    n = len(rp) - 1
+    He = AmgHierarchy(dev(rp), dev(ci), dev(v), vcycle_prec=prec, use_graphs=0)
+    Hg = AmgHierarchy(dev(rp), dev(ci), dev(v), vcycle_prec=prec, use_graphs=1)
+    b1 = dev(M.rhs_normal(n, 1))
+    b2 = dev(M.rhs_normal(n, 2))
+    xe1, ie1 = He.solve(b1, 1e-10)
+    xe2, ie2 = He.solve(b2, 1e-10)
+    out = torch.empty_like(b1)
+    for rep in range(4):
+        xg, ig = Hg.solve(b1 if rep % 2 == 0 else b2, 1e-10, out=out)
+        ref, iref = (xe1, ie1) if rep % 2 == 0 else (xe2, ie2)
+        assert torch.equal(xg, ref) and ig["iters"] == iref["iters"], rep
+        He.solve(b2, 1e-10)              # eager work between replays
+        torch.cuda.synchronize()
+    x_new, _ = Hg.solve(b1, 1e-10)       # a new output buffer: captured again
+    assert torch.equal(x_new, xe1)
+
+
+def test_graph_replays_batched_match_eager():
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    rp, ci, v = M.poisson(20, 3)
+    n = len(rp) - 1
+    B = dev(M.rhs_normal(n, 5, nrhs=6))
+    He = AmgHierarchy(dev(rp), dev(ci), dev(v), max_coarse=32, use_graphs=0)
+    Hg = AmgHierarchy(dev(rp), dev(ci), dev(v), max_coarse=32, use_graphs=1)
+    xe, ie = He.solve(B, 1e-10)
+    out = torch.empty_like(B)
+    for rep in range(3):
+        xg, ig = Hg.solve(B, 1e-10, out=out)
+        assert torch.equal(xg, xe) and ig["iters"] == ie["iters"]
+        He.solve(B, 1e-10)
+        torch.cuda.synchronize()
+
+
+def test_autotuned_shapes_keep_parity(tmp_path, monkeypatch):
+    import os
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("AMG_TUNE_CACHE", str(cache))
+    rp, ci, v = M.diffusion(np.exp(M.grf(24, 3, seed=5)))
+    H, O = _solve_parity(rp, ci, v, M.rhs_normal(len(rp) - 1, 3), 1e-10, autotune=1)
+    assert_hierarchy_bitexact(H, O)
+    assert os.path.exists(cache) and len(cache.read_text().splitlines()) >= 3

@@ -52,7 +52,14 @@ def test_setup_rejects_bad_arguments_before_touching_a_device():
     L.amg_params_default(C.byref(p))
     assert L.amg_setup(C.byref(p), 0, 0, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
     assert L.amg_setup(C.byref(p), 4, 4, None, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 0, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 65, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    p.theta = 0.1   # several systems need the pattern-only aggregation
     assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 2, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    p.theta = 0.0
+    p.nu_pre = 2    # and V(1,1)
+    assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 2, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    p.nu_pre = 1
     p.symmetric = 0
     assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
     p.symmetric = 1
