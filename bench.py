@@ -54,6 +54,210 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+# ------------------------------------------------------------ profile summaries
+#
+# Turns rocprofv3 output of this script into the committed summaries under
+# profiles/: per-kernel durations from a --kernel-trace --stats run, and HBM
+# bytes per dispatch from two --pmc runs (FETCH_SIZE, then WRITE_SIZE), each
+# scaled by what the same counter reads for the calibration kernel (a negation
+# of CALIB_MIB MiB: that many bytes read and written).
+
+FINE_KERNELS = {  # tag -> (regex on the demangled name); level 0 = the largest grid
+    "spmv_dot_L0": r"k_stream<\d+, [^>]*OpSpmvXpayDev>",
+    "pre_L0": r"k_stream<\d+, [^>]*OpResid<double, double> >",
+    "post_L0": r"k_stream<\d+, [^>]*OpPost<double, double, double, 1> >",
+}
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _working(durs):
+    """Dispatches that did work: launches queued past convergence return at
+    once (a few microseconds) and are left out, as in the in-solve timing."""
+    if not durs:
+        return []
+    top = sorted(durs)[int(0.9 * (len(durs) - 1))]
+    return [d for d in durs if d > 0.3 * top]
+
+
+def _level0(rows, pattern, grid_key):
+    import re
+    rx = re.compile(pattern)
+    sel = [r for r in rows if rx.search(r["Kernel_Name"])]
+    if not sel:
+        return []
+    g = max(int(r[grid_key]) for r in sel)
+    return [r for r in sel if int(r[grid_key]) == g]
+
+
+def summarize_profiles(a):
+    tag = a.summary_tag
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    lines = [f"# rocprofv3 kernel trace: {tag}", "", "command:", f"    {a.cmd_trace}", ""]
+    stats = _csv_rows(a.trace_dir, "kernel_stats.csv")
+    trace = _csv_rows(a.trace_dir, "kernel_trace.csv")
+    lines.append("top kernels by total time (all dispatches; AverageNs includes launches queued past convergence):")
+    lines.append(f"{'calls':>7} {'total_ms':>10} {'avg_us':>9} {'min_us':>8} {'max_us':>8}  name")
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:24]:
+        lines.append(f"{int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['MinNs']) / 1e3:8.2f} {float(r['MaxNs']) / 1e3:8.2f}  {r['Name'][:150]}")
+    lines += ["", "level-0 sweeps, FP64 solve (largest grid of each kernel; working dispatches only):"]
+    summary = {}
+    for k, pat in FINE_KERNELS.items():
+        sel = _level0(trace, pat, "Grid_Size_X")
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
+        w = _working(durs)
+        if not w:
+            continue
+        summary[k] = dict(dispatches=len(durs), working=len(w), avg_us=sum(w) / len(w), min_us=min(w), max_us=max(w))
+        lines.append(f"  {k:12s} dispatches {len(durs):5d} working {len(w):5d} avg {summary[k]['avg_us']:8.2f} us "
+                     f"min {min(w):8.2f} max {max(w):8.2f}")
+    with open(os.path.join(out_dir, f"{tag}_kernels.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    if not (a.fetch_dir and a.write_dir):
+        return
+
+    def per_dispatch(d, counter):
+        rows = [r for r in _csv_rows(d, "counter_collection.csv") if r["Counter_Name"] == counter]
+        calib = [float(r["Counter_Value"]) for r in rows if "neg_kernel" in r["Kernel_Name"]]
+        if not calib:
+            raise SystemExit(f"no calibration dispatch in {d}")
+        factor = max(calib) / (CALIB_MIB * 1024.0)   # counter KiB per known KiB
+        res = {}
+        for k, pat in FINE_KERNELS.items():
+            sel = _level0(rows, pat, "Grid_Size")
+            vals = [float(r["Counter_Value"]) for r in sel]
+            w = _working(vals)
+            if w:
+                res[k] = dict(kib=sum(w) / len(w), n=len(w), bytes=sum(w) / len(w) / factor * 1024.0)
+        return factor, res
+
+    ff, fetch = per_dispatch(a.fetch_dir, "FETCH_SIZE")
+    wf, write = per_dispatch(a.write_dir, "WRITE_SIZE")
+    src = kernel_source_hash()
+    txt = [f"# HBM traffic per dispatch: {tag}", "", "commands:", f"    {a.cmd_fetch}", f"    {a.cmd_write}", "",
+           f"calibration: negation of {CALIB_MIB} MiB (reads and writes {CALIB_MIB * 1024} KiB); "
+           f"FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f} (counter KiB per byte-exact KiB)", "",
+           f"{'kernel':12s} {'FETCH KiB':>12} {'WRITE KiB':>12} {'traffic MB':>11}  dispatches"]
+    for k in FINE_KERNELS:
+        if k not in fetch or k not in write:
+            continue
+        traffic = fetch[k]["bytes"] + write[k]["bytes"]
+        txt.append(f"{k:12s} {fetch[k]['kib']:12.0f} {write[k]['kib']:12.0f} {traffic / 1e6:11.2f}  "
+                   f"{fetch[k]['n']}/{write[k]['n']}")
+        with open(os.path.join(out_dir, f"{tag}_{k}_pmc.json"), "w") as f:
+            json.dump({"kernel": k, "source_sha256": src, "fetch_kib_per_dispatch": fetch[k]["kib"],
+                       "write_kib_per_dispatch": write[k]["kib"], "fetch_factor": ff, "write_factor": wf,
+                       "traffic_bytes_per_launch": round(traffic), "commands": [a.cmd_fetch, a.cmd_write],
+                       "working_avg_us_from_trace": summary.get(k, {}).get("avg_us")}, f, indent=1)
+    txt.append(f"\nkernel source sha256 (solve.hip + amg_internal.hpp): {src}")
+    with open(os.path.join(out_dir, f"{tag}_pmc.txt"), "w") as f:
+        f.write("\n".join(txt) + "\n")
+    print("\n".join(txt))
+
+
+CALIB_MIB = 512
+
+
+def time_solves(H, B, X, tol, steps, warmup):
+    """Events bracketing `steps` batched solves (after `warmup`); returns
+    (ms per solve, per-column info of the last solve, info)."""
+    import torch
+    for _ in range(warmup):
+        H.solve(B, tol, out=X)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        _, info = H.solve(B, tol, out=X)
+    e1.record()
+    torch.cuda.synchronize()
+    k = B.shape[1] if B.dim() == 2 else 1
+    cols = H.columns(k) if k > 1 else None
+    return e0.elapsed_time(e1) / steps, cols, info
+
+
+def run_batched(args, dev):
+    """Batched forms: k right-hand sides of one matrix, and S systems sharing a
+    pattern; FP64 and FP32-cycle, columns/s and the mixed speedup."""
+    import numpy as np
+    import torch
+    from paper_2606_09001_amd import matrices as M
+    from paper_2606_09001_amd.solver import AmgHierarchy, finalize
+    out = {}
+    # (1) 32 right-hand sides on the 256^3 Poisson system
+    N, k = args.batched_rhs_grid, 32
+    rp, ci, v = M.poisson(N, 3)
+    n = len(rp) - 1
+    B = np.empty((n, k))
+    for c in range(k):
+        B[:, c] = M.rhs_normal(n, 3000 + c)
+    d_rp, d_ci, d_v = (torch.from_numpy(a).to(dev) for a in (rp, ci, v))
+    d_B = torch.from_numpy(B).to(dev)
+    del B
+    X = torch.empty_like(d_B)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec)
+        ms, cols, info = time_solves(H, d_B, X, args.tol, args.batched_steps, 1)
+        res[prec] = dict(ms_per_batch=round(ms, 3), rhs_per_s=round(k * 1e3 / ms, 2), iters_max=max(cols["iters"]),
+                         rel_resid_max=max(cols["rel_resid"]), all_converged=all(s_ == 0 for s_ in cols["status"]))
+        log(f"batched {k} RHS on {N}^3 {prec}: {ms:.1f} ms/batch, {k * 1e3 / ms:.1f} RHS/s, "
+            f"iters {min(cols['iters'])}..{max(cols['iters'])}")
+        H.close()
+        del H
+        finalize()
+        torch.cuda.synchronize()
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms_per_batch"] / res["fp32"]["ms_per_batch"], 4)
+    out[f"poisson3d_{N}_x{k}rhs"] = res
+    del d_B, X, d_rp, d_ci, d_v
+    torch.cuda.empty_cache()
+    # (2) S same-pattern lognormal diffusion systems on a 96^3 grid
+    N, S = args.batched_sys_grid, 64
+    vals = []
+    for s in range(S):
+        rp, ci, vv = M.diffusion(np.exp(M.grf(N, 3, seed=1000 + s)))
+        vals.append(vv)
+    V = np.ascontiguousarray(np.stack(vals, axis=1))
+    del vals
+    n = len(rp) - 1
+    B = np.ascontiguousarray(np.stack([M.rhs_normal(n, 2000 + s) for s in range(S)], axis=1))
+    d_rp, d_ci, d_V, d_B = (torch.from_numpy(a).to(dev) for a in (rp, ci, V, B))
+    del V, B
+    X = torch.empty_like(d_B)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        t0 = time.time()
+        H = AmgHierarchy(d_rp, d_ci, d_V, vcycle_prec=prec)
+        torch.cuda.synchronize()
+        setup_ms = (time.time() - t0) * 1e3
+        ms, cols, info = time_solves(H, d_B, X, args.tol, args.batched_steps, 1)
+        res[prec] = dict(ms_per_batch=round(ms, 3), systems_per_s=round(S * 1e3 / ms, 2),
+                         iters_max=max(cols["iters"]), rel_resid_max=max(cols["rel_resid"]),
+                         all_converged=all(s_ == 0 for s_ in cols["status"]), setup_ms=round(setup_ms, 1))
+        log(f"batched {S} systems {N}^3 {prec}: setup {setup_ms:.0f} ms, {ms:.1f} ms/batch, "
+            f"{S * 1e3 / ms:.1f} systems/s, iters {min(cols['iters'])}..{max(cols['iters'])}")
+        H.close()
+        del H
+        finalize()
+        torch.cuda.synchronize()
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms_per_batch"] / res["fp32"]["ms_per_batch"], 4)
+    out[f"diffusion3d_{N}_x{S}systems"] = res
+    del d_B, X, d_V
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,7 +270,25 @@ def main():
                     help="size of a plain device copy run once (PMC calibration of FETCH/WRITE_SIZE)")
     ap.add_argument("--no-kernel-table", action="store_true",
                     help="skip the per-kernel timing passes (used for counter-collection runs)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (multi-RHS / multi-system) section")
+    ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--batched-rhs-grid", type=int, default=256)
+    ap.add_argument("--batched-sys-grid", type=int, default=96)
+    ap.add_argument("--summarize-profiles", action="store_true",
+                    help="write profiles/ summaries from rocprofv3 output of this script (no GPU)")
+    ap.add_argument("--summary-tag", default="poisson3d_128")
+    ap.add_argument("--trace-dir")
+    ap.add_argument("--fetch-dir")
+    ap.add_argument("--write-dir")
+    ap.add_argument("--cmd-trace", default="")
+    ap.add_argument("--cmd-fetch", default="")
+    ap.add_argument("--cmd-write", default="")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        global CALIB_MIB
+        CALIB_MIB = args.calib_copy_mib
+        summarize_profiles(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solve path is single-GPU "
               f"by design and multi-GPU runs are not part of this benchmark.", file=sys.stderr)
@@ -109,6 +331,8 @@ def main():
         torch.cuda.synchronize()
         copy_gbs = 2 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         log(f"device copy {args.calib_copy_mib} MiB: {copy_gbs:.0f} GB/s (read+write)")
+        torch.neg(src, out=dst)   # counter calibration: reads and writes exactly this many bytes
+        torch.cuda.synchronize()
         del src, dst
 
     res = {}
@@ -205,6 +429,18 @@ def main():
                "oracle_iters": io["iters"], "gpu_vs_oracle_rel_err": err}
         log(f"oracle: setup {osetup:.2f}s solve {osolve:.2f}s iters {io['iters']}; |x_gpu-x_oracle|/|x|={err:.2e}")
 
+    batched = None
+    if not args.no_batched:
+        from paper_2606_09001_amd.solver import finalize
+        for h_ in hier.values():
+            h_.close()
+        del hier, H
+        finalize()          # the setup cache holds its own reference
+        del d_rp, d_ci, d_v, d_b, x
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        batched = run_batched(args, dev)
+
     f64, f32 = res["fp64"], res["fp32"]
     out = {
         "metric": METRIC,
@@ -237,6 +473,7 @@ def main():
                     for k, d in kernels.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -222,7 +222,9 @@ enum {
 amg_status amg_instrument(amg_handle h, int kernel, int level);
 
 /* Synchronises on the recorded events; returns the number of timed launches
- * and their total, minimum and maximum durations in ms. */
+ * that did work and their total, minimum and maximum durations in ms.
+ * Launches that started after the solve had converged (they return at once)
+ * are left out. */
 amg_status amg_instrument_read(amg_handle h, int* launches, double* total_ms, double* min_ms, double* max_ms);
 
 /* Algorithmic bytes of one launch of `kernel` at `level` (every matrix

@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/amg355.h"
+#include "amg355.h"
 
 namespace amg {
 
@@ -142,6 +142,7 @@ enum KernelId {
 struct Instr {
   int kernel = -1, level = -1;
   std::vector<hipEvent_t> ev;  // begin/end pairs
+  DBuf<int> was_done;          // per timed launch: the solve's done flag just before it
   int used = 0;
 };
 

@@ -430,6 +430,25 @@ __global__ void k_spgemm_count(int nrows, const int* __restrict__ xrp, const int
   cnt[i] = c;
 }
 
+// Column pattern of row i of C = X Y (ascending), no values.
+__global__ void k_spgemm_cols(int nrows, const int* __restrict__ xrp, const int* __restrict__ xci,
+                              const int* __restrict__ yrp, const int* __restrict__ yci, const int* __restrict__ crp,
+                              int* __restrict__ cci) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  int pos = crp[i], prev = -1;
+  for (;;) {
+    int nxt = INT_MAX;
+    for (int a = xrp[i]; a < xrp[i + 1]; ++a) {
+      int k = xci[a];
+      nxt = min(nxt, next_col(yci, yrp[k], yrp[k + 1], prev));
+    }
+    if (nxt == INT_MAX) break;
+    cci[pos++] = nxt;
+    prev = nxt;
+  }
+}
+
 // Values of C = X Y in canonical order: for every output column J
 // (ascending), acc = +0.0 and for every k of row i of X in ascending order
 // with y_kJ stored, acc += x_ik * y_kJ (product rounded, then sum rounded).
@@ -463,6 +482,36 @@ __global__ void k_spgemm_fill(int nrows, const int* __restrict__ xrp, const int*
     ++pos;
     prev = nxt;
   }
+}
+
+// Numeric C = X Y on a known pattern, one thread per stored entry (row i,
+// column J): the same fold over k of row i of X in ascending order as
+// k_spgemm_fill, so the values are identical; parallel over all entries.
+__global__ void k_spgemm_fill_entries(int nrows, int64_t cnnz, const int* __restrict__ crp,
+                                      const int* __restrict__ cci, const int* __restrict__ xrp,
+                                      const int* __restrict__ xci, const double* __restrict__ xv,
+                                      const int* __restrict__ yrp, const int* __restrict__ yci,
+                                      const double* __restrict__ yv, double* __restrict__ cv, int vs) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= cnnz) return;
+  // row of entry e: last i with crp[i] <= e
+  int lo = 0, hi = nrows;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)crp[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int i = lo;
+  const int J = cci[e];
+  double acc = 0.0;
+  for (int a = xrp[i]; a < xrp[i + 1]; ++a) {
+    const int k = xci[a];
+    const int q = find_col(yci, yrp[k], yrp[k + 1], J);
+    if (q >= 0) {
+      double prod = xv[(int64_t)a * vs] * yv[(int64_t)q * vs];
+      acc = acc + prod;
+    }
+  }
+  cv[e * vs] = acc;
 }
 
 // ------------------------------------------------------ precision copies
@@ -697,9 +746,14 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     L.apci.alloc(L.apnnz);
     L.apv.alloc(L.apnnz * S);
   }
-  for (int sy = 0; sy < S; ++sy)
-    hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p + sy, L.prp.p, L.pci.p,
-                       L.pv.p + sy, L.aprp.p, (symbolic && sy == 0) ? L.apci.p : (int*)nullptr, L.apv.p + sy, S);
+  for (int sy = 0; sy < S; ++sy) {
+    if (symbolic && sy == 0)
+      hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p,
+                         L.pv.p, L.aprp.p, L.apci.p, L.apv.p, S);
+    else
+      hipLaunchKernelGGL(k_spgemm_fill_entries, dim3(grid_for(L.apnnz)), b, 0, s, n, L.apnnz, L.aprp.p, L.apci.p,
+                         L.rp.p, L.ci.p, L.v.p + sy, L.prp.p, L.pci.p, L.pv.p + sy, L.apv.p + sy, S);
+  }
   AMG_HIP(hipGetLastError());
   // A_{l+1} = R (A P)
   if (symbolic) {
@@ -719,10 +773,14 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     C.ci.alloc(C.nnz);
     C.v.alloc(C.nnz * S);
   }
+  if (symbolic) {
+    // column pattern of the coarse operator (thread per row), values below
+    hipLaunchKernelGGL(k_spgemm_cols, dim3(grid_for(nc)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p,
+                       C.rp.p, C.ci.p);
+  }
   for (int sy = 0; sy < S; ++sy)
-    hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(nc)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.rv.p + sy, Lr.aprp.p,
-                       Lr.apci.p, Lr.apv.p + sy, C.rp.p, (symbolic && sy == 0) ? C.ci.p : (int*)nullptr, C.v.p + sy,
-                       S);
+    hipLaunchKernelGGL(k_spgemm_fill_entries, dim3(grid_for(C.nnz)), b, 0, s, nc, C.nnz, C.rp.p, C.ci.p, Lr.rrp.p,
+                       Lr.rci.p, Lr.rv.p + sy, Lr.aprp.p, Lr.apci.p, Lr.apv.p + sy, C.v.p + sy, S);
   AMG_HIP(hipGetLastError());
 }
 

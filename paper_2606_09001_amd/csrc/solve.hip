@@ -588,15 +588,25 @@ void launch_fin_beta(Ctl* ctl, double* partials, int np, int first, int nv, hipS
 
 // ------------------------------------------------------------ V-cycle
 
-// Records an event pair around a launch when (kernel, level) is instrumented.
+// Copies the done flag (0 when there is none) into the instrument record.
+__global__ void k_snap_done(const Ctl* ctl, int* dst) {
+  if (threadIdx.x == 0) dst[0] = ctl ? ctl->done : 0;
+}
+
+// Records an event pair around a launch when (kernel, level) is instrumented,
+// and, before the pair, the solve's done flag: a launch that starts with the
+// flag set returns at once and is left out of the statistics.
 struct InstScope {
   Hierarchy& H;
   hipStream_t s;
   bool on;
-  InstScope(Hierarchy& h, int kid, int level, hipStream_t st) : H(h), s(st) {
+  InstScope(Hierarchy& h, int kid, int level, hipStream_t st, const Ctl* ctl) : H(h), s(st) {
     on = H.inst.kernel == kid && (H.inst.level == level || H.inst.level < 0) &&
          2 * (H.inst.used + 1) <= (int)H.inst.ev.size();
-    if (on) AMG_HIP(hipEventRecord(H.inst.ev[2 * H.inst.used], s));
+    if (on) {
+      hipLaunchKernelGGL(k_snap_done, dim3(1), dim3(64), 0, s, ctl, H.inst.was_done.p + H.inst.used);
+      AMG_HIP(hipEventRecord(H.inst.ev[2 * H.inst.used], s));
+    }
   }
   ~InstScope() {
     if (on) {
@@ -676,7 +686,7 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
   Ctl* ctl = a.ctl;
   if (nl == 1) {
     {
-      InstScope is(H, KID_COARSE, 0, s);
+      InstScope is(H, KID_COARSE, 0, s, a.ctl);
       hipLaunchKernelGGL((k_coarse<double, double, double>), dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                          C.n, C.m, C.inv.p, a.r0, a.z0, ctl);
     }
@@ -701,7 +711,7 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
     {
       // pre-smoothing from zero: x = sw o b was written by the producer of b
       // (CG update on level 0, restriction below), so only r = b - A x remains
-      InstScope is(H, KID_PRE, l, s);
+      InstScope is(H, KID_PRE, l, s, a.ctl);
       if (l == 0 && !a.x0_ready)
         sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPre<T, double>{Bufs<T>::v(L), Bufs<T>::sw(L), a.r0, cx[l], cr[l]}, ctl,
               nullptr, s);
@@ -723,7 +733,7 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
       std::swap(cr[l], sr[l]);
     }
     {
-      InstScope is(H, KID_RESTRICT, l, s);
+      InstScope is(H, KID_RESTRICT, l, s, a.ctl);
       Level& Ln = H.lv[l + 1];
       const bool coarsest = (l + 1 == nl - 1);
       launch_restrict<T>(H, L, cr[l], Bufs<T>::b(Ln), coarsest ? nullptr : Bufs<T>::sw(Ln),
@@ -733,7 +743,7 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
   T* res;
   {
     Level& Lc = H.lv[nl - 1];
-    InstScope is(H, KID_COARSE, nl - 1, s);
+    InstScope is(H, KID_COARSE, nl - 1, s, a.ctl);
     hipLaunchKernelGGL((k_coarse<T, T, T>), dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C.n, C.m,
                        Bufs<T>::inv(C), Bufs<T>::b(Lc), Bufs<T>::x(Lc), ctl);
     res = Bufs<T>::x(Lc);
@@ -741,7 +751,7 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = H.lv[l];
     {
-      InstScope is(H, KID_PROLONG, l, s);
+      InstScope is(H, KID_PROLONG, l, s, a.ctl);
       launch_prolong<T>(H, L, res, cx[l], ctl, s);
     }
     // free T buffers of this level after restriction: cr[l] and sx[l]
@@ -754,7 +764,7 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
       if (l == 0 && last) {
         int np = 0;
         {
-          InstScope is(H, KID_POST, l, s);
+          InstScope is(H, KID_POST, l, s, a.ctl);
           if (a.red == 2)
             np = sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, double, 2>{vv, sw, a.r0, cur, a.z0, a.q}, ctl,
                        a.partials, s);
@@ -768,7 +778,7 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
         if (a.red) launch_fin_beta(ctl, a.partials, np, a.first, a.red, s);
       } else {
         T* dst = spare[k & 1];
-        InstScope is(H, KID_POST, l, s);
+        InstScope is(H, KID_POST, l, s, a.ctl);
         if (l == 0)
           sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, T, 0>{vv, sw, a.r0, cur, dst, nullptr}, ctl, nullptr,
                 s);
@@ -1122,6 +1132,7 @@ void set_instrument(Hierarchy& H, int kid, int level) {
   if (H.inst.ev.empty()) {
     H.inst.ev.resize(2 * 8192);
     for (auto& e : H.inst.ev) AMG_HIP(hipEventCreate(&e));
+    H.inst.was_done.alloc(8192);
   }
   H.inst.kernel = kid;
   H.inst.level = level;
@@ -1130,17 +1141,24 @@ void set_instrument(Hierarchy& H, int kid, int level) {
 
 void read_instrument(Hierarchy& H, int* launches, double* total_ms, double* min_ms, double* max_ms) {
   double tot = 0.0, mn = 1e300, mx = 0.0;
+  std::vector<int> done(H.inst.used);
+  if (H.inst.used) {
+    AMG_HIP(hipEventSynchronize(H.inst.ev[2 * H.inst.used - 1]));
+    AMG_HIP(hipMemcpy(done.data(), H.inst.was_done.p, sizeof(int) * H.inst.used, hipMemcpyDeviceToHost));
+  }
+  int working = 0;
   for (int i = 0; i < H.inst.used; ++i) {
-    AMG_HIP(hipEventSynchronize(H.inst.ev[2 * i + 1]));
+    if (done[i]) continue;
     float ms = 0.f;
     AMG_HIP(hipEventElapsedTime(&ms, H.inst.ev[2 * i], H.inst.ev[2 * i + 1]));
     tot += ms;
     mn = std::min(mn, (double)ms);
     mx = std::max(mx, (double)ms);
+    ++working;
   }
-  *launches = H.inst.used;
+  *launches = working;
   *total_ms = tot;
-  *min_ms = H.inst.used ? mn : 0.0;
+  *min_ms = working ? mn : 0.0;
   *max_ms = mx;
 }
 
@@ -1242,13 +1260,13 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
   auto iteration = [&](int first, int c, hipStream_t st) {
     int np;
     {
-      InstScope is(H, KID_SPMV_DOT, 0, st);
+      InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
       np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpSpmvXpayDev{L0.v.p, H.z.p, pb[c], pb[c ^ 1], H.q.p, ctl, first},
                  ctl, part, st);
     }
     hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinBlock), 0, st, ctl, part, np);
     {
-      InstScope is(H, KID_CG_UPDATE, 0, st);
+      InstScope is(H, KID_CG_UPDATE, 0, st, ctl);
       if (H.fp32()) launch_cg_update<float>(H, n, d_x, pb[c ^ 1], ctl, part, st);
       else launch_cg_update<double>(H, n, d_x, pb[c ^ 1], ctl, part, st);
     }
