@@ -65,11 +65,12 @@ struct WResid {
   const T* x;
   T* r;
   int W;
+  struct Row {
+    T b;
+  };
   __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
-  __device__ void epi(int row, int c, PT s, double*) const {
-    const int64_t e = (int64_t)row * W + c;
-    r[e] = (T)b[e] - s;
-  }
+  __device__ Row row_in(int row, int c) const { return {(T)b[(int64_t)row * W + c]}; }
+  __device__ void epi(int row, int c, PT s, const Row& a, double*) const { r[(int64_t)row * W + c] = a.b - s; }
 };
 
 // y = R x ; xc = swc o y
@@ -86,10 +87,14 @@ struct WRestrict {
   __device__ PT prod(int k, int j, int c) const {
     return (T)ValCvt<RT>::f(val_at<SYS>(v, k, c, W)) * x[(int64_t)j * W + c];
   }
-  __device__ void epi(int row, int c, PT s, double*) const {
+  struct Row {
+    T w;
+  };
+  __device__ Row row_in(int row, int c) const { return {xc ? row_at<SYS>(swc, row, c, W) : (T)0}; }
+  __device__ void epi(int row, int c, PT s, const Row& a, double*) const {
     const int64_t e = (int64_t)row * W + c;
     y[e] = s;
-    if (xc) xc[e] = row_at<SYS>(swc, row, c, W) * s;
+    if (xc) xc[e] = a.w * s;
   }
 };
 
@@ -105,10 +110,11 @@ struct WProlong {
   __device__ PT prod(int k, int j, int c) const {
     return (T)ValCvt<RT>::f(val_at<SYS>(v, k, c, W)) * xc[(int64_t)j * W + c];
   }
-  __device__ void epi(int row, int c, PT s, double*) const {
-    const int64_t e = (int64_t)row * W + c;
-    x[e] = x[e] + s;
-  }
+  struct Row {
+    T x;
+  };
+  __device__ Row row_in(int row, int c) const { return {x[(int64_t)row * W + c]}; }
+  __device__ void epi(int row, int c, PT s, const Row& a, double*) const { x[(int64_t)row * W + c] = a.x + s; }
 };
 
 // out = x + sw o (b - A x); RED >= 1: <b, out>, RED == 2: <out, q> per column
@@ -124,14 +130,23 @@ struct WPost {
   const double* q;
   int W;
   __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
-  __device__ void epi(int row, int c, PT s, double* d) const {
+  struct Row {
+    BT b;
+    T x, w;
+    double q;
+  };
+  __device__ Row row_in(int row, int c) const {
     const int64_t e = (int64_t)row * W + c;
-    const T bi = (T)b[e];
-    const T o = x[e] + row_at<SYS>(sw, row, c, W) * (bi - s);
+    Row a{b[e], x[e], row_at<SYS>(sw, row, c, W), 0.0};
+    if constexpr (RED >= 2) a.q = q[e];
+    return a;
+  }
+  __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
+    const T o = a.x + a.w * ((T)a.b - s);
     const OT oo = (OT)o;
-    out[e] = oo;
-    if constexpr (RED >= 1) d[0] += (double)b[e] * (double)oo;
-    if constexpr (RED >= 2) d[1] += (double)oo * q[e];
+    out[(int64_t)row * W + c] = oo;
+    if constexpr (RED >= 1) d[0] += (double)a.b * (double)oo;
+    if constexpr (RED >= 2) d[1] += (double)oo * a.q;
   }
 };
 
@@ -147,17 +162,23 @@ struct WSpmvXpay {
   double* q;
   const WCtl* ctl;
   int W;
+  struct Row {
+    double pr;
+  };
+  // both operands are always loaded (no divergent branch around a load);
+  // a column that (re)starts takes p' = z
   __device__ double dir(int64_t e, int c) const {
     const WCtl& cc = ctl[c];
-    return cc.first ? z[e] : z[e] + cc.beta * p[e];
+    const double zz = z[e], pp = p[e];
+    return cc.first ? zz : zz + cc.beta * pp;
   }
   __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * dir((int64_t)j * W + c, c); }
-  __device__ void epi(int row, int c, PT s, double* d) const {
+  __device__ Row row_in(int row, int c) const { return {dir((int64_t)row * W + c, c)}; }
+  __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
     const int64_t e = (int64_t)row * W + c;
-    const double pr = dir(e, c);
-    pn[e] = pr;
+    pn[e] = a.pr;
     q[e] = s;
-    d[0] += pr * s;
+    d[0] += a.pr * s;
   }
 };
 
@@ -171,11 +192,14 @@ struct WTrueResid {
   const double* b;
   double* r;
   int W;
+  struct Row {
+    double b;
+  };
   __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
-  __device__ void epi(int row, int c, PT s, double* d) const {
-    const int64_t e = (int64_t)row * W + c;
-    const double ri = b[e] - s;
-    r[e] = ri;
+  __device__ Row row_in(int row, int c) const { return {b[(int64_t)row * W + c]}; }
+  __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
+    const double ri = a.b - s;
+    r[(int64_t)row * W + c] = ri;
     d[0] += ri * ri;
   }
 };
@@ -206,7 +230,7 @@ template <int LW, class Op>
 __global__ void __launch_bounds__(kBlock) k_wide(int n, int W, const int* __restrict__ rp,
                                                  const int* __restrict__ ci, Op op,
                                                  const BatchHead* __restrict__ head, double* __restrict__ partials) {
-  if (head && head->ndone >= head->W) return;
+  if ((head && head->ndone >= head->W) || n <= 0) return;
   using PT = typename Op::PT;
   constexpr int RB = kBlock / LW;
   constexpr int U = 8;
@@ -215,24 +239,39 @@ __global__ void __launch_bounds__(kBlock) k_wide(int n, int W, const int* __rest
   const int lb = logical_block_w();
   const int g0 = (int)(groups * lb / gridDim.x), g1 = (int)(groups * (lb + 1) / gridDim.x);
   double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  const int cc = min(c, W - 1);
+  // row pointers of the next row group are loaded one iteration ahead, and
+  // the row's own operands together with its first entries, so that one
+  // iteration waits on memory twice (entries, then gathers)
+  int k0 = 0, k1 = 0;
+  if (g0 < g1) {
+    const int r = min(g0 * RB + lr, n - 1);
+    k0 = rp[r];
+    k1 = rp[r + 1];
+  }
   for (int g = g0; g < g1; ++g) {
     const int row = g * RB + lr;
+    const int rn = min(row + RB, n - 1);
+    const int kn0 = rp[rn], kn1 = rp[rn + 1];
+    const typename Op::Row in = op.row_in(min(row, n - 1), cc);
     PT s = 0;
     if (row < n && c < W) {
-      const int k0 = rp[row], k1 = rp[row + 1];
       for (int kb = k0; kb < k1; kb += U) {
+        // unconditional loads (indices clamped to the row's last entry) so
+        // that the U gathers are in flight together; the sum is masked
         int cols[U];
 #pragma unroll
-        for (int e = 0; e < U; ++e) cols[e] = kb + e < k1 ? ci[kb + e] : -1;
+        for (int e = 0; e < U; ++e) cols[e] = ci[min(kb + e, k1 - 1)];
         PT pr[U];
 #pragma unroll
-        for (int e = 0; e < U; ++e) pr[e] = cols[e] >= 0 ? op.prod(kb + e, cols[e], c) : (PT)0;
+        for (int e = 0; e < U; ++e) pr[e] = op.prod(min(kb + e, k1 - 1), cols[e], c);
 #pragma unroll
-        for (int e = 0; e < U; ++e)
-          if (cols[e] >= 0) s += pr[e];
+        for (int e = 0; e < U; ++e) s = kb + e < k1 ? s + pr[e] : s;
       }
-      op.epi(row, c, s, d);
+      op.epi(row, c, s, in, d);
     }
+    k0 = kn0;
+    k1 = kn1;
   }
   publish_w<LW, Op::NRED>(d, W, partials);
 }

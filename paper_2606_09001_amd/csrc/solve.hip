@@ -60,9 +60,12 @@ inline int round8(int64_t g) {
 
 // ----------------------------------------------------------- operators
 // An operator supplies
-//   PT prod(k, j)              product for stored entry k (column j)
-//   void epi(row, s, d[])      consumes the row sum s; d[] collects dot partials
-//   static constexpr int NRED  number of dot products reduced
+//   PT prod(k, j)                 product for stored entry k (column j)
+//   Row row_in(row)               the row's own operands (loaded by the sweep
+//                                 kernels before the row sum is formed, so that
+//                                 their latency overlaps the matrix stream)
+//   void epi(row, s, in, d[])     consumes the row sum s; d[] collects dot partials
+//   static constexpr int NRED     number of dot products reduced
 
 // Direction update fused with the product: p' = z + beta p (p' = z on the
 // first iteration of a (re)start), q = A p', <p', q>; p' goes to a second
@@ -78,13 +81,16 @@ struct OpSpmvXpayDev {
   double* q;
   const Ctl* ctl;
   int first;
+  struct Row {
+    double pr;
+  };
   __device__ double dir(int j, double beta) const { return first ? z[j] : z[j] + beta * p[j]; }
   __device__ PT prod(int k, int j) const { return v[k] * dir(j, ctl->beta); }
-  __device__ void epi(int row, PT s, double* d) const {
-    const double pr = dir(row, ctl->beta);
-    pn[row] = pr;
+  __device__ Row row_in(int row) const { return {dir(row, ctl->beta)}; }
+  __device__ void epi(int row, PT s, const Row& a, double* d) const {
+    pn[row] = a.pr;
     q[row] = s;
-    d[0] += pr * s;
+    d[0] += a.pr * s;
   }
 };
 
@@ -96,9 +102,13 @@ struct OpTrueResid {
   const double* x;
   const double* b;
   double* r;
+  struct Row {
+    double b;
+  };
   __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
-  __device__ void epi(int row, PT s, double* d) const {
-    const double ri = b[row] - s;
+  __device__ Row row_in(int row) const { return {b[row]}; }
+  __device__ void epi(int row, PT s, const Row& a, double* d) const {
+    const double ri = a.b - s;
     r[row] = ri;
     d[0] += ri * ri;
   }
@@ -115,11 +125,14 @@ struct OpPre {
   const BT* b;
   T* x;
   T* r;
+  struct Row {
+    T b, w;
+  };
   __device__ PT prod(int k, int j) const { return v[k] * (sw[j] * (T)b[j]); }
-  __device__ void epi(int row, PT s, double*) const {
-    const T bi = (T)b[row];
-    x[row] = sw[row] * bi;
-    r[row] = bi - s;
+  __device__ Row row_in(int row) const { return {(T)b[row], sw[row]}; }
+  __device__ void epi(int row, PT s, const Row& a, double*) const {
+    x[row] = a.w * a.b;
+    r[row] = a.b - s;
   }
 };
 
@@ -133,8 +146,12 @@ struct OpResid {
   const BT* b;
   const T* x;
   T* r;
+  struct Row {
+    T b;
+  };
   __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
-  __device__ void epi(int row, PT s, double*) const { r[row] = (T)b[row] - s; }
+  __device__ Row row_in(int row) const { return {(T)b[row]}; }
+  __device__ void epi(int row, PT s, const Row& a, double*) const { r[row] = a.b - s; }
 };
 
 // Further Jacobi sweep in residual form, fused with the new residual:
@@ -150,10 +167,14 @@ struct OpSweep {
   const T* r;
   T* x2;
   T* r2;
+  struct Row {
+    T x, w, r, b;
+  };
   __device__ PT prod(int k, int j) const { return v[k] * (x[j] + sw[j] * r[j]); }
-  __device__ void epi(int row, PT s, double*) const {
-    x2[row] = x[row] + sw[row] * r[row];
-    r2[row] = (T)b[row] - s;
+  __device__ Row row_in(int row) const { return {x[row], sw[row], r[row], (T)b[row]}; }
+  __device__ void epi(int row, PT s, const Row& a, double*) const {
+    x2[row] = a.x + a.w * a.r;
+    r2[row] = a.b - s;
   }
 };
 
@@ -169,14 +190,23 @@ struct OpPost {
   const T* x;
   OT* out;
   const double* q;
+  struct Row {
+    BT b;
+    T x, w;
+    double q;
+  };
   __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
-  __device__ void epi(int row, PT s, double* d) const {
-    const T bi = (T)b[row];
-    const T o = x[row] + sw[row] * (bi - s);
+  __device__ Row row_in(int row) const {
+    Row a{b[row], x[row], sw[row], 0.0};
+    if constexpr (RED >= 2) a.q = q[row];
+    return a;
+  }
+  __device__ void epi(int row, PT s, const Row& a, double* d) const {
+    const T o = a.x + a.w * ((T)a.b - s);
     const OT oo = (OT)o;
     out[row] = oo;
-    if constexpr (RED >= 1) d[0] += (double)b[row] * (double)oo;
-    if constexpr (RED >= 2) d[1] += (double)oo * q[row];
+    if constexpr (RED >= 1) d[0] += (double)a.b * (double)oo;
+    if constexpr (RED >= 2) d[1] += (double)oo * a.q;
   }
 };
 
@@ -191,10 +221,14 @@ struct OpRestrict {
   T* y;
   const T* swc;
   T* xc;
+  struct Row {
+    T w;
+  };
   __device__ PT prod(int k, int j) const { return (T)ValCvt<RT>::f(v[k]) * x[j]; }
-  __device__ void epi(int row, PT s, double*) const {
+  __device__ Row row_in(int row) const { return {xc ? swc[row] : (T)0}; }
+  __device__ void epi(int row, PT s, const Row& a, double*) const {
     y[row] = s;
-    if (xc) xc[row] = swc[row] * s;
+    if (xc) xc[row] = a.w * s;
   }
 };
 
@@ -206,8 +240,12 @@ struct OpProlong {
   const RT* v;
   const T* xc;
   T* x;
+  struct Row {
+    T x;
+  };
   __device__ PT prod(int k, int j) const { return (T)ValCvt<RT>::f(v[k]) * xc[j]; }
-  __device__ void epi(int row, PT s, double*) const { x[row] = x[row] + s; }
+  __device__ Row row_in(int row) const { return {x[row]}; }
+  __device__ void epi(int row, PT s, const Row& a, double*) const { x[row] = a.x + s; }
 };
 
 template <int NRED>
@@ -227,7 +265,7 @@ template <int G3, class Op>
 __global__ void __launch_bounds__(kBlock) k_stream(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    Op op, const Ctl* __restrict__ ctl,
                                                    double* __restrict__ partials) {
-  if (ctl && ctl->done) return;
+  if ((ctl && ctl->done) || n <= 0) return;
   constexpr int RB = kBlock / G3;
   constexpr int U = kStreamCap / kBlock;
   using PT = typename Op::PT;
@@ -235,23 +273,28 @@ __global__ void __launch_bounds__(kBlock) k_stream(int n, const int* __restrict_
   __shared__ PT s_p[kStreamCap];
   const int r0 = logical_block() * RB;
   for (int t = threadIdx.x; t <= RB; t += kBlock) s_rp[t] = rp[min(r0 + t, n)];
+  const int lr = threadIdx.x / G3, lane = threadIdx.x & (G3 - 1);
+  const int row = r0 + lr;
+  const typename Op::Row in = op.row_in(min(row, n - 1));
   __syncthreads();
   const int k0 = s_rp[0];
   const int nk = s_rp[RB] - k0;
-  int col[U];
+  if (nk > 0) {
+    // Loads are unconditional (indices clamped to the block's last entry) so
+    // that all of them are in flight at once; only the LDS stores are masked.
+    int col[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int j = threadIdx.x + u * kBlock;
-    col[u] = j < nk ? ci[k0 + j] : 0;
-  }
+    for (int u = 0; u < U; ++u) col[u] = ci[k0 + min((int)threadIdx.x + u * kBlock, nk - 1)];
+    PT pv[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int j = threadIdx.x + u * kBlock;
-    if (j < nk) s_p[j] = op.prod(k0 + j, col[u]);
+    for (int u = 0; u < U; ++u) pv[u] = op.prod(k0 + min((int)threadIdx.x + u * kBlock, nk - 1), col[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = threadIdx.x + u * kBlock;
+      if (j < nk) s_p[j] = pv[u];
+    }
   }
   __syncthreads();
-  const int lr = threadIdx.x / G3, lane = threadIdx.x & (G3 - 1);
-  const int row = r0 + lr;
   PT s = 0;
   if (row < n) {
     const int e = s_rp[lr + 1] - k0;
@@ -259,25 +302,40 @@ __global__ void __launch_bounds__(kBlock) k_stream(int n, const int* __restrict_
   }
   s = group_sum<G3>(s);
   double d[Op::NRED > 0 ? Op::NRED : 1] = {};
-  if (row < n && group_leader<G3>()) op.epi(row, s, d);
+  if (row < n && group_leader<G3>()) op.epi(row, s, in, d);
   publish_partials<Op::NRED>(d, partials);
 }
 
 template <int G, class Op>
 __global__ void __launch_bounds__(kBlock) k_vec(int n, const int* __restrict__ rp, const int* __restrict__ ci, Op op,
                                                 const Ctl* __restrict__ ctl, double* __restrict__ partials) {
-  if (ctl && ctl->done) return;
+  if ((ctl && ctl->done) || n <= 0) return;
   using PT = typename Op::PT;
   constexpr int RB = kBlock / G;
   const int lr = threadIdx.x / G, lane = threadIdx.x & (G - 1);
   double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  constexpr int U = 4;
   for (int r0 = logical_block() * RB; r0 < n; r0 += gridDim.x * RB) {
     const int row = r0 + lr;
+    const typename Op::Row in = op.row_in(min(row, n - 1));
     PT s = 0;
-    if (row < n)
-      for (int k = rp[row] + lane; k < rp[row + 1]; k += G) s += op.prod(k, ci[k]);
+    if (row < n) {
+      const int kb = rp[row], ke = rp[row + 1];
+      // U entries per lane in flight (clamped indices, unconditional loads);
+      // each lane still adds its entries k, k+G, k+2G, ... in that order
+      for (int k = kb + lane; k < ke; k += U * G) {
+        int cc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cc[u] = ci[min(k + u * G, ke - 1)];
+        PT pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pv[u] = op.prod(min(k + u * G, ke - 1), cc[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) s = k + u * G < ke ? s + pv[u] : s;
+      }
+    }
     s = group_sum<G>(s);
-    if (row < n && group_leader<G>()) op.epi(row, s, d);
+    if (row < n && group_leader<G>()) op.epi(row, s, in, d);
   }
   publish_partials<Op::NRED>(d, partials);
 }
