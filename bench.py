@@ -189,7 +189,9 @@ def time_solves(H, B, X, tol, steps, warmup):
 
 def run_batched(args, dev):
     """Batched forms: k right-hand sides of one matrix, and S systems sharing a
-    pattern; FP64 and FP32-cycle, columns/s and the mixed speedup."""
+    pattern; FP64 and FP32-cycle, columns/s and the mixed speedup.  Launch
+    shapes are autotuned: the first (untimed) solve of each hierarchy times
+    the candidates."""
     import numpy as np
     import torch
     from paper_2606_09001_amd import matrices as M
@@ -208,7 +210,7 @@ def run_batched(args, dev):
     X = torch.empty_like(d_B)
     res = {}
     for prec in ("fp64", "fp32"):
-        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec)
+        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec, autotune=1)
         ms, cols, info = time_solves(H, d_B, X, args.tol, args.batched_steps, 1)
         res[prec] = dict(ms_per_batch=round(ms, 3), rhs_per_s=round(k * 1e3 / ms, 2), iters_max=max(cols["iters"]),
                          rel_resid_max=max(cols["rel_resid"]), all_converged=all(s_ == 0 for s_ in cols["status"]))
@@ -238,7 +240,7 @@ def run_batched(args, dev):
     res = {}
     for prec in ("fp64", "fp32"):
         t0 = time.time()
-        H = AmgHierarchy(d_rp, d_ci, d_V, vcycle_prec=prec)
+        H = AmgHierarchy(d_rp, d_ci, d_V, vcycle_prec=prec, autotune=1)
         torch.cuda.synchronize()
         setup_ms = (time.time() - t0) * 1e3
         ms, cols, info = time_solves(H, d_B, X, args.tol, args.batched_steps, 1)

@@ -161,9 +161,13 @@ struct BatchHead {
 struct BatchLevel {
   DBuf<double> x64, b64, r64;
   DBuf<float> x32, b32, r32;
+  // row streams per XCD of the wide sweeps over A, P and R of this level
+  // (0: one contiguous row range per workgroup)
+  int spxA = 0, spxP = 0, spxR = 0;
 };
 struct Batch {
   int W = 0;
+  int tuned_W = 0;  // width the stream counts were chosen for
   DBuf<double> r, z, p, p2, q, partials;
   DBuf<WCtl> ctl;
   DBuf<BatchHead> head;
@@ -238,6 +242,11 @@ bool values_equal(const Hierarchy& H, const double* d_val, int* d_flags, int* h_
 void coarse_setup(Hierarchy& H, hipStream_t s);
 // solve.hip
 void alloc_solve_workspace(Hierarchy& H);
+// Persistent tuning cache (in memory and, when AMG_TUNE_CACHE names a file,
+// in a text file): lookup and record of a launch choice under a key.
+bool tune_lookup(const std::string& key, Shape* out);
+void tune_record(const std::string& key, const Shape& sh);
+
 amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int nrhs,
                      amg_info* info, hipStream_t s);
 void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s);

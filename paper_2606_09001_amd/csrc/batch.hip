@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <type_traits>
 
@@ -60,6 +61,7 @@ template <bool SYS, class T, class BT>
 struct WResid {
   using PT = T;
   static constexpr int NRED = 0;
+  __device__ void bind(int) {}
   const T* v;
   const BT* b;
   const T* x;
@@ -78,6 +80,7 @@ template <bool SYS, class RT, class T>
 struct WRestrict {
   using PT = T;
   static constexpr int NRED = 0;
+  __device__ void bind(int) {}
   const RT* v;
   const T* x;
   T* y;
@@ -103,6 +106,7 @@ template <bool SYS, class RT, class T>
 struct WProlong {
   using PT = T;
   static constexpr int NRED = 0;
+  __device__ void bind(int) {}
   const RT* v;
   const T* xc;
   T* x;
@@ -122,6 +126,7 @@ template <bool SYS, class T, class BT, class OT, int RED>
 struct WPost {
   using PT = T;
   static constexpr int NRED = RED;
+  __device__ void bind(int) {}
   const T* v;
   const T* sw;
   const BT* b;
@@ -167,10 +172,15 @@ struct WSpmvXpay {
   };
   // both operands are always loaded (no divergent branch around a load);
   // a column that (re)starts takes p' = z
-  __device__ double dir(int64_t e, int c) const {
-    const WCtl& cc = ctl[c];
+  double beta_c = 0.0;  // this lane's column scalars, read once by bind()
+  int first_c = 1;
+  __device__ void bind(int c) {
+    beta_c = ctl[c].beta;
+    first_c = ctl[c].first;
+  }
+  __device__ double dir(int64_t e, int) const {
     const double zz = z[e], pp = p[e];
-    return cc.first ? zz : zz + cc.beta * pp;
+    return first_c ? zz : zz + beta_c * pp;
   }
   __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * dir((int64_t)j * W + c, c); }
   __device__ Row row_in(int row, int c) const { return {dir((int64_t)row * W + c, c)}; }
@@ -187,6 +197,7 @@ template <bool SYS>
 struct WTrueResid {
   using PT = double;
   static constexpr int NRED = 1;
+  __device__ void bind(int) {}
   const double* v;
   const double* x;
   const double* b;
@@ -226,9 +237,36 @@ __device__ inline void publish_w(double (&d)[NRED > 0 ? NRED : 1], int W, double
   }
 }
 
+// Row-group schedule of a wide sweep.  Workgroups are dispatched round-robin
+// over the 8 XCDs; each XCD owns one contiguous eighth of the row groups,
+// split into `spx` streams.  The workgroups of a stream (a team) take its
+// groups in turn, so a stream advances as one front: the rows a front
+// gathers from (its neighbours at short index distance) stay in that XCD's
+// L2 while the front passes.  spx = G/8 gives every workgroup a contiguous
+// range of its own.
+struct WideSched {
+  int64_t first, end;
+  int step;
+};
+
+__device__ inline WideSched wide_sched(int64_t groups, int spx) {
+  const int G = gridDim.x;
+  if ((G & 7) == 0 && spx > 0 && ((G >> 3) % spx) == 0) {
+    const int gx = G >> 3;
+    const int team = gx / spx;
+    const int xcd = blockIdx.x & 7, w = blockIdx.x >> 3;
+    const int stream = xcd * spx + w / team, member = w % team;
+    const int64_t ns = 8ll * spx;
+    const int64_t s0 = groups * stream / ns, s1 = groups * (stream + 1) / ns;
+    return {s0 + member, s1, team};
+  }
+  const int lb = logical_block_w();
+  return {groups * lb / G, groups * (lb + 1) / G, 1};
+}
+
 template <int LW, class Op>
-__global__ void __launch_bounds__(kBlock) k_wide(int n, int W, const int* __restrict__ rp,
-                                                 const int* __restrict__ ci, Op op,
+__global__ void __launch_bounds__(kBlock) k_wide(int n, int W, int spx, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci, Op op_in,
                                                  const BatchHead* __restrict__ head, double* __restrict__ partials) {
   if ((head && head->ndone >= head->W) || n <= 0) return;
   using PT = typename Op::PT;
@@ -236,22 +274,23 @@ __global__ void __launch_bounds__(kBlock) k_wide(int n, int W, const int* __rest
   constexpr int U = 8;
   const int lr = threadIdx.x / LW, c = threadIdx.x & (LW - 1);
   const int64_t groups = ((int64_t)n + RB - 1) / RB;
-  const int lb = logical_block_w();
-  const int g0 = (int)(groups * lb / gridDim.x), g1 = (int)(groups * (lb + 1) / gridDim.x);
+  const WideSched sc = wide_sched(groups, spx);
   double d[Op::NRED > 0 ? Op::NRED : 1] = {};
   const int cc = min(c, W - 1);
+  Op op = op_in;  // per-lane copy holding the column's scalars
+  op.bind(cc);
   // row pointers of the next row group are loaded one iteration ahead, and
   // the row's own operands together with its first entries, so that one
   // iteration waits on memory twice (entries, then gathers)
   int k0 = 0, k1 = 0;
-  if (g0 < g1) {
-    const int r = min(g0 * RB + lr, n - 1);
+  if (sc.first < sc.end) {
+    const int r = (int)min<int64_t>(sc.first * RB + lr, n - 1);
     k0 = rp[r];
     k1 = rp[r + 1];
   }
-  for (int g = g0; g < g1; ++g) {
-    const int row = g * RB + lr;
-    const int rn = min(row + RB, n - 1);
+  for (int64_t g = sc.first; g < sc.end; g += sc.step) {
+    const int row = (int)(g * RB + lr);
+    const int rn = min(row + sc.step * RB, n - 1);
     const int kn0 = rp[rn], kn1 = rp[rn + 1];
     const typename Op::Row in = op.row_in(min(row, n - 1), cc);
     PT s = 0;
@@ -551,11 +590,11 @@ __global__ void __launch_bounds__(kBlock) k_wpattern_grad(int n, int W, const in
   }
 
 template <class Op>
-int wsweep(int LWv, int n, int W, const int* rp, const int* ci, const Op& op, const BatchHead* head,
+int wsweep(int LWv, int spx, int n, int W, const int* rp, const int* ci, const Op& op, const BatchHead* head,
            double* partials, hipStream_t s) {
   const int grid = wide_grid(n, LWv);
-  AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, rp, ci, op, head,
-                                          partials));
+  AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, rp, ci, op,
+                                          head, partials));
   return grid;
 }
 
@@ -581,27 +620,28 @@ struct WB<float> {
 };
 
 template <bool SYS, class T>
-void w_restrict(Hierarchy& H, Level& L, int LWv, int W, const T* r, T* bc, const T* swc, T* xc, hipStream_t s) {
+void w_restrict(Hierarchy& H, Level& L, int LWv, int spx, int W, const T* r, T* bc, const T* swc, T* xc,
+                hipStream_t s) {
   const BatchHead* hd = H.bt.head.p;
   if constexpr (std::is_same<T, double>::value) {
-    wsweep(LWv, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, double, T>{L.rv.p, r, bc, swc, xc, W}, hd, nullptr, s);
+    wsweep(LWv, spx, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, double, T>{L.rv.p, r, bc, swc, xc, W}, hd, nullptr, s);
   } else if (H.bf16()) {
-    wsweep(LWv, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, uint16_t, T>{L.rbf.p, r, bc, swc, xc, W}, hd, nullptr,
+    wsweep(LWv, spx, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, uint16_t, T>{L.rbf.p, r, bc, swc, xc, W}, hd, nullptr,
            s);
   } else {
-    wsweep(LWv, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, float, T>{L.rv32.p, r, bc, swc, xc, W}, hd, nullptr, s);
+    wsweep(LWv, spx, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, float, T>{L.rv32.p, r, bc, swc, xc, W}, hd, nullptr, s);
   }
 }
 
 template <bool SYS, class T>
-void w_prolong(Hierarchy& H, Level& L, int LWv, int W, const T* xc, T* x, hipStream_t s) {
+void w_prolong(Hierarchy& H, Level& L, int LWv, int spx, int W, const T* xc, T* x, hipStream_t s) {
   const BatchHead* hd = H.bt.head.p;
   if constexpr (std::is_same<T, double>::value) {
-    wsweep(LWv, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, double, T>{L.pv.p, xc, x, W}, hd, nullptr, s);
+    wsweep(LWv, spx, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, double, T>{L.pv.p, xc, x, W}, hd, nullptr, s);
   } else if (H.bf16()) {
-    wsweep(LWv, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, uint16_t, T>{L.pbf.p, xc, x, W}, hd, nullptr, s);
+    wsweep(LWv, spx, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, uint16_t, T>{L.pbf.p, xc, x, W}, hd, nullptr, s);
   } else {
-    wsweep(LWv, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, float, T>{L.pv32.p, xc, x, W}, hd, nullptr, s);
+    wsweep(LWv, spx, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, float, T>{L.pv32.p, xc, x, W}, hd, nullptr, s);
   }
 }
 
@@ -620,15 +660,15 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
     Level& L = H.lv[l];
     BatchLevel& BL = B.lv[l];
     if (l == 0)
-      wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, double>{WB<T>::v(L), r0, WB<T>::x(BL), WB<T>::r(BL), W}, hd,
+      wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, double>{WB<T>::v(L), r0, WB<T>::x(BL), WB<T>::r(BL), W}, hd,
              nullptr, s);
     else
-      wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W},
+      wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W},
              hd, nullptr, s);
     Level& Ln = H.lv[l + 1];
     BatchLevel& BN = B.lv[l + 1];
     const bool coarsest = (l + 1 == nl - 1);
-    w_restrict<SYS, T>(H, L, LWv, W, WB<T>::r(BL), WB<T>::b(BN), coarsest ? nullptr : WB<T>::sw(Ln),
+    w_restrict<SYS, T>(H, L, LWv, BL.spxR, W, WB<T>::r(BL), WB<T>::b(BN), coarsest ? nullptr : WB<T>::sw(Ln),
                        coarsest ? nullptr : WB<T>::x(BN), s);
   }
   {
@@ -641,26 +681,26 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = H.lv[l];
     BatchLevel& BL = B.lv[l];
-    w_prolong<SYS, T>(H, L, LWv, W, res, WB<T>::x(BL), s);
+    w_prolong<SYS, T>(H, L, LWv, BL.spxP, W, res, WB<T>::x(BL), s);
     const T* vv = WB<T>::v(L);
     const T* sw = WB<T>::sw(L);
     if (l == 0) {
       int np = 0;
       if (red == 2)
-        np = wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 2>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
+        np = wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 2>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
                     hd, part, s);
       else if (red == 1)
-        np = wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 1>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
+        np = wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 1>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
                     hd, part, s);
       else
-        wsweep(LWv, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 0>{vv, sw, r0, WB<T>::x(BL), z0, q, W}, hd,
+        wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 0>{vv, sw, r0, WB<T>::x(BL), z0, q, W}, hd,
                nullptr, s);
       if (red == 2)
         hipLaunchKernelGGL(k_wfin_beta<2>, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, np);
       else if (red == 1)
         hipLaunchKernelGGL(k_wfin_beta<1>, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, np);
     } else {
-      wsweep(LWv, L.n, W, L.rp.p, L.ci.p,
+      wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p,
              WPost<SYS, T, T, T, 0>{vv, sw, WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), nullptr, W}, hd, nullptr, s);
       res = WB<T>::r(BL);
     }
@@ -689,6 +729,7 @@ void ensure_batch(Hierarchy& H, int W) {
   AMG_HIP(hipMemset(B.ctl.p, 0, sizeof(WCtl) * W));
   B.lv.clear();
   B.lv.resize(H.lv.size());
+  B.tuned_W = 0;
   for (size_t l = 0; l < H.lv.size(); ++l) {
     const int64_t nl = (int64_t)H.lv[l].n * W;
     if (H.fp32()) {
@@ -710,11 +751,115 @@ void read_batch(Hierarchy& H, int W, hipStream_t s) {
   AMG_HIP(hipStreamSynchronize(s));
 }
 
+// ------------------------------------------------------ stream-count tuner
+//
+// The number of row streams per XCD of each wide sweep (A, P and R of every
+// level) is a locality choice: it does not change which operations a row
+// performs.  Without autotuning every workgroup takes a contiguous range;
+// with it, each candidate is timed with HIP events on the level's own
+// operands and the fastest is kept and recorded in the tuning cache.
+
+template <class Op>
+double time_wide(int LWv, int spx, int n, int W, const int* rp, const int* ci, const Op& op, hipStream_t s,
+                 hipEvent_t e0, hipEvent_t e1) {
+  wsweep(LWv, spx, n, W, rp, ci, op, nullptr, nullptr, s);
+  AMG_HIP(hipEventRecord(e0, s));
+  constexpr int reps = 3;
+  for (int r = 0; r < reps; ++r) wsweep(LWv, spx, n, W, rp, ci, op, nullptr, nullptr, s);
+  AMG_HIP(hipEventRecord(e1, s));
+  AMG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  return ms / reps;
+}
+
+std::vector<int> spx_candidates(int n, int LWv) {
+  const int gx = wide_grid(n, LWv) / 8;
+  std::vector<int> out{0};
+  if (wide_grid(n, LWv) % 8 != 0 || gx < 2) return out;
+  for (int spx : {64, 32, 16, 8, 4, 2, 1})
+    if (spx < gx && gx % spx == 0) out.push_back(spx);
+  return out;
+}
+
+template <class Op>
+int pick_spx(Hierarchy& H, const char* kind, int W, int n, int nnz, const int* rp, const int* ci, const Op& op,
+             hipStream_t s) {
+  char key[160];
+  std::snprintf(key, sizeof key, "wide%s:n%d:nnz%d:W%d:S%d:p%d:t%d", kind, n, nnz, W, H.S, H.prm.vcycle_prec,
+                H.fp32() && H.prm.transfer_bf16);
+  Shape sh;
+  if (tune_lookup(key, &sh)) return sh.stream;
+  const int LWv = pow2_ceil(W);
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  int best = 0;
+  double tbest = 1e300;
+  for (int spx : spx_candidates(n, LWv)) {
+    const double t = time_wide(LWv, spx, n, W, rp, ci, op, s, e0, e1);
+    if (t < tbest) {
+      tbest = t;
+      best = spx;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  sh = Shape{};
+  sh.stream = best;
+  tune_record(key, sh);
+  return best;
+}
+
+template <bool SYS, class T>
+void tune_wide(Hierarchy& H, int W, hipStream_t s) {
+  Batch& B = H.bt;
+  if (B.tuned_W == W) return;
+  B.tuned_W = W;
+  for (auto& BL : B.lv) BL.spxA = BL.spxP = BL.spxR = 0;
+  if (!H.prm.autotune) return;
+  const int nl = (int)H.lv.size();
+  for (int l = 0; l < nl; ++l) {
+    BatchLevel& BL = B.lv[l];
+    T* x = WB<T>::x(BL);
+    T* b = WB<T>::b(BL);
+    T* r = WB<T>::r(BL);
+    const int64_t len = (int64_t)H.lv[l].n * W;
+    AMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * len, s));
+    AMG_HIP(hipMemsetAsync(b, 0, sizeof(T) * len, s));
+  }
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level& L = H.lv[l];
+    BatchLevel& BL = B.lv[l];
+    BatchLevel& BN = B.lv[l + 1];
+    BL.spxA = pick_spx(H, "A", W, L.n, (int)L.nnz, L.rp.p, L.ci.p,
+                       WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W}, s);
+    if constexpr (std::is_same<T, double>::value) {
+      BL.spxP = pick_spx(H, "P", W, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
+                         WProlong<SYS, double, T>{L.pv.p, WB<T>::x(BN), WB<T>::r(BL), W}, s);
+      BL.spxR = pick_spx(H, "R", W, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
+                         WRestrict<SYS, double, T>{L.rv.p, WB<T>::x(BL), WB<T>::b(BN), nullptr, nullptr, W}, s);
+    } else if (H.bf16()) {
+      BL.spxP = pick_spx(H, "P", W, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
+                         WProlong<SYS, uint16_t, T>{L.pbf.p, WB<T>::x(BN), WB<T>::r(BL), W}, s);
+      BL.spxR = pick_spx(H, "R", W, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
+                         WRestrict<SYS, uint16_t, T>{L.rbf.p, WB<T>::x(BL), WB<T>::b(BN), nullptr, nullptr, W}, s);
+    } else {
+      BL.spxP = pick_spx(H, "P", W, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
+                         WProlong<SYS, float, T>{L.pv32.p, WB<T>::x(BN), WB<T>::r(BL), W}, s);
+      BL.spxR = pick_spx(H, "R", W, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
+                         WRestrict<SYS, float, T>{L.rv32.p, WB<T>::x(BL), WB<T>::b(BN), nullptr, nullptr, W}, s);
+    }
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
 template <bool SYS, class T>
 amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int W,
                            amg_info* info, hipStream_t caller) {
   auto t0 = std::chrono::steady_clock::now();
   ensure_batch(H, W);
+  tune_wide<SYS, T>(H, W, caller);
   Batch& B = H.bt;
   Level& L0 = H.lv[0];
   const int n = H.n;
@@ -749,7 +894,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
   T* x0 = WB<T>::x(B.lv[0]);
   // one batched iteration (columns flagged `first` take p = z on device)
   auto iteration = [&](int c, hipStream_t stq) {
-    const int np = wsweep(LWv, n, W, L0.rp.p, L0.ci.p, WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W},
+    const int np = wsweep(LWv, B.lv[0].spxA, n, W, L0.rp.p, L0.ci.p, WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W},
                           B.head.p, part, stq);
     hipLaunchKernelGGL(k_wfin_alpha, dim3(W), dim3(kWFin), 0, stq, B.ctl.p, B.head.p, part, W, np);
     AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wupdate<LW, SYS, T>), dim3(gw), dim3(kBlock), 0, stq, n, W, d_x,
@@ -808,7 +953,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
       }
     }
     // true residuals of every column
-    const int np = wsweep(LWv, n, W, L0.rp.p, L0.ci.p, WTrueResid<SYS>{L0.v.p, d_x, d_b, B.r.p, W}, nullptr, part, s);
+    const int np = wsweep(LWv, B.lv[0].spxA, n, W, L0.rp.p, L0.ci.p, WTrueResid<SYS>{L0.v.p, d_x, d_b, B.r.p, W}, nullptr, part, s);
     hipLaunchKernelGGL(k_wfin_trr, dim3(W), dim3(kWFin), 0, s, B.ctl.p, part, W, np);
     read_batch(H, W, s);
     int nre = 0;

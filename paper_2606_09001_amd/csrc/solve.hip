@@ -1027,6 +1027,21 @@ struct TuneOp {
 
 }  // namespace
 
+bool tune_lookup(const std::string& key, Shape* out) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load();
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+void tune_record(const std::string& key, const Shape& sh) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load();
+  tune_store(key, sh);
+}
+
 void choose_shapes(Hierarchy& H, hipStream_t s) {
   const bool f32 = H.fp32();
   for (size_t l = 0; l < H.lv.size(); ++l) {
