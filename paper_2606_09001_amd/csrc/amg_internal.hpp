@@ -164,6 +164,8 @@ struct BatchLevel {
   // row streams per XCD of the wide sweeps over A, P and R of this level
   // (0: one contiguous row range per workgroup)
   int spxA = 0, spxP = 0, spxR = 0;
+  // rows per LDS-staged block of the wide sweeps over A, P and R (0: direct)
+  int brA = 0, brP = 0, brR = 0;
 };
 struct Batch {
   int W = 0;

@@ -18,6 +18,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <map>
 #include <type_traits>
 
 #include "amg_internal.hpp"
@@ -60,6 +62,8 @@ __device__ inline V row_at(const V* v, int i, int c, int W) {
 template <bool SYS, class T, class BT>
 struct WResid {
   using PT = T;
+  using VT = T;
+  static constexpr bool kSys = SYS;
   static constexpr int NRED = 0;
   __device__ void bind(int) {}
   const T* v;
@@ -67,10 +71,10 @@ struct WResid {
   const T* x;
   T* r;
   int W;
+  __device__ PT prod_v(VT a, int j, int c) const { return a * x[(int64_t)j * W + c]; }
   struct Row {
     T b;
   };
-  __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
   __device__ Row row_in(int row, int c) const { return {(T)b[(int64_t)row * W + c]}; }
   __device__ void epi(int row, int c, PT s, const Row& a, double*) const { r[(int64_t)row * W + c] = a.b - s; }
 };
@@ -79,6 +83,8 @@ struct WResid {
 template <bool SYS, class RT, class T>
 struct WRestrict {
   using PT = T;
+  using VT = RT;
+  static constexpr bool kSys = SYS;
   static constexpr int NRED = 0;
   __device__ void bind(int) {}
   const RT* v;
@@ -87,9 +93,7 @@ struct WRestrict {
   const T* swc;
   T* xc;
   int W;
-  __device__ PT prod(int k, int j, int c) const {
-    return (T)ValCvt<RT>::f(val_at<SYS>(v, k, c, W)) * x[(int64_t)j * W + c];
-  }
+  __device__ PT prod_v(VT a, int j, int c) const { return (T)ValCvt<RT>::f(a) * x[(int64_t)j * W + c]; }
   struct Row {
     T w;
   };
@@ -105,15 +109,15 @@ struct WRestrict {
 template <bool SYS, class RT, class T>
 struct WProlong {
   using PT = T;
+  using VT = RT;
+  static constexpr bool kSys = SYS;
   static constexpr int NRED = 0;
   __device__ void bind(int) {}
   const RT* v;
   const T* xc;
   T* x;
   int W;
-  __device__ PT prod(int k, int j, int c) const {
-    return (T)ValCvt<RT>::f(val_at<SYS>(v, k, c, W)) * xc[(int64_t)j * W + c];
-  }
+  __device__ PT prod_v(VT a, int j, int c) const { return (T)ValCvt<RT>::f(a) * xc[(int64_t)j * W + c]; }
   struct Row {
     T x;
   };
@@ -125,6 +129,8 @@ struct WProlong {
 template <bool SYS, class T, class BT, class OT, int RED>
 struct WPost {
   using PT = T;
+  using VT = T;
+  static constexpr bool kSys = SYS;
   static constexpr int NRED = RED;
   __device__ void bind(int) {}
   const T* v;
@@ -134,7 +140,7 @@ struct WPost {
   OT* out;
   const double* q;
   int W;
-  __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
+  __device__ PT prod_v(VT a, int j, int c) const { return a * x[(int64_t)j * W + c]; }
   struct Row {
     BT b;
     T x, w;
@@ -159,6 +165,8 @@ struct WPost {
 template <bool SYS>
 struct WSpmvXpay {
   using PT = double;
+  using VT = double;
+  static constexpr bool kSys = SYS;
   static constexpr int NRED = 1;
   const double* v;
   const double* z;
@@ -182,7 +190,7 @@ struct WSpmvXpay {
     const double zz = z[e], pp = p[e];
     return first_c ? zz : zz + beta_c * pp;
   }
-  __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * dir((int64_t)j * W + c, c); }
+  __device__ PT prod_v(VT a, int j, int c) const { return a * dir((int64_t)j * W + c, c); }
   __device__ Row row_in(int row, int c) const { return {dir((int64_t)row * W + c, c)}; }
   __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
     const int64_t e = (int64_t)row * W + c;
@@ -196,6 +204,8 @@ struct WSpmvXpay {
 template <bool SYS>
 struct WTrueResid {
   using PT = double;
+  using VT = double;
+  static constexpr bool kSys = SYS;
   static constexpr int NRED = 1;
   __device__ void bind(int) {}
   const double* v;
@@ -206,7 +216,7 @@ struct WTrueResid {
   struct Row {
     double b;
   };
-  __device__ PT prod(int k, int j, int c) const { return val_at<SYS>(v, k, c, W) * x[(int64_t)j * W + c]; }
+  __device__ PT prod_v(VT a, int j, int c) const { return a * x[(int64_t)j * W + c]; }
   __device__ Row row_in(int row, int c) const { return {b[(int64_t)row * W + c]}; }
   __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
     const double ri = a.b - s;
@@ -303,7 +313,10 @@ __global__ void __launch_bounds__(kBlock) k_wide(int n, int W, int spx, const in
         for (int e = 0; e < U; ++e) cols[e] = ci[min(kb + e, k1 - 1)];
         PT pr[U];
 #pragma unroll
-        for (int e = 0; e < U; ++e) pr[e] = op.prod(min(kb + e, k1 - 1), cols[e], c);
+        for (int e = 0; e < U; ++e) {
+          const int k = min(kb + e, k1 - 1);
+          pr[e] = op.prod_v(val_at<Op::kSys>(op.v, k, cc, W), cols[e], c);
+        }
 #pragma unroll
         for (int e = 0; e < U; ++e) s = kb + e < k1 ? s + pr[e] : s;
       }
@@ -589,13 +602,146 @@ __global__ void __launch_bounds__(kBlock) k_wpattern_grad(int n, int W, const in
     default: { constexpr int LW = 64; __VA_ARGS__; } break; \
   }
 
+// Staged wide sweep: per block of `br` rows, the workgroup loads the row
+// pointers, the column indices and (shared-value form) the values with
+// coalesced loads into LDS; each group of LW lanes then reads its row's
+// entries from LDS and gathers x[j][c] for its column.  Blocks are scheduled
+// like the row groups of k_wide (streams per XCD); the grid is the number of
+// workgroups that are resident at once.
+constexpr int kWCap = 1024;  // staged entries per block
+
+template <int LW, class Op>
+__global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int br, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, Op op_in,
+                                                    const BatchHead* __restrict__ head,
+                                                    double* __restrict__ partials) {
+  if ((head && head->ndone >= head->W) || n <= 0) return;
+  using PT = typename Op::PT;
+  using VT = typename Op::VT;
+  constexpr bool SYS = Op::kSys;
+  constexpr int RB = kBlock / LW;
+  constexpr int U = kWCap / kBlock;
+  __shared__ int s_rp[kBlock + 1];
+  __shared__ int s_ci[kWCap];
+  __shared__ VT s_v[SYS ? 1 : kWCap];
+  const int lr = threadIdx.x / LW, c = threadIdx.x & (LW - 1);
+  const int cc = min(c, W - 1);
+  Op op = op_in;
+  op.bind(cc);
+  const int64_t blocks = ((int64_t)n + br - 1) / br;
+  const WideSched sc = wide_sched(blocks, spx);
+  double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  for (int64_t blk = sc.first; blk < sc.end; blk += sc.step) {
+    const int r0 = (int)(blk * br);
+    __syncthreads();  // the previous block's entries have been read
+    for (int t = threadIdx.x; t <= br; t += kBlock) s_rp[t] = rp[min(r0 + t, n)];
+    __syncthreads();
+    const int k0 = s_rp[0], nk = s_rp[br] - k0;
+    if (nk > 0) {
+      int cv[U];
+      VT vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int jj = k0 + min((int)threadIdx.x + u * kBlock, nk - 1);
+        cv[u] = ci[jj];
+        if constexpr (!SYS) vv[u] = op.v[jj];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = threadIdx.x + u * kBlock;
+        if (j < nk) {
+          s_ci[j] = cv[u];
+          if constexpr (!SYS) s_v[j] = vv[u];
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = lr; q < br; q += RB) {
+      const int row = r0 + q;
+      const typename Op::Row in = op.row_in(min(row, n - 1), cc);
+      PT acc = 0;
+      if (row < n && c < W) {
+        const int a = s_rp[q] - k0, e = s_rp[q + 1] - k0;
+        for (int kb = a; kb < e; kb += 8) {
+          PT pr[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = min(kb + u, e - 1);
+            VT val;
+            if constexpr (SYS) val = op.v[(int64_t)(k0 + k) * W + c];
+            else val = s_v[k];
+            pr[u] = op.prod_v(val, s_ci[k], c);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = kb + u < e ? acc + pr[u] : acc;
+        }
+        op.epi(row, c, acc, in, d);
+      }
+    }
+  }
+  publish_w<LW, Op::NRED>(d, W, partials);
+}
+
+// Workgroups of `kernel` resident at once on the device (a multiple of 8).
+int resident_grid(const void* kernel) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  static int ncu = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(kernel);
+  if (it != cache.end()) return it->second;
+  if (!ncu) {
+    int dev = 0;
+    AMG_HIP(hipGetDevice(&dev));
+    AMG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  int per_cu = 0;
+  AMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
+  int g = std::max(1, per_cu) * std::max(1, ncu);
+  g = std::max(8, std::min(g, kWGrid) / 8 * 8);
+  cache[kernel] = g;
+  return g;
+}
+
+// br > 0: staged kernel with br rows per block; 0: direct kernel.
 template <class Op>
-int wsweep(int LWv, int spx, int n, int W, const int* rp, const int* ci, const Op& op, const BatchHead* head,
-           double* partials, hipStream_t s) {
-  const int grid = wide_grid(n, LWv);
-  AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, rp, ci, op,
-                                          head, partials));
+int wsweep(int LWv, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op,
+           const BatchHead* head, double* partials, hipStream_t s) {
+  int grid = 0;
+  if (br > 0) {
+    AMG_DISPATCH_LW(LWv, {
+      const void* kp = reinterpret_cast<const void*>(&k_wide_st<LW, Op>);
+      grid = std::min<int64_t>(resident_grid(kp), std::max<int64_t>(8, ((int64_t)n + br - 1) / br / 8 * 8));
+      hipLaunchKernelGGL((k_wide_st<LW, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, br, rp, ci, op, head,
+                         partials);
+    });
+  } else {
+    grid = wide_grid(n, LWv);
+    AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, rp, ci,
+                                            op, head, partials));
+  }
   return grid;
+}
+
+std::vector<int> host_rows(const DBuf<int>& rp, int n) {
+  std::vector<int> h(n + 1);
+  AMG_HIP(hipMemcpy(h.data(), rp.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+  return h;
+}
+
+// Rows per staged block for a matrix: the largest power of two from the
+// lane group's rows per step up to 256 whose blocks all fit the staging
+// buffer; 0 when even the smallest does not (direct kernel).
+int wide_block_rows(const std::vector<int>& rp, int n, int LWv) {
+  const int rb = kBlock / LWv;
+  int best = 0;
+  for (int br = rb; br <= kBlock; br <<= 1) {
+    int mx = 0;
+    for (int r0 = 0; r0 < n; r0 += br) mx = std::max(mx, rp[std::min(r0 + br, n)] - rp[r0]);
+    if (mx > kWCap) break;
+    best = br;
+  }
+  return best;
 }
 
 template <class T>
@@ -620,28 +766,28 @@ struct WB<float> {
 };
 
 template <bool SYS, class T>
-void w_restrict(Hierarchy& H, Level& L, int LWv, int spx, int W, const T* r, T* bc, const T* swc, T* xc,
+void w_restrict(Hierarchy& H, Level& L, int LWv, int spx, int br, int W, const T* r, T* bc, const T* swc, T* xc,
                 hipStream_t s) {
   const BatchHead* hd = H.bt.head.p;
   if constexpr (std::is_same<T, double>::value) {
-    wsweep(LWv, spx, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, double, T>{L.rv.p, r, bc, swc, xc, W}, hd, nullptr, s);
+    wsweep(LWv, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, double, T>{L.rv.p, r, bc, swc, xc, W}, hd, nullptr, s);
   } else if (H.bf16()) {
-    wsweep(LWv, spx, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, uint16_t, T>{L.rbf.p, r, bc, swc, xc, W}, hd, nullptr,
+    wsweep(LWv, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, uint16_t, T>{L.rbf.p, r, bc, swc, xc, W}, hd, nullptr,
            s);
   } else {
-    wsweep(LWv, spx, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, float, T>{L.rv32.p, r, bc, swc, xc, W}, hd, nullptr, s);
+    wsweep(LWv, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, float, T>{L.rv32.p, r, bc, swc, xc, W}, hd, nullptr, s);
   }
 }
 
 template <bool SYS, class T>
-void w_prolong(Hierarchy& H, Level& L, int LWv, int spx, int W, const T* xc, T* x, hipStream_t s) {
+void w_prolong(Hierarchy& H, Level& L, int LWv, int spx, int br, int W, const T* xc, T* x, hipStream_t s) {
   const BatchHead* hd = H.bt.head.p;
   if constexpr (std::is_same<T, double>::value) {
-    wsweep(LWv, spx, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, double, T>{L.pv.p, xc, x, W}, hd, nullptr, s);
+    wsweep(LWv, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, double, T>{L.pv.p, xc, x, W}, hd, nullptr, s);
   } else if (H.bf16()) {
-    wsweep(LWv, spx, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, uint16_t, T>{L.pbf.p, xc, x, W}, hd, nullptr, s);
+    wsweep(LWv, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, uint16_t, T>{L.pbf.p, xc, x, W}, hd, nullptr, s);
   } else {
-    wsweep(LWv, spx, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, float, T>{L.pv32.p, xc, x, W}, hd, nullptr, s);
+    wsweep(LWv, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, float, T>{L.pv32.p, xc, x, W}, hd, nullptr, s);
   }
 }
 
@@ -660,15 +806,15 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
     Level& L = H.lv[l];
     BatchLevel& BL = B.lv[l];
     if (l == 0)
-      wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, double>{WB<T>::v(L), r0, WB<T>::x(BL), WB<T>::r(BL), W}, hd,
+      wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, double>{WB<T>::v(L), r0, WB<T>::x(BL), WB<T>::r(BL), W}, hd,
              nullptr, s);
     else
-      wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W},
+      wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W},
              hd, nullptr, s);
     Level& Ln = H.lv[l + 1];
     BatchLevel& BN = B.lv[l + 1];
     const bool coarsest = (l + 1 == nl - 1);
-    w_restrict<SYS, T>(H, L, LWv, BL.spxR, W, WB<T>::r(BL), WB<T>::b(BN), coarsest ? nullptr : WB<T>::sw(Ln),
+    w_restrict<SYS, T>(H, L, LWv, BL.spxR, BL.brR, W, WB<T>::r(BL), WB<T>::b(BN), coarsest ? nullptr : WB<T>::sw(Ln),
                        coarsest ? nullptr : WB<T>::x(BN), s);
   }
   {
@@ -681,26 +827,26 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = H.lv[l];
     BatchLevel& BL = B.lv[l];
-    w_prolong<SYS, T>(H, L, LWv, BL.spxP, W, res, WB<T>::x(BL), s);
+    w_prolong<SYS, T>(H, L, LWv, BL.spxP, BL.brP, W, res, WB<T>::x(BL), s);
     const T* vv = WB<T>::v(L);
     const T* sw = WB<T>::sw(L);
     if (l == 0) {
       int np = 0;
       if (red == 2)
-        np = wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 2>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
+        np = wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 2>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
                     hd, part, s);
       else if (red == 1)
-        np = wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 1>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
+        np = wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 1>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
                     hd, part, s);
       else
-        wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 0>{vv, sw, r0, WB<T>::x(BL), z0, q, W}, hd,
+        wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 0>{vv, sw, r0, WB<T>::x(BL), z0, q, W}, hd,
                nullptr, s);
       if (red == 2)
         hipLaunchKernelGGL(k_wfin_beta<2>, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, np);
       else if (red == 1)
         hipLaunchKernelGGL(k_wfin_beta<1>, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, np);
     } else {
-      wsweep(LWv, BL.spxA, L.n, W, L.rp.p, L.ci.p,
+      wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
              WPost<SYS, T, T, T, 0>{vv, sw, WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), nullptr, W}, hd, nullptr, s);
       res = WB<T>::r(BL);
     }
@@ -760,12 +906,12 @@ void read_batch(Hierarchy& H, int W, hipStream_t s) {
 // operands and the fastest is kept and recorded in the tuning cache.
 
 template <class Op>
-double time_wide(int LWv, int spx, int n, int W, const int* rp, const int* ci, const Op& op, hipStream_t s,
+double time_wide(int LWv, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op, hipStream_t s,
                  hipEvent_t e0, hipEvent_t e1) {
-  wsweep(LWv, spx, n, W, rp, ci, op, nullptr, nullptr, s);
+  wsweep(LWv, spx, br, n, W, rp, ci, op, nullptr, nullptr, s);
   AMG_HIP(hipEventRecord(e0, s));
   constexpr int reps = 3;
-  for (int r = 0; r < reps; ++r) wsweep(LWv, spx, n, W, rp, ci, op, nullptr, nullptr, s);
+  for (int r = 0; r < reps; ++r) wsweep(LWv, spx, br, n, W, rp, ci, op, nullptr, nullptr, s);
   AMG_HIP(hipEventRecord(e1, s));
   AMG_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -773,41 +919,52 @@ double time_wide(int LWv, int spx, int n, int W, const int* rp, const int* ci, c
   return ms / reps;
 }
 
-std::vector<int> spx_candidates(int n, int LWv) {
-  const int gx = wide_grid(n, LWv) / 8;
+// Candidate stream counts: divisors of the per-XCD workgroup count (the
+// launch's grid depends on the kernel's residency, so the candidates are
+// taken for the smallest resident grid that divides into 8 XCDs evenly).
+std::vector<int> spx_candidates() {
   std::vector<int> out{0};
-  if (wide_grid(n, LWv) % 8 != 0 || gx < 2) return out;
-  for (int spx : {64, 32, 16, 8, 4, 2, 1})
-    if (spx < gx && gx % spx == 0) out.push_back(spx);
+  for (int spx : {64, 32, 16, 8, 4, 2, 1}) out.push_back(spx);
   return out;
 }
 
+// Picks the kernel form (staged with `br` rows per block, or direct) and the
+// stream count of one wide sweep; returns the stream count and sets br.
 template <class Op>
-int pick_spx(Hierarchy& H, const char* kind, int W, int n, int nnz, const int* rp, const int* ci, const Op& op,
-             hipStream_t s) {
+int pick_spx(Hierarchy& H, const char* kind, int W, int& br, int n, int nnz, const int* rp, const int* ci,
+             const Op& op, hipStream_t s) {
   char key[160];
-  std::snprintf(key, sizeof key, "wide%s:n%d:nnz%d:W%d:S%d:p%d:t%d", kind, n, nnz, W, H.S, H.prm.vcycle_prec,
-                H.fp32() && H.prm.transfer_bf16);
+  std::snprintf(key, sizeof key, "wide%s:n%d:nnz%d:W%d:S%d:p%d:t%d:br%d", kind, n, nnz, W, H.S, H.prm.vcycle_prec,
+                H.fp32() && H.prm.transfer_bf16, br);
   Shape sh;
-  if (tune_lookup(key, &sh)) return sh.stream;
+  if (tune_lookup(key, &sh)) {
+    br = sh.g ? br : 0;
+    return sh.stream;
+  }
   const int LWv = pow2_ceil(W);
   hipEvent_t e0, e1;
   AMG_HIP(hipEventCreate(&e0));
   AMG_HIP(hipEventCreate(&e1));
-  int best = 0;
+  int best = 0, best_br = 0;
   double tbest = 1e300;
-  for (int spx : spx_candidates(n, LWv)) {
-    const double t = time_wide(LWv, spx, n, W, rp, ci, op, s, e0, e1);
-    if (t < tbest) {
-      tbest = t;
-      best = spx;
+  for (int form : {br, 0}) {  // staged (when the blocks fit), then direct
+    for (int spx : spx_candidates()) {
+      const double t = time_wide(LWv, spx, form, n, W, rp, ci, op, s, e0, e1);
+      if (t < tbest) {
+        tbest = t;
+        best = spx;
+        best_br = form;
+      }
     }
+    if (br == 0) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   sh = Shape{};
   sh.stream = best;
+  sh.g = best_br ? 1 : 0;
   tune_record(key, sh);
+  br = best_br;
   return best;
 }
 
@@ -816,7 +973,19 @@ void tune_wide(Hierarchy& H, int W, hipStream_t s) {
   Batch& B = H.bt;
   if (B.tuned_W == W) return;
   B.tuned_W = W;
-  for (auto& BL : B.lv) BL.spxA = BL.spxP = BL.spxR = 0;
+  const int LWv = pow2_ceil(W);
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    BatchLevel& BL = B.lv[l];
+    Level& L = H.lv[l];
+    BL.spxA = BL.spxP = BL.spxR = 0;
+    BL.brA = BL.brP = BL.brR = 0;
+    if (l + 1 == H.lv.size()) continue;
+    BL.brA = wide_block_rows(host_rows(L.rp, L.n), L.n, LWv);
+    BL.brP = wide_block_rows(host_rows(L.prp, L.n), L.n, LWv);
+    BL.brR = wide_block_rows(host_rows(L.rrp, L.nagg), L.nagg, LWv);
+    // per-system values cannot be staged: the direct form is the default there
+    if (SYS && !H.prm.autotune) BL.brA = BL.brP = BL.brR = 0;
+  }
   if (!H.prm.autotune) return;
   const int nl = (int)H.lv.size();
   for (int l = 0; l < nl; ++l) {
@@ -832,22 +1001,22 @@ void tune_wide(Hierarchy& H, int W, hipStream_t s) {
     Level& L = H.lv[l];
     BatchLevel& BL = B.lv[l];
     BatchLevel& BN = B.lv[l + 1];
-    BL.spxA = pick_spx(H, "A", W, L.n, (int)L.nnz, L.rp.p, L.ci.p,
+    BL.spxA = pick_spx(H, "A", W, BL.brA, L.n, (int)L.nnz, L.rp.p, L.ci.p,
                        WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W}, s);
     if constexpr (std::is_same<T, double>::value) {
-      BL.spxP = pick_spx(H, "P", W, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
+      BL.spxP = pick_spx(H, "P", W, BL.brP, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
                          WProlong<SYS, double, T>{L.pv.p, WB<T>::x(BN), WB<T>::r(BL), W}, s);
-      BL.spxR = pick_spx(H, "R", W, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
+      BL.spxR = pick_spx(H, "R", W, BL.brR, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
                          WRestrict<SYS, double, T>{L.rv.p, WB<T>::x(BL), WB<T>::b(BN), nullptr, nullptr, W}, s);
     } else if (H.bf16()) {
-      BL.spxP = pick_spx(H, "P", W, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
+      BL.spxP = pick_spx(H, "P", W, BL.brP, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
                          WProlong<SYS, uint16_t, T>{L.pbf.p, WB<T>::x(BN), WB<T>::r(BL), W}, s);
-      BL.spxR = pick_spx(H, "R", W, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
+      BL.spxR = pick_spx(H, "R", W, BL.brR, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
                          WRestrict<SYS, uint16_t, T>{L.rbf.p, WB<T>::x(BL), WB<T>::b(BN), nullptr, nullptr, W}, s);
     } else {
-      BL.spxP = pick_spx(H, "P", W, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
+      BL.spxP = pick_spx(H, "P", W, BL.brP, L.n, (int)L.pnnz, L.prp.p, L.pci.p,
                          WProlong<SYS, float, T>{L.pv32.p, WB<T>::x(BN), WB<T>::r(BL), W}, s);
-      BL.spxR = pick_spx(H, "R", W, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
+      BL.spxR = pick_spx(H, "R", W, BL.brR, L.nagg, (int)L.pnnz, L.rrp.p, L.rci.p,
                          WRestrict<SYS, float, T>{L.rv32.p, WB<T>::x(BL), WB<T>::b(BN), nullptr, nullptr, W}, s);
     }
   }
@@ -894,7 +1063,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
   T* x0 = WB<T>::x(B.lv[0]);
   // one batched iteration (columns flagged `first` take p = z on device)
   auto iteration = [&](int c, hipStream_t stq) {
-    const int np = wsweep(LWv, B.lv[0].spxA, n, W, L0.rp.p, L0.ci.p, WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W},
+    const int np = wsweep(LWv, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p, WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W},
                           B.head.p, part, stq);
     hipLaunchKernelGGL(k_wfin_alpha, dim3(W), dim3(kWFin), 0, stq, B.ctl.p, B.head.p, part, W, np);
     AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wupdate<LW, SYS, T>), dim3(gw), dim3(kBlock), 0, stq, n, W, d_x,
@@ -953,7 +1122,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
       }
     }
     // true residuals of every column
-    const int np = wsweep(LWv, B.lv[0].spxA, n, W, L0.rp.p, L0.ci.p, WTrueResid<SYS>{L0.v.p, d_x, d_b, B.r.p, W}, nullptr, part, s);
+    const int np = wsweep(LWv, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p, WTrueResid<SYS>{L0.v.p, d_x, d_b, B.r.p, W}, nullptr, part, s);
     hipLaunchKernelGGL(k_wfin_trr, dim3(W), dim3(kWFin), 0, s, B.ctl.p, part, W, np);
     read_batch(H, W, s);
     int nre = 0;
