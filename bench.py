@@ -273,6 +273,8 @@ def main():
     ap.add_argument("--no-kernel-table", action="store_true",
                     help="skip the per-kernel timing passes (used for counter-collection runs)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (multi-RHS / multi-system) section")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="1: launch shapes of the single-system solves chosen by the autotuner at setup")
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--batched-rhs-grid", type=int, default=256)
     ap.add_argument("--batched-sys-grid", type=int, default=96)
@@ -341,7 +343,7 @@ def main():
     hier = {}
     for prec in ("fp64", "fp32"):
         t0 = time.time()
-        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec)
+        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec, autotune=args.autotune)
         torch.cuda.synchronize()
         setup_s = time.time() - t0
         hier[prec] = H

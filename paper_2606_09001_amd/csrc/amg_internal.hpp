@@ -65,7 +65,7 @@ struct DBuf {
 // with `g` lanes; vec (fallback for very long rows): `g` lanes per row read
 // the row directly.
 struct Shape {
-  int stream = 1;
+  int stream = 1;  // 1: CSR-stream, 0: lanes-per-row, 2: sliced (thread per row)
   int g = 1;
   int rows_per_block = 256;
   int grid = 1;
@@ -78,6 +78,21 @@ struct Level {
   DBuf<int> rp, ci;           // A_l pattern
   DBuf<double> v;             // A_l values
   DBuf<float> v32;            // FP32 copy (FP32 cycle)
+  // Sliced copy of A_l for levels of short rows (single system): slices of
+  // 64 consecutive rows, entries stored column-major within a slice (entry j
+  // of the slice's row r at soff[s] + 64 j + r), each row padded with
+  // column -1 / value 0 to the slice's longest row.  sperm maps a sliced
+  // position to its CSR position (-1: padding) for value refresh.
+  bool sell = false;
+  int64_t sell_len = 0;
+  DBuf<int> soff, sci, sperm;
+  DBuf<double> sv;
+  DBuf<float> sv32;
+  // arrays the operator sweeps over A_l read (sliced when present)
+  const int* arp() const { return sell ? soff.p : rp.p; }
+  const int* aci() const { return sell ? sci.p : ci.p; }
+  const double* av() const { return sell ? sv.p : v.p; }
+  const float* av32() const { return sell ? sv32.p : v32.p; }
   DBuf<int> diagpos;          // position of a_ii in row i
   DBuf<double> dinv;          // 1 / a_ii
   DBuf<double> sw;            // smoother weight per row (omega/a_ii or 1/sum|a_ij|)
@@ -272,7 +287,8 @@ constexpr int kMaxGrid = 2048;     // blocks of grid-stride kernels
 constexpr int kStreamCap = 2048;   // nonzeros a stream workgroup stages in LDS
 constexpr int kVecPer = 4;         // vector elements per thread in BLAS1 kernels
 constexpr int kFinBlock = 1024;    // threads of the single-workgroup finalize kernels
-constexpr int kMaxWidth = 64;      // columns of a batched solve (right-hand sides or systems)
+constexpr int kMaxWidth = 64;       // columns of a batched solve (right-hand sides or systems)
+constexpr int kSellMaxW = 8;        // longest row stored in the sliced form
 
 __host__ __device__ inline int pow2_ceil(int x) {
   int g = 1;

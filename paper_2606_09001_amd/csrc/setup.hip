@@ -526,6 +526,47 @@ __global__ void k_to_bf16(int64_t m, const double* __restrict__ a, uint16_t* __r
   if (t < m) b[t] = f32_to_bf16((float)a[t]);
 }
 
+// ------------------------------------------------------ sliced copy of A
+
+// Entries per slice of 64 rows: 64 times the slice's longest row.
+__global__ void k_sell_width(int n, int ns, const int* __restrict__ rp, int* __restrict__ cnt) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl > ns) return;
+  if (sl == ns) {
+    cnt[ns] = 0;
+    return;
+  }
+  int w = 0;
+  const int r1 = min(n, sl * 64 + 64);
+  for (int i = sl * 64; i < r1; ++i) w = max(w, rp[i + 1] - rp[i]);
+  cnt[sl] = 64 * w;
+}
+
+// Thread per (padded) row: its entries in stored order, then padding.
+__global__ void k_sell_fill(int n, int ns, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const int* __restrict__ soff, int* __restrict__ sci, int* __restrict__ sperm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns * 64) return;
+  const int sl = i >> 6, lane = i & 63;
+  const int w = (soff[sl + 1] - soff[sl]) >> 6;
+  const int k0 = i < n ? rp[i] : 0, len = i < n ? rp[i + 1] - k0 : 0;
+  for (int j = 0; j < w; ++j) {
+    const int64_t p = soff[sl] + (int64_t)j * 64 + lane;
+    sci[p] = j < len ? ci[k0 + j] : -1;
+    sperm[p] = j < len ? k0 + j : -1;
+  }
+}
+
+__global__ void k_sell_vals(int64_t m, const int* __restrict__ sperm, const double* __restrict__ v,
+                            double* __restrict__ sv, float* __restrict__ sv32) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  const int k = sperm[p];
+  const double a = k >= 0 ? v[k] : 0.0;
+  sv[p] = a;
+  if (sv32) sv32[p] = (float)a;
+}
+
 // ---------------------------------------------------------- host helpers
 
 template <class F>
@@ -808,6 +849,47 @@ void precision_copies(Hierarchy& H, hipStream_t s) {
   AMG_HIP(hipGetLastError());
 }
 
+// Sliced copies of the levels whose rows are short (longest row at most
+// kSellMaxW, padding at most 1/8 of the nonzeros; one system only).  The
+// pattern part is built once; values are gathered again on every refresh.
+void sliced_copies(Hierarchy& H, bool build, hipStream_t s) {
+  if (H.S != 1) return;
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    Level& L = H.lv[l];
+    if (build) {
+      L.sell = false;
+      const int ns = (L.n + 63) / 64;
+      DBuf<int> cnt;
+      cnt.alloc(ns + 1);
+      hipLaunchKernelGGL(k_sell_width, dim3((ns + kBlock) / kBlock), dim3(kBlock), 0, s, L.n, ns, L.rp.p, cnt.p);
+      std::vector<int> h(ns + 1);
+      AMG_HIP(hipMemcpyAsync(h.data(), cnt.p, sizeof(int) * (ns + 1), hipMemcpyDeviceToHost, s));
+      AMG_HIP(hipStreamSynchronize(s));
+      int64_t tot = 0;
+      int wmax = 0;
+      for (int i = 0; i < ns; ++i) {
+        tot += h[i];
+        wmax = std::max(wmax, h[i] / 64);
+      }
+      if (wmax > kSellMaxW || tot * 8 > L.nnz * 9 || tot >= (int64_t)INT32_MAX) continue;
+      L.soff.alloc(ns + 1);
+      exclusive_scan(cnt.p, L.soff.p, ns + 1, s);
+      L.sci.alloc(tot);
+      L.sperm.alloc(tot);
+      hipLaunchKernelGGL(k_sell_fill, dim3((ns * 64 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, L.n, ns, L.rp.p,
+                         L.ci.p, L.soff.p, L.sci.p, L.sperm.p);
+      L.sv.alloc(tot);
+      if (H.fp32()) L.sv32.alloc(tot);
+      L.sell_len = tot;
+      L.sell = true;
+    }
+    if (!L.sell) continue;
+    hipLaunchKernelGGL(k_sell_vals, dim3(grid_for(L.sell_len)), dim3(kBlock), 0, s, L.sell_len, L.sperm.p, L.v.p,
+                       L.sv.p, H.fp32() ? L.sv32.p : nullptr);
+  }
+  AMG_HIP(hipGetLastError());
+}
+
 void alloc_cycle_vectors(Hierarchy& H) {
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level& L = H.lv[l];
@@ -898,6 +980,7 @@ void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const doubl
   }
   coarse_setup(H, s);
   precision_copies(H, s);
+  sliced_copies(H, true, s);
   alloc_cycle_vectors(H);
   choose_shapes(H, s);
   alloc_solve_workspace(H);
@@ -914,6 +997,7 @@ void refresh_hierarchy(Hierarchy& H, const double* d_val, hipStream_t s) {
   }
   coarse_setup(H, s);
   precision_copies(H, s);
+  sliced_copies(H, false, s);
   AMG_HIP(hipStreamSynchronize(s));
 }
 

@@ -340,6 +340,36 @@ __global__ void __launch_bounds__(kBlock) k_vec(int n, const int* __restrict__ r
   publish_partials<Op::NRED>(d, partials);
 }
 
+// Sliced sweep: thread per row, the wave's 64 rows form one slice whose
+// entries are stored column-major, so entry j of all 64 rows is one
+// coalesced load.  The slice width is uniform across the wave; padding
+// entries (column -1) are masked out of the sum.  Each row sums its entries
+// in stored order (the same fold as a one-lane CSR sweep).
+template <class Op>
+__global__ void __launch_bounds__(kBlock) k_sell(int n, const int* __restrict__ soff, const int* __restrict__ sci,
+                                                 Op op, const Ctl* __restrict__ ctl, double* __restrict__ partials) {
+  if ((ctl && ctl->done) || n <= 0) return;
+  using PT = typename Op::PT;
+  const int row = logical_block() * kBlock + threadIdx.x;
+  const int rc = min(row, n - 1);
+  const typename Op::Row in = op.row_in(rc);
+  const int sl = rc >> 6, lane = rc & 63;
+  const int off = soff[sl];
+  const int w = (soff[sl + 1] - off) >> 6;
+  int col[kSellMaxW];
+#pragma unroll
+  for (int j = 0; j < kSellMaxW; ++j) col[j] = sci[off + min(j, w - 1) * 64 + lane];
+  PT pv[kSellMaxW];
+#pragma unroll
+  for (int j = 0; j < kSellMaxW; ++j) pv[j] = op.prod(off + min(j, w - 1) * 64 + lane, col[j] < 0 ? rc : col[j]);
+  PT s = 0;
+#pragma unroll
+  for (int j = 0; j < kSellMaxW; ++j) s = j < w && col[j] >= 0 ? s + pv[j] : s;
+  double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  if (row < n) op.epi(row, s, in, d);
+  publish_partials<Op::NRED>(d, partials);
+}
+
 #define AMG_DISPATCH_G(g, ...)                             \
   switch (g) {                                             \
     case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
@@ -356,7 +386,9 @@ __global__ void __launch_bounds__(kBlock) k_vec(int n, const int* __restrict__ r
 template <class Op>
 int sweep(const Shape& sh, int n, const int* rp, const int* ci, const Op& op, const Ctl* ctl, double* partials,
           hipStream_t s) {
-  if (sh.stream) {
+  if (sh.stream == 2) {
+    hipLaunchKernelGGL((k_sell<Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl, partials);
+  } else if (sh.stream) {
     AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_stream<G, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl,
                                             partials));
   } else {
@@ -695,7 +727,7 @@ struct Bufs<double> {
   static double* r(Level& L) { return L.r64.p; }
   static double* xs(Level& L) { return L.xs64.p; }
   static double* rs(Level& L) { return L.rs64.p; }
-  static const double* v(Level& L) { return L.v.p; }
+  static const double* v(Level& L) { return L.av(); }
   static const double* sw(Level& L) { return L.sw.p; }
   static const double* inv(Coarse& C) { return C.inv.p; }
 };
@@ -706,7 +738,7 @@ struct Bufs<float> {
   static float* r(Level& L) { return L.r32.p; }
   static float* xs(Level& L) { return L.xs32.p; }
   static float* rs(Level& L) { return L.rs32.p; }
-  static const float* v(Level& L) { return L.v32.p; }
+  static const float* v(Level& L) { return L.av32(); }
   static const float* sw(Level& L) { return L.sw32.p; }
   static const float* inv(Coarse& C) { return C.inv32.p; }
 };
@@ -771,20 +803,20 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
       // (CG update on level 0, restriction below), so only r = b - A x remains
       InstScope is(H, KID_PRE, l, s, a.ctl);
       if (l == 0 && !a.x0_ready)
-        sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPre<T, double>{Bufs<T>::v(L), Bufs<T>::sw(L), a.r0, cx[l], cr[l]}, ctl,
+        sweep(L.shA, L.n, L.arp(), L.aci(), OpPre<T, double>{Bufs<T>::v(L), Bufs<T>::sw(L), a.r0, cx[l], cr[l]}, ctl,
               nullptr, s);
       else if (l == 0)
-        sweep(L.shA, L.n, L.rp.p, L.ci.p, OpResid<T, double>{Bufs<T>::v(L), a.r0, cx[l], cr[l]}, ctl, nullptr, s);
+        sweep(L.shA, L.n, L.arp(), L.aci(), OpResid<T, double>{Bufs<T>::v(L), a.r0, cx[l], cr[l]}, ctl, nullptr, s);
       else
-        sweep(L.shA, L.n, L.rp.p, L.ci.p, OpResid<T, T>{Bufs<T>::v(L), Bufs<T>::b(L), cx[l], cr[l]}, ctl, nullptr,
+        sweep(L.shA, L.n, L.arp(), L.aci(), OpResid<T, T>{Bufs<T>::v(L), Bufs<T>::b(L), cx[l], cr[l]}, ctl, nullptr,
               s);
     }
     for (int k = 1; k < npre; ++k) {
       if (l == 0)
-        sweep(L.shA, L.n, L.rp.p, L.ci.p,
+        sweep(L.shA, L.n, L.arp(), L.aci(),
               OpSweep<T, double>{Bufs<T>::v(L), Bufs<T>::sw(L), a.r0, cx[l], cr[l], sx[l], sr[l]}, ctl, nullptr, s);
       else
-        sweep(L.shA, L.n, L.rp.p, L.ci.p,
+        sweep(L.shA, L.n, L.arp(), L.aci(),
               OpSweep<T, T>{Bufs<T>::v(L), Bufs<T>::sw(L), Bufs<T>::b(L), cx[l], cr[l], sx[l], sr[l]}, ctl, nullptr,
               s);
       std::swap(cx[l], sx[l]);
@@ -824,13 +856,13 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
         {
           InstScope is(H, KID_POST, l, s, a.ctl);
           if (a.red == 2)
-            np = sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, double, 2>{vv, sw, a.r0, cur, a.z0, a.q}, ctl,
+            np = sweep(L.shA, L.n, L.arp(), L.aci(), OpPost<T, double, double, 2>{vv, sw, a.r0, cur, a.z0, a.q}, ctl,
                        a.partials, s);
           else if (a.red == 1)
-            np = sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, double, 1>{vv, sw, a.r0, cur, a.z0, a.q}, ctl,
+            np = sweep(L.shA, L.n, L.arp(), L.aci(), OpPost<T, double, double, 1>{vv, sw, a.r0, cur, a.z0, a.q}, ctl,
                        a.partials, s);
           else
-            sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, double, 0>{vv, sw, a.r0, cur, a.z0, nullptr}, ctl,
+            sweep(L.shA, L.n, L.arp(), L.aci(), OpPost<T, double, double, 0>{vv, sw, a.r0, cur, a.z0, nullptr}, ctl,
                   nullptr, s);
         }
         if (a.red) launch_fin_beta(ctl, a.partials, np, a.first, a.red, s);
@@ -838,10 +870,10 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
         T* dst = spare[k & 1];
         InstScope is(H, KID_POST, l, s, a.ctl);
         if (l == 0)
-          sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, double, T, 0>{vv, sw, a.r0, cur, dst, nullptr}, ctl, nullptr,
+          sweep(L.shA, L.n, L.arp(), L.aci(), OpPost<T, double, T, 0>{vv, sw, a.r0, cur, dst, nullptr}, ctl, nullptr,
                 s);
         else
-          sweep(L.shA, L.n, L.rp.p, L.ci.p, OpPost<T, T, T, 0>{vv, sw, Bufs<T>::b(L), cur, dst, nullptr}, ctl,
+          sweep(L.shA, L.n, L.arp(), L.aci(), OpPost<T, T, T, 0>{vv, sw, Bufs<T>::b(L), cur, dst, nullptr}, ctl,
                 nullptr, s);
         spare[k & 1] = cur;
         cur = dst;
@@ -1047,7 +1079,11 @@ void choose_shapes(Hierarchy& H, hipStream_t s) {
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level& L = H.lv[l];
     const int nc = l + 1 < H.lv.size() ? L.nagg : 0;
-    if (f32) {
+    if (L.sell) {
+      L.shA = Shape{};
+      L.shA.stream = 2;
+      L.shA.grid = round8(((int64_t)L.n + kBlock - 1) / kBlock);
+    } else if (f32) {
       L.shA = pick_shape(H, "A", (int)l, L.rp, L.ci, L.n, nc, [&](int64_t len) {
         auto t = std::make_unique<TuneOp<OpResid<float, float>, float>>();
         t->a.alloc(len); t->b.alloc(len); t->c.alloc(len);
@@ -1155,17 +1191,22 @@ double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible) {
   const double pw = H.fp32() ? (H.bf16() ? 2.0 : 4.0) : 8.0;   // transfer value bytes
   const double n = L.n, nnz = (double)L.nnz;
   auto M = [](double nz, double rows, double w) { return nz * (w + 4.0) + 4.0 * (rows + 1.0); };
+  // operator matrix: the sliced copy when present (its padded entries and
+  // slice offsets), else the CSR arrays
+  auto MA = [&](double w) {
+    return L.sell ? (double)L.sell_len * (w + 4.0) + 4.0 * ((L.n + 63) / 64 + 1.0) : M(nnz, n, w);
+  };
   const double bw = level == 0 ? 8.0 : v;                       // rhs of the level
   const bool has_next = level + 1 < nl;
   const bool next_coarsest = level + 2 == nl;
   switch (kid) {
     // direction update fused with the product: gathers z and old p, writes new p and q
-    case KID_SPMV_DOT: return M(nnz, n, 8.0) + 32.0 * n;
+    case KID_SPMV_DOT: return MA(8.0) + 32.0 * n;
     // residual of the pre-smoothed iterate: reads b, gathers x, writes r
-    case KID_PRE: return M(nnz, n, v) + (bw + 2.0 * v) * n;
+    case KID_PRE: return MA(v) + (bw + 2.0 * v) * n;
     case KID_POST: {
       const double ow = level == 0 ? 8.0 : v;
-      return M(nnz, n, v) + (bw + 2.0 * v + ow) * n + (level == 0 && flexible ? 8.0 * n : 0.0);
+      return MA(v) + (bw + 2.0 * v + ow) * n + (level == 0 && flexible ? 8.0 * n : 0.0);
     }
     case KID_RESTRICT: {
       if (!has_next) return 0.0;
@@ -1334,7 +1375,7 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
     int np;
     {
       InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
-      np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpSpmvXpayDev{L0.v.p, H.z.p, pb[c], pb[c ^ 1], H.q.p, ctl, first},
+      np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpSpmvXpayDev{L0.av(), H.z.p, pb[c], pb[c ^ 1], H.q.p, ctl, first},
                  ctl, part, st);
     }
     hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinBlock), 0, st, ctl, part, np);
@@ -1417,7 +1458,7 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
       break;
     }
     // true residual r = b - A x
-    const int np = sweep(L0.shA, n, L0.rp.p, L0.ci.p, OpTrueResid{L0.v.p, d_x, d_b, H.r.p}, nullptr, part, s);
+    const int np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpTrueResid{L0.av(), d_x, d_b, H.r.p}, nullptr, part, s);
     hipLaunchKernelGGL(k_fin_trr, dim3(1), dim3(kFinBlock), 0, s, ctl, part, np);
     read_ctl(H, s);
     const Ctl& c = *H.h_ctl;
