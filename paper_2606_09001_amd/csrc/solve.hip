@@ -85,7 +85,8 @@ struct OpSpmvXpayDev {
     double pr;
   };
   __device__ double dir(int j, double beta) const { return first ? z[j] : z[j] + beta * p[j]; }
-  __device__ PT prod(int k, int j) const { return v[k] * dir(j, ctl->beta); }
+  __device__ PT prod_v(double a, int j) const { return a * dir(j, ctl->beta); }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
   __device__ Row row_in(int row) const { return {dir(row, ctl->beta)}; }
   __device__ void epi(int row, PT s, const Row& a, double* d) const {
     pn[row] = a.pr;
@@ -105,7 +106,8 @@ struct OpTrueResid {
   struct Row {
     double b;
   };
-  __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
+  __device__ PT prod_v(PT a, int j) const { return a * x[j]; }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
   __device__ Row row_in(int row) const { return {b[row]}; }
   __device__ void epi(int row, PT s, const Row& a, double* d) const {
     const double ri = a.b - s;
@@ -128,7 +130,8 @@ struct OpPre {
   struct Row {
     T b, w;
   };
-  __device__ PT prod(int k, int j) const { return v[k] * (sw[j] * (T)b[j]); }
+  __device__ PT prod_v(PT a, int j) const { return a * (sw[j] * (T)b[j]); }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
   __device__ Row row_in(int row) const { return {(T)b[row], sw[row]}; }
   __device__ void epi(int row, PT s, const Row& a, double*) const {
     x[row] = a.w * a.b;
@@ -149,7 +152,8 @@ struct OpResid {
   struct Row {
     T b;
   };
-  __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
+  __device__ PT prod_v(PT a, int j) const { return a * x[j]; }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
   __device__ Row row_in(int row) const { return {(T)b[row]}; }
   __device__ void epi(int row, PT s, const Row& a, double*) const { r[row] = a.b - s; }
 };
@@ -170,7 +174,8 @@ struct OpSweep {
   struct Row {
     T x, w, r, b;
   };
-  __device__ PT prod(int k, int j) const { return v[k] * (x[j] + sw[j] * r[j]); }
+  __device__ PT prod_v(PT a, int j) const { return a * (x[j] + sw[j] * r[j]); }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
   __device__ Row row_in(int row) const { return {x[row], sw[row], r[row], (T)b[row]}; }
   __device__ void epi(int row, PT s, const Row& a, double*) const {
     x2[row] = a.x + a.w * a.r;
@@ -195,7 +200,8 @@ struct OpPost {
     T x, w;
     double q;
   };
-  __device__ PT prod(int k, int j) const { return v[k] * x[j]; }
+  __device__ PT prod_v(PT a, int j) const { return a * x[j]; }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
   __device__ Row row_in(int row) const {
     Row a{b[row], x[row], sw[row], 0.0};
     if constexpr (RED >= 2) a.q = q[row];
@@ -224,7 +230,8 @@ struct OpRestrict {
   struct Row {
     T w;
   };
-  __device__ PT prod(int k, int j) const { return (T)ValCvt<RT>::f(v[k]) * x[j]; }
+  __device__ PT prod_v(RT a, int j) const { return (T)ValCvt<RT>::f(a) * x[j]; }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
   __device__ Row row_in(int row) const { return {xc ? swc[row] : (T)0}; }
   __device__ void epi(int row, PT s, const Row& a, double*) const {
     y[row] = s;
@@ -243,7 +250,8 @@ struct OpProlong {
   struct Row {
     T x;
   };
-  __device__ PT prod(int k, int j) const { return (T)ValCvt<RT>::f(v[k]) * xc[j]; }
+  __device__ PT prod_v(RT a, int j) const { return (T)ValCvt<RT>::f(a) * xc[j]; }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
   __device__ Row row_in(int row) const { return {x[row]}; }
   __device__ void epi(int row, PT s, const Row& a, double*) const { x[row] = a.x + s; }
 };
@@ -340,6 +348,11 @@ __global__ void __launch_bounds__(kBlock) k_vec(int n, const int* __restrict__ r
   publish_partials<Op::NRED>(d, partials);
 }
 
+// Loads of the operator's entry stream (read once per sweep).
+#ifndef AMG_STREAM_LOAD
+#define AMG_STREAM_LOAD(ptr) (*(ptr))
+#endif
+
 // Sliced sweep: thread per row, the wave's 64 rows form one slice whose
 // entries are stored column-major, so entry j of all 64 rows is one
 // coalesced load.  The slice width is uniform across the wave; padding
@@ -353,15 +366,22 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, const int* __restrict__ 
   const int row = logical_block() * kBlock + threadIdx.x;
   const int rc = min(row, n - 1);
   const typename Op::Row in = op.row_in(rc);
-  const int sl = rc >> 6, lane = rc & 63;
+  // the wave's 64 rows are one slice: its offsets are scalar loads, which
+  // leave the vector loads of the row operands in flight
+  const int sl = __builtin_amdgcn_readfirstlane(rc >> 6), lane = rc & 63;
   const int off = soff[sl];
   const int w = (soff[sl + 1] - off) >> 6;
   int col[kSellMaxW];
+  typename std::remove_const<typename std::remove_pointer<decltype(op.v)>::type>::type val[kSellMaxW];
 #pragma unroll
-  for (int j = 0; j < kSellMaxW; ++j) col[j] = sci[off + min(j, w - 1) * 64 + lane];
+  for (int j = 0; j < kSellMaxW; ++j) {
+    const int p = off + min(j, w - 1) * 64 + lane;
+    col[j] = AMG_STREAM_LOAD(sci + p);
+    val[j] = AMG_STREAM_LOAD(op.v + p);
+  }
   PT pv[kSellMaxW];
 #pragma unroll
-  for (int j = 0; j < kSellMaxW; ++j) pv[j] = op.prod(off + min(j, w - 1) * 64 + lane, col[j] < 0 ? rc : col[j]);
+  for (int j = 0; j < kSellMaxW; ++j) pv[j] = op.prod_v(val[j], col[j] < 0 ? rc : col[j]);
   PT s = 0;
 #pragma unroll
   for (int j = 0; j < kSellMaxW; ++j) s = j < w && col[j] >= 0 ? s + pv[j] : s;
