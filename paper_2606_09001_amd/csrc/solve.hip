@@ -957,7 +957,7 @@ namespace {
 //
 // Candidate launch shapes of one matrix: every stream shape whose row blocks
 // fit the staging buffer (1..64 lanes per row in the in-LDS sums) and the
-// lanes-per-row fallback with 8..64 lanes.  Each is timed with HIP events on
+// direct lanes-per-row form with 1..64 lanes.  Each is timed with HIP events on
 // the operator that runs on that matrix in the cycle; the fastest wins.
 // Choices are cached in memory and, when AMG_TUNE_CACHE names a file, in a
 // text file of "key stream lanes rows_per_block" lines, so that later runs
@@ -977,7 +977,7 @@ std::vector<Shape> candidate_shapes(const std::vector<int>& rp, int n) {
     sh.grid = round8(((int64_t)n + rb - 1) / rb);
     out.push_back(sh);
   }
-  for (int g = 8; g <= 64; g <<= 1) {
+  for (int g = 1; g <= 64; g <<= 1) {
     Shape sh;
     sh.stream = 0;
     sh.g = g;
