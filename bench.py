@@ -63,9 +63,9 @@ def kernel_source_hash():
 # of CALIB_MIB MiB: that many bytes read and written).
 
 FINE_KERNELS = {  # tag -> (regex on the demangled name); level 0 = the largest grid
-    "spmv_dot_L0": r"k_stream<\d+, [^>]*OpSpmvXpayDev>",
-    "pre_L0": r"k_stream<\d+, [^>]*OpResid<double, double> >",
-    "post_L0": r"k_stream<\d+, [^>]*OpPost<double, double, double, 1> >",
+    "spmv_dot_L0": r"k_(?:stream<\d+, |sell<)[^>]*OpSpmvXpayDev>",
+    "pre_L0": r"k_(?:stream<\d+, |sell<)[^>]*OpResid<double, double> >",
+    "post_L0": r"k_(?:stream<\d+, |sell<)[^>]*OpPost<double, double, double, 1> >",
 }
 
 
