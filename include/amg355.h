@@ -105,6 +105,8 @@ typedef struct {
   int group_a[AMG_MAX_LEVELS];       /* lanes per row chosen for A_l, P_l, R_l kernels */
   int group_p[AMG_MAX_LEVELS];
   int group_r[AMG_MAX_LEVELS];
+  int form_a[AMG_MAX_LEVELS];        /* sweep form over A_l: 0 lanes-per-row, 1 CSR-stream, 2 sliced */
+  int64_t sliced_len[AMG_MAX_LEVELS]; /* stored entries of the sliced copy of A_l (0: none) */
 } amg_hier_stats;
 
 /* Fields of a level that amg_export_field can copy out (for bit-exact checks). */

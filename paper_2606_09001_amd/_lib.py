@@ -71,13 +71,14 @@ class amg_hier_stats(C.Structure):
     _fields_ = [
         ("num_levels", C.c_int), ("n", _L20), ("nnz", _L20), ("nnz_p", _L20), ("nnz_g", _L20), ("rho", _D20),
         ("omega_p", _D20), ("mis_rounds", _I20), ("operator_complexity", C.c_double), ("group_a", _I20),
-        ("group_p", _I20), ("group_r", _I20),
+        ("group_p", _I20), ("group_r", _I20), ("form_a", _I20), ("sliced_len", _L20),
     ]
 
     def to_dict(self):
         L = self.num_levels
         d = {"num_levels": L, "operator_complexity": self.operator_complexity}
-        for f in ("n", "nnz", "nnz_p", "nnz_g", "rho", "omega_p", "mis_rounds", "group_a", "group_p", "group_r"):
+        for f in ("n", "nnz", "nnz_p", "nnz_g", "rho", "omega_p", "mis_rounds", "group_a", "group_p", "group_r",
+                  "form_a", "sliced_len"):
             d[f] = list(getattr(self, f))[:L]
         return d
 

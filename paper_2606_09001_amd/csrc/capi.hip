@@ -330,6 +330,8 @@ amg_status amg_hierarchy_stats(amg_handle h, amg_hier_stats* out) {
     out->group_a[l] = L.shA.g;
     out->group_p[l] = L.shP.g;
     out->group_r[l] = L.shR.g;
+    out->form_a[l] = L.shA.stream;
+    out->sliced_len[l] = L.sell ? L.sell_len : 0;
     tot += (double)L.nnz;
   }
   out->operator_complexity = tot / (double)H.lv[0].nnz;

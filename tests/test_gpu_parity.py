@@ -279,3 +279,25 @@ def test_autotuned_shapes_keep_parity(tmp_path, monkeypatch):
     H, O = _solve_parity(rp, ci, v, M.rhs_normal(len(rp) - 1, 3), 1e-10, autotune=1)
     assert_hierarchy_bitexact(H, O)
     assert os.path.exists(cache) and len(cache.read_text().splitlines()) >= 3
+
+
+@pytest.mark.parametrize("case,sliced", [("poisson2d_75", True), ("tridiag_3000", True), ("poisson3d_24", True),
+                                         ("random_spd_700", False)])
+def test_level0_sweep_form(case, sliced):
+    """Short-row level-0 operators are swept from the sliced copy (rows of at
+    most 8 entries, padding at most 1/8), others from CSR; either way the
+    solve is the oracle's to the iterate."""
+    rp, ci, v = CASES[case]()
+    H, O = _solve_parity(rp, ci, v, M.rhs_normal(len(rp) - 1, 21), 1e-10)
+    st = H.stats()
+    nnz = len(ci)
+    assert (st["form_a"][0] == 2) == sliced
+    if sliced:
+        lens = np.diff(rp)
+        ns = (len(lens) + 63) // 64
+        pad = np.zeros(ns * 64, dtype=np.int64)
+        pad[:len(lens)] = lens
+        assert st["sliced_len"][0] == 64 * pad.reshape(ns, 64).max(axis=1).sum()
+        assert nnz <= st["sliced_len"][0] <= nnz * 9 // 8
+    else:
+        assert st["sliced_len"][0] == 0
