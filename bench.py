@@ -260,6 +260,99 @@ def run_batched(args, dev):
     return out
 
 
+def run_diffusion(args, dev):
+    """3D lognormal diffusion 192^3 (k = exp(GRF), harmonic faces): setup once,
+    then 10 solves with new right-hand sides (seeds 100-109), FP64 and FP32
+    cycle; solves/s and the solve's algorithmic HBM rate."""
+    import numpy as np
+    import torch
+    from paper_2606_09001_amd import matrices as M
+    from paper_2606_09001_amd.solver import AmgHierarchy, finalize
+    N = args.diffusion_grid
+    rp, ci, v = M.diffusion(np.exp(M.grf(N, 3, seed=2)))
+    n = len(rp) - 1
+    d_rp, d_ci, d_v = (torch.from_numpy(a).to(dev) for a in (rp, ci, v))
+    Bs = [torch.from_numpy(M.rhs_normal(n, s)).to(dev) for s in range(100, 110)]
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    out = {"workload": f"3D lognormal diffusion {N}^3 ({n} unknowns, {len(ci)} nnz), k = exp(GRF seed 2, sigma 1, "
+                       f"correlation 0.1), 10 right-hand sides with the setup cached, tol {args.tol:g}"}
+    for prec in ("fp64", "fp32"):
+        t0 = time.time()
+        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec)
+        torch.cuda.synchronize()
+        setup_ms = (time.time() - t0) * 1e3
+        H.solve(Bs[0], args.tol, out=x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        iters, rr = [], []
+        e0.record()
+        for b in Bs:
+            _, info = H.solve(b, args.tol, out=x)
+            iters.append(info["iters"])
+            rr.append(info["rel_resid"])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / len(Bs)
+        gbs = float(np.mean(iters)) * H.kernel_bytes(None, 0, flexible=(prec == "fp32")) / (ms * 1e-3) / 1e9
+        out[prec] = dict(ms_per_solve=round(ms, 3), solves_per_s=round(1e3 / ms, 2), iters_mean=float(np.mean(iters)),
+                         rel_resid_max=max(rr), setup_ms=round(setup_ms, 1), solve_hbm_gbs=round(gbs, 1),
+                         solve_hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+        log(f"diffusion {N}^3 {prec}: setup {setup_ms:.0f} ms, {ms:.2f} ms/solve ({1e3 / ms:.1f} solves/s), "
+            f"iters {np.mean(iters):.1f}, {gbs:.0f} GB/s over the solve")
+        H.close()
+        finalize()
+    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["fp32"]["ms_per_solve"], 4)
+    return out
+
+
+def run_adjoint(args, dev):
+    """2D diffusion 512^2 inverse-problem step: values k = exp(theta) assembled
+    in torch, forward solve, loss 0.5||u - u_obs||^2, backward (adjoint solve
+    on the cached hierarchy + pattern gradient + chain to theta), then a
+    gradient step, so every step refreshes the hierarchy with new values."""
+    import numpy as np
+    import torch
+    from paper_2606_09001_amd import matrices as M
+    from paper_2606_09001_amd.solver import AmgHierarchy, amg_solve, finalize
+    N = 512
+    theta0 = M.grf(N, 2, seed=41)
+    rp, ci, vt = M.diffusion(np.exp(M.grf(N, 2, seed=42)))
+    d_rp, d_ci = torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev)
+    b = torch.ones(N * N, dtype=torch.float64, device=dev)
+    Ht = AmgHierarchy(d_rp, d_ci, torch.from_numpy(vt).to(dev))
+    u_obs, _ = Ht.solve(b, 1e-12)
+    Ht.close()
+    out = {"workload": f"2D diffusion {N}^2 ({N * N} unknowns), theta = GRF seed 41, u_obs from theta = GRF seed 42, "
+                       f"loss 0.5||u - u_obs||^2, forward and adjoint solves to 1e-10, one gradient step per iteration"}
+    for prec in ("fp64", "fp32"):
+        th = torch.tensor(theta0, device=dev, requires_grad=True)
+
+        def step():
+            val = M.diffusion_values_torch(torch.exp(th))
+            xx = amg_solve(d_rp, d_ci, val, b, 1e-10, vcycle_prec=prec)
+            loss = 0.5 * torch.sum((xx - u_obs) ** 2)
+            loss.backward()
+            with torch.no_grad():   # a small normalized step: new values every step
+                th.sub_(0.01 * th.grad / (th.grad.abs().max() + 1e-300))
+                th.grad = None
+            return loss
+
+        step()
+        torch.cuda.synchronize()
+        k = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            loss = step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / k
+        out[prec] = dict(ms_per_step=round(ms, 3), steps_per_s=round(1e3 / ms, 2), loss_last=float(loss))
+        log(f"adjoint {N}^2 {prec}: {ms:.2f} ms per gradient step (refresh + forward + adjoint + pattern grad)")
+        finalize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +371,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--batched-rhs-grid", type=int, default=256)
     ap.add_argument("--batched-sys-grid", type=int, default=96)
+    ap.add_argument("--no-extra", action="store_true", help="skip the diffusion and adjoint workloads")
+    ap.add_argument("--diffusion-grid", type=int, default=192)
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write profiles/ summaries from rocprofv3 output of this script (no GPU)")
     ap.add_argument("--summary-tag", default="poisson3d_128")
@@ -444,6 +539,13 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         batched = run_batched(args, dev)
+    diffusion = adjoint = None
+    if not args.no_extra:
+        from paper_2606_09001_amd.solver import finalize
+        finalize()
+        torch.cuda.empty_cache()
+        diffusion = run_diffusion(args, dev)
+        adjoint = run_adjoint(args, dev)
 
     f64, f32 = res["fp64"], res["fp32"]
     out = {
@@ -478,6 +580,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "diffusion": diffusion,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
 
