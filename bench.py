@@ -294,15 +294,66 @@ def run_diffusion(args, dev):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / len(Bs)
         gbs = float(np.mean(iters)) * H.kernel_bytes(None, 0, flexible=(prec == "fp32")) / (ms * 1e-3) / 1e9
+        t0 = time.time()
+        H.update_values(d_v)     # warm resetup: numeric refresh of the whole hierarchy, same pattern
+        torch.cuda.synchronize()
+        refresh_ms = (time.time() - t0) * 1e3
         out[prec] = dict(ms_per_solve=round(ms, 3), solves_per_s=round(1e3 / ms, 2), iters_mean=float(np.mean(iters)),
-                         rel_resid_max=max(rr), setup_ms=round(setup_ms, 1), solve_hbm_gbs=round(gbs, 1),
-                         solve_hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
-        log(f"diffusion {N}^3 {prec}: setup {setup_ms:.0f} ms, {ms:.2f} ms/solve ({1e3 / ms:.1f} solves/s), "
-            f"iters {np.mean(iters):.1f}, {gbs:.0f} GB/s over the solve")
+                         rel_resid_max=max(rr), setup_ms=round(setup_ms, 1), refresh_ms=round(refresh_ms, 1),
+                         solve_hbm_gbs=round(gbs, 1), solve_hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+        log(f"diffusion {N}^3 {prec}: setup {setup_ms:.0f} ms, refresh {refresh_ms:.1f} ms, {ms:.2f} ms/solve "
+            f"({1e3 / ms:.1f} solves/s), iters {np.mean(iters):.1f}, {gbs:.0f} GB/s over the solve")
+        if prec == "fp64" and not args.no_kernel_table:
+            # level-0 kernels at a size whose streams exceed the 256 MB Infinity Cache twice over
+            kt = {}
+            for name in ("spmv_dot", "pre", "post", "restrict", "prolong", "cg_update"):
+                H.instrument(name, 0)
+                for b in Bs[:3]:
+                    H.solve(b, args.tol, out=x)
+                r = H.instrument_read()
+                H.instrument(None)
+                if r["launches"] == 0:
+                    continue
+                nbytes = H.kernel_bytes(name, 0, flexible=False)
+                g = nbytes / (r["avg_ms"] * 1e-3) / 1e9
+                kt[f"{name}_L0"] = dict(avg_us=round(r["avg_ms"] * 1e3, 2), bytes_per_launch=nbytes,
+                                        gbs=round(g, 1), frac=round(g / HBM_PEAK_GBS, 4), launches=r["launches"])
+                log(f"diffusion {N}^3 kernel {name}_L0: {r['avg_ms'] * 1e3:.1f} us, {nbytes / 1e6:.1f} MB -> "
+                    f"{g:.0f} GB/s ({100 * g / HBM_PEAK_GBS:.1f}% of peak)")
+            out["kernels_fp64"] = kt
         H.close()
         finalize()
     out["speedup_mixed_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["fp32"]["ms_per_solve"], 4)
     return out
+
+
+def run_small(args, dev):
+    """2D Poisson 32^2 to 1e-10 (latency-bound: every array is cache-resident)."""
+    import numpy as np
+    import torch
+    from paper_2606_09001_amd import matrices as M
+    from paper_2606_09001_amd.solver import AmgHierarchy, finalize
+    rp, ci, v = M.poisson(32, 2)
+    n = len(rp) - 1
+    d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v, M.rhs_normal(n, 0))]
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    H = AmgHierarchy(d[0], d[1], d[2])
+    _, info = H.solve(d[3], 1e-10, out=x)
+    torch.cuda.synchronize()
+    k = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(k):
+        _, info = H.solve(d[3], 1e-10, out=x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / k
+    log(f"poisson 32^2: {ms * 1e3:.0f} us/solve ({1e3 / ms:.0f} solves/s), iters {info['iters']}")
+    H.close()
+    finalize()
+    return {"workload": "2D Poisson 5-point 32^2 (1024 unknowns), b ~ N(0,1) seed 0, tol 1e-10, FP64",
+            "ms_per_solve": round(ms, 4), "solves_per_s": round(1e3 / ms, 1), "iters": info["iters"],
+            "rel_resid": info["rel_resid"]}
 
 
 def run_adjoint(args, dev):
@@ -372,6 +423,8 @@ def main():
     ap.add_argument("--batched-rhs-grid", type=int, default=256)
     ap.add_argument("--batched-sys-grid", type=int, default=96)
     ap.add_argument("--no-extra", action="store_true", help="skip the diffusion and adjoint workloads")
+    ap.add_argument("--diffusion-only", action="store_true",
+                    help="only the 192^3 diffusion workload (with the counter calibration kernel); for profiling")
     ap.add_argument("--diffusion-grid", type=int, default=192)
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write profiles/ summaries from rocprofv3 output of this script (no GPU)")
@@ -433,6 +486,37 @@ def main():
         torch.neg(src, out=dst)   # counter calibration: reads and writes exactly this many bytes
         torch.cuda.synchronize()
         del src, dst
+    # practical streaming ceilings of this device (2 GiB, outside any cache):
+    # a read-only reduction and a copy
+    ceilings = None
+    if args.calib_copy_mib > 0:
+        a = torch.ones((2 << 30) // 8, dtype=torch.float64, device=dev)
+        bcp = torch.empty_like(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.sum()
+        e0.record()
+        for _ in range(5):
+            a.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        read_gbs = a.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        bcp.copy_(a)
+        e0.record()
+        for _ in range(5):
+            bcp.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        copy2_gbs = 2 * a.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        ceilings = {"read_gbs": round(read_gbs, 1), "copy_gbs": round(copy2_gbs, 1),
+                    "read_frac": round(read_gbs / HBM_PEAK_GBS, 4), "copy_frac": round(copy2_gbs / HBM_PEAK_GBS, 4),
+                    "note": "torch sum (read only) and copy_ of 2 GiB FP64 tensors, events over 5 launches"}
+        log(f"streaming ceilings (2 GiB): read {read_gbs:.0f} GB/s, copy {copy2_gbs:.0f} GB/s (read+write)")
+        del a, bcp
+        torch.cuda.empty_cache()
+    if args.diffusion_only:
+        print(json.dumps({"diffusion": run_diffusion(args, dev)}), flush=True)
+        return
 
     res = {}
     hier = {}
@@ -539,13 +623,14 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         batched = run_batched(args, dev)
-    diffusion = adjoint = None
+    diffusion = adjoint = small = None
     if not args.no_extra:
         from paper_2606_09001_amd.solver import finalize
         finalize()
         torch.cuda.empty_cache()
         diffusion = run_diffusion(args, dev)
         adjoint = run_adjoint(args, dev)
+        small = run_small(args, dev)
 
     f64, f32 = res["fp64"], res["fp32"]
     out = {
@@ -582,6 +667,8 @@ def main():
         "batched": batched,
         "diffusion": diffusion,
         "adjoint": adjoint,
+        "poisson2d_32": small,
+        "ceilings": ceilings,
     }
     print(json.dumps(out), flush=True)
 
