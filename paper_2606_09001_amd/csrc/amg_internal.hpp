@@ -65,7 +65,7 @@ struct DBuf {
 // with `g` lanes; vec (fallback for very long rows): `g` lanes per row read
 // the row directly.
 struct Shape {
-  int stream = 1;  // 1: CSR-stream, 0: lanes-per-row, 2: sliced (thread per row)
+  int stream = 1;  // 1: CSR-stream, 0: lanes-per-row, 2: sliced (thread per row), 3: sliced, slot offsets
   int g = 1;
   int rows_per_block = 256;
   int grid = 1;
@@ -83,14 +83,24 @@ struct Level {
   // of the slice's row r at soff[s] + 64 j + r), each row padded with
   // column -1 / value 0 to the slice's longest row.  sperm maps a sliced
   // position to its CSR position (-1: padding) for value refresh.
+  //
+  // Offset form (when every slice's rows use at most kSellMaxW distinct
+  // column offsets col - row, as stencil operators do): slot j of a slice
+  // holds the entries with offset slots[j].x of all its rows, in ascending
+  // offset order; slots[j].z/.w are the 64-bit mask of the rows that have
+  // that entry.  Values as above (0 where masked); no column array.
   bool sell = false;
+  int sell_form = 0;          // 1: explicit columns, 2: slot offsets
   int64_t sell_len = 0;
   DBuf<int> soff, sci, sperm;
+  DBuf<int4> sslot;
   DBuf<double> sv;
   DBuf<float> sv32;
   // arrays the operator sweeps over A_l read (sliced when present)
   const int* arp() const { return sell ? soff.p : rp.p; }
-  const int* aci() const { return sell ? sci.p : ci.p; }
+  const int* aci() const {
+    return sell ? (sell_form == 2 ? reinterpret_cast<const int*>(sslot.p) : sci.p) : ci.p;
+  }
   const double* av() const { return sell ? sv.p : v.p; }
   const float* av32() const { return sell ? sv32.p : v32.p; }
   DBuf<int> diagpos;          // position of a_ii in row i

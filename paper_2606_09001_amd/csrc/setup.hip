@@ -557,6 +557,64 @@ __global__ void k_sell_fill(int n, int ns, const int* __restrict__ rp, const int
   }
 }
 
+// Offset form, pass 1: per slice, the sorted union of its rows' column
+// offsets (col - row); 64 x its size (kSellMaxW + 1 when it overflows).
+__global__ void k_sello_count(int n, int ns, const int* __restrict__ rp, const int* __restrict__ ci,
+                              int* __restrict__ cnt, int* __restrict__ uoff) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl > ns) return;
+  if (sl == ns) {
+    cnt[ns] = 0;
+    return;
+  }
+  int u[kSellMaxW];
+  int m = 0;
+  bool over = false;
+  const int r1 = min(n, sl * 64 + 64);
+  for (int i = sl * 64; i < r1 && !over; ++i) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int d = ci[k] - i;
+      int pos = 0;
+      while (pos < m && u[pos] < d) ++pos;
+      if (pos < m && u[pos] == d) continue;
+      if (m == kSellMaxW) {
+        over = true;
+        break;
+      }
+      for (int t = m; t > pos; --t) u[t] = u[t - 1];
+      u[pos] = d;
+      ++m;
+    }
+  }
+  cnt[sl] = 64 * (over ? kSellMaxW + 1 : m);
+  for (int j = 0; j < kSellMaxW; ++j) uoff[(int64_t)sl * kSellMaxW + j] = j < m ? u[j] : 0;
+}
+
+// Offset form, pass 2: slot records (offset, row mask) and the position map.
+__global__ void k_sello_fill(int n, int ns, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const int* __restrict__ soff, const int* __restrict__ uoff, int4* __restrict__ slots,
+                             int* __restrict__ sperm) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= ns) return;
+  const int base = soff[sl], w = (soff[sl + 1] - base) >> 6;
+  const int* u = uoff + (int64_t)sl * kSellMaxW;
+  for (int p = base; p < base + 64 * w; ++p) sperm[p] = -1;
+  unsigned long long mask[kSellMaxW] = {};
+  const int r1 = min(n, sl * 64 + 64);
+  for (int i = sl * 64; i < r1; ++i) {
+    const int lane = i - sl * 64;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int d = ci[k] - i;
+      int j = 0;
+      while (j < w && u[j] != d) ++j;
+      sperm[base + j * 64 + lane] = k;
+      mask[j] |= 1ull << lane;
+    }
+  }
+  for (int j = 0; j < w; ++j)
+    slots[(base >> 6) + j] = make_int4(u[j], 0, (int)(unsigned)(mask[j] & 0xffffffffull), (int)(unsigned)(mask[j] >> 32));
+}
+
 __global__ void k_sell_vals(int64_t m, const int* __restrict__ sperm, const double* __restrict__ v,
                             double* __restrict__ sv, float* __restrict__ sv32) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -858,6 +916,43 @@ void sliced_copies(Hierarchy& H, bool build, hipStream_t s) {
     Level& L = H.lv[l];
     if (build) {
       L.sell = false;
+      L.sell_form = 0;
+      const int ns = (L.n + 63) / 64;
+      DBuf<int> cnt;
+      cnt.alloc(ns + 1);
+      {
+        // offset form first: every slice's offsets fit kSellMaxW slots
+        DBuf<int> uoff;
+        uoff.alloc((int64_t)ns * kSellMaxW);
+        hipLaunchKernelGGL(k_sello_count, dim3((ns + kBlock) / kBlock), dim3(kBlock), 0, s, L.n, ns, L.rp.p, L.ci.p,
+                           cnt.p, uoff.p);
+        std::vector<int> h(ns + 1);
+        AMG_HIP(hipMemcpyAsync(h.data(), cnt.p, sizeof(int) * (ns + 1), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        int64_t tot = 0;
+        int wmax = 0;
+        for (int i = 0; i < ns; ++i) {
+          tot += h[i];
+          wmax = std::max(wmax, h[i] / 64);
+        }
+        if (wmax <= kSellMaxW && tot * 8 <= L.nnz * 9 && tot < (int64_t)INT32_MAX) {
+          L.soff.alloc(ns + 1);
+          exclusive_scan(cnt.p, L.soff.p, ns + 1, s);
+          L.sslot.alloc(tot / 64 + kSellMaxW);  // padded: a slice loads kSellMaxW records at once
+          AMG_HIP(hipMemsetAsync(L.sslot.p, 0, L.sslot.bytes(), s));
+          L.sperm.alloc(tot);
+          hipLaunchKernelGGL(k_sello_fill, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, s, L.n, ns, L.rp.p,
+                             L.ci.p, L.soff.p, uoff.p, L.sslot.p, L.sperm.p);
+          L.sv.alloc(tot);
+          if (H.fp32()) L.sv32.alloc(tot);
+          L.sell_len = tot;
+          L.sell = true;
+          L.sell_form = 2;
+          AMG_HIP(hipStreamSynchronize(s));  // uoff is freed on leaving this scope
+        }
+      }
+    }
+    if (build && !L.sell) {
       const int ns = (L.n + 63) / 64;
       DBuf<int> cnt;
       cnt.alloc(ns + 1);
@@ -882,6 +977,7 @@ void sliced_copies(Hierarchy& H, bool build, hipStream_t s) {
       if (H.fp32()) L.sv32.alloc(tot);
       L.sell_len = tot;
       L.sell = true;
+      L.sell_form = 1;
     }
     if (!L.sell) continue;
     hipLaunchKernelGGL(k_sell_vals, dim3(grid_for(L.sell_len)), dim3(kBlock), 0, s, L.sell_len, L.sperm.p, L.v.p,

@@ -390,6 +390,49 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, const int* __restrict__ 
   publish_partials<Op::NRED>(d, partials);
 }
 
+// Sliced sweep, offset form: slot j of the wave's slice holds offset
+// slots[j].x for every row whose mask bit is set; the slot records are
+// wave-uniform (scalar loads), so the only per-entry stream is the values.
+// Each row adds its present entries in ascending offset (= column) order.
+template <class Op>
+__global__ void __launch_bounds__(kBlock) k_sello(int n, const int* __restrict__ soff, const int4* __restrict__ slots,
+                                                  Op op, const Ctl* __restrict__ ctl, double* __restrict__ partials) {
+  if ((ctl && ctl->done) || n <= 0) return;
+  using PT = typename Op::PT;
+  const int row = logical_block() * kBlock + threadIdx.x;
+  const int rc = min(row, n - 1);
+  const typename Op::Row in = op.row_in(rc);
+  const int sl = __builtin_amdgcn_readfirstlane(rc >> 6), lane = rc & 63;
+  const int off = soff[sl];
+  const int w = (soff[sl + 1] - off) >> 6;
+  const int sb = off >> 6;
+  typename std::remove_const<typename std::remove_pointer<decltype(op.v)>::type>::type val[kSellMaxW];
+#pragma unroll
+  for (int j = 0; j < kSellMaxW; ++j) val[j] = AMG_STREAM_LOAD(op.v + off + min(j, w - 1) * 64 + lane);
+  // the slice's kSellMaxW records as one block (the array is padded so the
+  // last slice's block stays in bounds)
+  int4 rec[kSellMaxW];
+#pragma unroll
+  for (int j = 0; j < kSellMaxW; ++j) rec[j] = slots[sb + j];
+  int col[kSellMaxW];
+  bool has[kSellMaxW];
+#pragma unroll
+  for (int j = 0; j < kSellMaxW; ++j) {
+    const unsigned bits = lane < 32 ? (unsigned)rec[j].z : (unsigned)rec[j].w;
+    has[j] = j < w && ((bits >> (lane & 31)) & 1u);
+    col[j] = has[j] ? rc + rec[j].x : rc;
+  }
+  PT pv[kSellMaxW];
+#pragma unroll
+  for (int j = 0; j < kSellMaxW; ++j) pv[j] = op.prod_v(val[j], col[j]);
+  PT s = 0;
+#pragma unroll
+  for (int j = 0; j < kSellMaxW; ++j) s = has[j] ? s + pv[j] : s;
+  double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  if (row < n) op.epi(row, s, in, d);
+  publish_partials<Op::NRED>(d, partials);
+}
+
 #define AMG_DISPATCH_G(g, ...)                             \
   switch (g) {                                             \
     case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
@@ -406,7 +449,10 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, const int* __restrict__ 
 template <class Op>
 int sweep(const Shape& sh, int n, const int* rp, const int* ci, const Op& op, const Ctl* ctl, double* partials,
           hipStream_t s) {
-  if (sh.stream == 2) {
+  if (sh.stream == 3) {
+    hipLaunchKernelGGL((k_sello<Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, reinterpret_cast<const int4*>(ci), op,
+                       ctl, partials);
+  } else if (sh.stream == 2) {
     hipLaunchKernelGGL((k_sell<Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl, partials);
   } else if (sh.stream) {
     AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_stream<G, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl,
@@ -1101,7 +1147,7 @@ void choose_shapes(Hierarchy& H, hipStream_t s) {
     const int nc = l + 1 < H.lv.size() ? L.nagg : 0;
     if (L.sell) {
       L.shA = Shape{};
-      L.shA.stream = 2;
+      L.shA.stream = L.sell_form == 2 ? 3 : 2;
       L.shA.grid = round8(((int64_t)L.n + kBlock - 1) / kBlock);
     } else if (f32) {
       L.shA = pick_shape(H, "A", (int)l, L.rp, L.ci, L.n, nc, [&](int64_t len) {
@@ -1211,10 +1257,13 @@ double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible) {
   const double pw = H.fp32() ? (H.bf16() ? 2.0 : 4.0) : 8.0;   // transfer value bytes
   const double n = L.n, nnz = (double)L.nnz;
   auto M = [](double nz, double rows, double w) { return nz * (w + 4.0) + 4.0 * (rows + 1.0); };
-  // operator matrix: the sliced copy when present (its padded entries and
-  // slice offsets), else the CSR arrays
+  // operator matrix: the sliced copy when present (its padded values, and
+  // columns or slot records, and slice offsets), else the CSR arrays
   auto MA = [&](double w) {
-    return L.sell ? (double)L.sell_len * (w + 4.0) + 4.0 * ((L.n + 63) / 64 + 1.0) : M(nnz, n, w);
+    if (!L.sell) return M(nnz, n, w);
+    const double slices = 4.0 * ((L.n + 63) / 64 + 1.0);
+    if (L.sell_form == 2) return (double)L.sell_len * w + 16.0 * (double)(L.sell_len / 64) + slices;
+    return (double)L.sell_len * (w + 4.0) + slices;
   };
   const double bw = level == 0 ? 8.0 : v;                       // rhs of the level
   const bool has_next = level + 1 < nl;

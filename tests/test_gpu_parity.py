@@ -281,23 +281,51 @@ def test_autotuned_shapes_keep_parity(tmp_path, monkeypatch):
     assert os.path.exists(cache) and len(cache.read_text().splitlines()) >= 3
 
 
-@pytest.mark.parametrize("case,sliced", [("poisson2d_75", True), ("tridiag_3000", True), ("poisson3d_24", True),
-                                         ("random_spd_700", False)])
-def test_level0_sweep_form(case, sliced):
-    """Short-row level-0 operators are swept from the sliced copy (rows of at
-    most 8 entries, padding at most 1/8), others from CSR; either way the
-    solve is the oracle's to the iterate."""
-    rp, ci, v = CASES[case]()
+def _permuted_poisson(N, seed):
+    """2D Poisson under a random symmetric permutation: short rows (3-5
+    entries) with scattered columns."""
+    import scipy.sparse as sp
+    rp, ci, v = M.poisson(N, 2)
+    n = len(rp) - 1
+    A = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    p = np.random.default_rng(seed).permutation(n)
+    B = A[p][:, p].tocsr()
+    B.sort_indices()
+    return B.indptr.astype(np.int32), B.indices.astype(np.int32), B.data.astype(np.float64)
+
+
+def _expected_sliced(rp, ci, form):
+    lens = np.diff(rp)
+    n = len(lens)
+    ns = (n + 63) // 64
+    tot = 0
+    for s in range(ns):
+        rows = range(s * 64, min(n, s * 64 + 64))
+        if form == 3:   # slots = distinct column offsets of the slice's rows
+            tot += 64 * len({int(ci[k]) - i for i in rows for k in range(rp[i], rp[i + 1])})
+        else:           # slots = the slice's longest row
+            tot += 64 * int(max(lens[i] for i in rows))
+    return tot
+
+
+@pytest.mark.parametrize("case,form", [("poisson2d_75", 3), ("tridiag_3000", 3), ("poisson3d_24", 3),
+                                       ("diffusion3d_21", 3), ("permuted_poisson_40", 2), ("random_spd_700", 1)])
+def test_level0_sweep_form(case, form):
+    """Level-0 operators whose slices use at most 8 distinct column offsets
+    are swept from the offset form (3), other short-row operators from the
+    sliced form with explicit columns (2), the rest from CSR (1); the
+    stored length is the one the forms define, and the solve is the
+    oracle's to the iterate either way."""
+    if case == "permuted_poisson_40":
+        rp, ci, v = _permuted_poisson(40, 3)
+    else:
+        rp, ci, v = CASES[case]()
     H, O = _solve_parity(rp, ci, v, M.rhs_normal(len(rp) - 1, 21), 1e-10)
     st = H.stats()
     nnz = len(ci)
-    assert (st["form_a"][0] == 2) == sliced
-    if sliced:
-        lens = np.diff(rp)
-        ns = (len(lens) + 63) // 64
-        pad = np.zeros(ns * 64, dtype=np.int64)
-        pad[:len(lens)] = lens
-        assert st["sliced_len"][0] == 64 * pad.reshape(ns, 64).max(axis=1).sum()
+    assert st["form_a"][0] == form, st["form_a"][0]
+    if form in (2, 3):
+        assert st["sliced_len"][0] == _expected_sliced(rp, ci, form)
         assert nnz <= st["sliced_len"][0] <= nnz * 9 // 8
     else:
         assert st["sliced_len"][0] == 0
