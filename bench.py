@@ -63,9 +63,9 @@ def kernel_source_hash():
 # of CALIB_MIB MiB: that many bytes read and written).
 
 FINE_KERNELS = {  # tag -> (regex on the demangled name); level 0 = the largest grid
-    "spmv_dot_L0": r"k_(?:stream<\d+, |sell<)[^>]*OpSpmvXpayDev>",
-    "pre_L0": r"k_(?:stream<\d+, |sell<)[^>]*OpResid<double, double> >",
-    "post_L0": r"k_(?:stream<\d+, |sell<)[^>]*OpPost<double, double, double, 1> >",
+    "spmv_dot_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpSpmvXpayDev>",
+    "pre_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpResid<double, double> >",
+    "post_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpPost<double, double, double, 1> >",
 }
 
 
@@ -167,6 +167,17 @@ def summarize_profiles(a):
 
 
 CALIB_MIB = 512
+
+
+def csr_equivalent_bytes(name, level, st):
+    """Bytes of a level-0 FP64 sweep if its operator were streamed as CSR
+    (12 bytes per nonzero plus row pointers), for comparison with the
+    format-specific algorithmic bytes."""
+    if level != 0 or name not in ("spmv_dot", "pre", "post"):
+        return None
+    n, nnz = st["n"][0], st["nnz"][0]
+    vec = {"spmv_dot": 32.0, "pre": 24.0, "post": 32.0}[name] * n
+    return 12.0 * nnz + 4.0 * (n + 1) + vec
 
 
 def time_solves(H, B, X, tol, steps, warmup):
@@ -398,7 +409,7 @@ def run_adjoint(args, dev):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / k
-        out[prec] = dict(ms_per_step=round(ms, 3), steps_per_s=round(1e3 / ms, 2), loss_last=float(loss))
+        out[prec] = dict(ms_per_step=round(ms, 3), steps_per_s=round(1e3 / ms, 2), loss_last=float(loss.detach()))
         log(f"adjoint {N}^2 {prec}: {ms:.2f} ms per gradient step (refresh + forward + adjoint + pattern grad)")
         finalize()
     return out
@@ -581,6 +592,10 @@ def main():
                                          launches=r["launches"], bytes_per_launch=nbytes,
                                          gbs_avg=nbytes / (r["avg_ms"] * 1e-3) / 1e9,
                                          gbs_best=nbytes / (r["min_ms"] * 1e-3) / 1e9)
+        ceq = csr_equivalent_bytes(name, lvl, st)
+        if ceq:
+            # the same sweep counted with the CSR operator's bytes (12 per nonzero + row pointers)
+            kernels[f"{name}_L{lvl}"]["csr_equivalent_gbs"] = ceq / (r["avg_ms"] * 1e-3) / 1e9
     for k, d in kernels.items():
         log(f"kernel {k}: avg {d['avg_us']:.1f} us, min {d['min_us']:.1f} us, "
             f"{d['bytes_per_launch'] / 1e6:.1f} MB -> {d['gbs_avg']:.0f} GB/s avg, {d['gbs_best']:.0f} best")
@@ -591,6 +606,7 @@ def main():
         src_hash = kernel_source_hash()
         traffic = traffic_from_profiles(f"poisson3d_{N}_{dom_name}", src_hash)
         roofline = {"bound": "hbm", "achieved": round(dom["gbs_avg"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "csr_equivalent_gbs": round(dom.get("csr_equivalent_gbs", 0.0), 1) or None,
                     "frac": round(dom["gbs_avg"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom_name,
                     "bytes_per_launch": dom["bytes_per_launch"], "avg_us": round(dom["avg_us"], 2),
                     "launches_timed": dom["launches"], "copy_ceiling_gbs": round(copy_gbs, 1) if copy_gbs else None}
