@@ -122,6 +122,17 @@ struct Level {
   DBuf<double> pv, rv;
   DBuf<float> pv32, rv32;     // FP32 transfer copies (when not bf16)
   DBuf<uint16_t> pbf, rbf;    // bf16 transfer copies
+  // Product maps of the numeric Galerkin products (the patterns are fixed, so
+  // they are built once): for every output entry, the (x position, y
+  // position) pairs of its terms in ascending inner index.  AP = A P uses
+  // apm/apmo (per AP entry); A_{l+1} = R (AP) uses cm/cmo (per coarse entry).
+  // Absent when they would exceed the memory budget (search kernels then).
+  DBuf<int64_t> apmo, cmo;
+  DBuf<int2> apm, cm;
+  bool pmaps = false;
+  // Map of the prolongator fill: P entry e sums A entries pak[pao[e] ..
+  // pao[e+1]) (stored order) of row prow[e].
+  DBuf<int> pao, pak, prow;
   // A*P intermediate (kept for value refresh)
   int64_t apnnz = 0;
   DBuf<int> aprp, apci;

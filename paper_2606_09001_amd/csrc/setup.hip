@@ -359,6 +359,45 @@ __global__ void k_p_fill(int n, const int* __restrict__ rp, const int* __restric
   }
 }
 
+// Map of the prolongator fill (thread per row): for each P entry of row i,
+// the A entries of row i whose column lies in that entry's aggregate, in
+// stored order, and the entry's row.
+__global__ void k_pmap_build(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const int* __restrict__ agg, const int* __restrict__ prp, const int* __restrict__ pci,
+                             int* __restrict__ pao, int* __restrict__ pak, int* __restrict__ prow) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int t = rp[i];
+  for (int e = prp[i]; e < prp[i + 1]; ++e) {
+    pao[e] = t;
+    prow[e] = i;
+    const int J = pci[e];
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (agg[ci[k]] == J) pak[t++] = k;
+  }
+  // entries whose column has no aggregate belong to no P entry
+  for (; t < rp[i + 1]; ++t) pak[t] = -1;
+  if (i == n - 1) pao[prp[n]] = rp[n];
+}
+
+// Prolongator values through the map (thread per entry): the same
+// expression and fold as k_p_fill.
+__global__ void k_p_refill(int64_t pnnz, const int* __restrict__ pao, const int* __restrict__ pak,
+                           const int* __restrict__ prow, const int* __restrict__ pci, const double* __restrict__ v,
+                           int vs, const int* __restrict__ diagpos, const int* __restrict__ agg, double omegaP,
+                           double* __restrict__ pv) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= pnnz) return;
+  const int i = prow[e];
+  const double w = omegaP / v[(int64_t)diagpos[i] * vs];
+  double sJ = 0.0;
+  for (int t = pao[e]; t < pao[e + 1]; ++t)
+    if (pak[t] >= 0) sJ += v[(int64_t)pak[t] * vs];
+  const double delta = (pci[e] == agg[i]) ? 1.0 : 0.0;
+  const double ws = w * sJ;
+  pv[e * vs] = delta - ws;
+}
+
 __global__ void k_row_ids(int n, const int* __restrict__ rp, int* __restrict__ rowid) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -514,6 +553,65 @@ __global__ void k_spgemm_fill_entries(int nrows, int64_t cnnz, const int* __rest
   cv[e * vs] = acc;
 }
 
+// Product map of C = X Y on C's fixed pattern: number of terms per entry.
+__global__ void k_pm_count(int nrows, int64_t cnnz, const int* __restrict__ crp, const int* __restrict__ cci,
+                           const int* __restrict__ xrp, const int* __restrict__ xci, const int* __restrict__ yrp,
+                           const int* __restrict__ yci, int64_t* __restrict__ cnt) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e > cnnz) return;
+  if (e == cnnz) {
+    cnt[cnnz] = 0;
+    return;
+  }
+  int lo = 0, hi = nrows;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)crp[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int J = cci[e];
+  int64_t c = 0;
+  for (int a = xrp[lo]; a < xrp[lo + 1]; ++a) c += find_col(yci, yrp[xci[a]], yrp[xci[a] + 1], J) >= 0;
+  cnt[e] = c;
+}
+
+// Product map, pass 2: the (x position, y position) pairs of each entry in
+// ascending inner index (the order of the fold that forms the entry).
+__global__ void k_pm_fill(int nrows, int64_t cnnz, const int* __restrict__ crp, const int* __restrict__ cci,
+                          const int* __restrict__ xrp, const int* __restrict__ xci, const int* __restrict__ yrp,
+                          const int* __restrict__ yci, const int64_t* __restrict__ off, int2* __restrict__ pairs) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= cnnz) return;
+  int lo = 0, hi = nrows;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)crp[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int J = cci[e];
+  int64_t p = off[e];
+  for (int a = xrp[lo]; a < xrp[lo + 1]; ++a) {
+    const int q = find_col(yci, yrp[xci[a]], yrp[xci[a] + 1], J);
+    if (q >= 0) pairs[p++] = make_int2(a, q);
+  }
+}
+
+// Numeric product through the map: the same fold (ascending inner index, each
+// product rounded before the add) as k_spgemm_fill_entries, with all loads
+// independent of each other.
+__global__ void k_pm_apply(int64_t cnnz, const int64_t* __restrict__ off, const int2* __restrict__ pairs,
+                           const double* __restrict__ xv, const double* __restrict__ yv, double* __restrict__ cv,
+                           int vs) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= cnnz) return;
+  double acc = 0.0;
+  const int64_t p1 = off[e + 1];
+  for (int64_t p = off[e]; p < p1; ++p) {
+    const int2 t = pairs[p];
+    double prod = xv[(int64_t)t.x * vs] * yv[(int64_t)t.y * vs];
+    acc = acc + prod;
+  }
+  cv[e * vs] = acc;
+}
+
 // ------------------------------------------------------ precision copies
 
 __global__ void k_to_f32(int64_t m, const double* __restrict__ a, float* __restrict__ b) {
@@ -640,6 +738,38 @@ void cub_call(F&& f, hipStream_t s) {
 // Exclusive scan of cnt[0..m) into out[0..m) (int).
 void exclusive_scan(const int* cnt, int* out, int64_t m, hipStream_t s) {
   cub_call([&](void* t, size_t& b) { return hipcub::DeviceScan::ExclusiveSum(t, b, cnt, out, (int)m, s); }, s);
+}
+
+int64_t read_i64(const int64_t* d, hipStream_t s) {
+  int64_t h = 0;
+  AMG_HIP(hipMemcpyAsync(&h, d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+// Builds the product map of C = X Y on C's pattern; false (and nothing kept)
+// when its pairs would exceed `budget`.
+bool build_product_map(int nrows, int64_t cnnz, const int* crp, const int* cci, const int* xrp, const int* xci,
+                       const int* yrp, const int* yci, int64_t budget, DBuf<int64_t>& off, DBuf<int2>& pairs,
+                       hipStream_t s) {
+  DBuf<int64_t> cnt;
+  cnt.alloc(cnnz + 1);
+  hipLaunchKernelGGL(k_pm_count, dim3((unsigned)((cnnz + kBlock) / kBlock)), dim3(kBlock), 0, s, nrows, cnnz, crp, cci,
+                     xrp, xci, yrp, yci, cnt.p);
+  off.alloc(cnnz + 1);
+  cub_call([&](void* t, size_t& b) {
+    return hipcub::DeviceScan::ExclusiveSum(t, b, cnt.p, off.p, (int)(cnnz + 1), s);
+  }, s);
+  const int64_t total = read_i64(off.p + cnnz, s);
+  if (total > budget) {
+    off.release();
+    return false;
+  }
+  pairs.alloc(std::max<int64_t>(total, 1));
+  hipLaunchKernelGGL(k_pm_fill, dim3((unsigned)((cnnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nrows, cnnz, crp,
+                     cci, xrp, xci, yrp, yci, off.p, pairs.p);
+  AMG_HIP(hipStreamSynchronize(s));  // cnt is freed on return
+  return true;
 }
 
 int read_int(const int* d, hipStream_t s) {
@@ -797,9 +927,18 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     L.pci.alloc(L.pnnz);
     L.pv.alloc(L.pnnz * S);
   }
-  for (int sy = 0; sy < S; ++sy)
-    hipLaunchKernelGGL(k_p_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p + sy, S, L.diagpos.p, L.agg.p,
-                       L.omegaPS[sy], L.prp.p, sy == 0 ? L.pci.p : (int*)nullptr, L.pv.p + sy);
+  if (symbolic) {
+    hipLaunchKernelGGL(k_p_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p, S, L.diagpos.p, L.agg.p,
+                       L.omegaPS[0], L.prp.p, L.pci.p, L.pv.p);
+    L.pao.alloc(L.pnnz + 1);
+    L.pak.alloc(L.nnz);
+    L.prow.alloc(L.pnnz);
+    hipLaunchKernelGGL(k_pmap_build, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.agg.p, L.prp.p, L.pci.p,
+                       L.pao.p, L.pak.p, L.prow.p);
+  }
+  for (int sy = symbolic ? 1 : 0; sy < S; ++sy)
+    hipLaunchKernelGGL(k_p_refill, dim3(grid_for(L.pnnz)), b, 0, s, L.pnnz, L.pao.p, L.pak.p, L.prow.p, L.pci.p,
+                       L.v.p + sy, S, L.diagpos.p, L.agg.p, L.omegaPS[sy], L.pv.p + sy);
   AMG_HIP(hipGetLastError());
   // R = P^T
   const int nc = L.nagg;
@@ -849,6 +988,9 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     if (symbolic && sy == 0)
       hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p,
                          L.pv.p, L.aprp.p, L.apci.p, L.apv.p, S);
+    else if (L.pmaps)
+      hipLaunchKernelGGL(k_pm_apply, dim3(grid_for(L.apnnz)), b, 0, s, L.apnnz, L.apmo.p, L.apm.p, L.v.p + sy,
+                         L.pv.p + sy, L.apv.p + sy, S);
     else
       hipLaunchKernelGGL(k_spgemm_fill_entries, dim3(grid_for(L.apnnz)), b, 0, s, n, L.apnnz, L.aprp.p, L.apci.p,
                          L.rp.p, L.ci.p, L.v.p + sy, L.prp.p, L.pci.p, L.pv.p + sy, L.apv.p + sy, S);
@@ -876,10 +1018,29 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     // column pattern of the coarse operator (thread per row), values below
     hipLaunchKernelGGL(k_spgemm_cols, dim3(grid_for(nc)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p,
                        C.rp.p, C.ci.p);
+    // product maps for the refreshes (8 bytes per term; the budget keeps each
+    // map within 128 bytes per fine-level nonzero: about 1.6 GB in all for
+    // the 128^3 Poisson hierarchy)
+    const int64_t budget = std::max<int64_t>(16 * (int64_t)H.lv[0].nnz, 1 << 20);
+    Lr.pmaps = build_product_map(n, Lr.apnnz, Lr.aprp.p, Lr.apci.p, Lr.rp.p, Lr.ci.p, Lr.prp.p, Lr.pci.p, budget,
+                                 Lr.apmo, Lr.apm, s) &&
+               build_product_map(nc, C.nnz, C.rp.p, C.ci.p, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p, budget,
+                                 Lr.cmo, Lr.cm, s);
+    if (!Lr.pmaps) {
+      Lr.apmo.release();
+      Lr.apm.release();
+      Lr.cmo.release();
+      Lr.cm.release();
+    }
   }
-  for (int sy = 0; sy < S; ++sy)
-    hipLaunchKernelGGL(k_spgemm_fill_entries, dim3(grid_for(C.nnz)), b, 0, s, nc, C.nnz, C.rp.p, C.ci.p, Lr.rrp.p,
-                       Lr.rci.p, Lr.rv.p + sy, Lr.aprp.p, Lr.apci.p, Lr.apv.p + sy, C.v.p + sy, S);
+  for (int sy = 0; sy < S; ++sy) {
+    if (Lr.pmaps)
+      hipLaunchKernelGGL(k_pm_apply, dim3(grid_for(C.nnz)), b, 0, s, C.nnz, Lr.cmo.p, Lr.cm.p, Lr.rv.p + sy,
+                         Lr.apv.p + sy, C.v.p + sy, S);
+    else
+      hipLaunchKernelGGL(k_spgemm_fill_entries, dim3(grid_for(C.nnz)), b, 0, s, nc, C.nnz, C.rp.p, C.ci.p, Lr.rrp.p,
+                         Lr.rci.p, Lr.rv.p + sy, Lr.aprp.p, Lr.apci.p, Lr.apv.p + sy, C.v.p + sy, S);
+  }
   AMG_HIP(hipGetLastError());
 }
 
