@@ -603,11 +603,19 @@ __global__ void k_pm_apply(int64_t cnnz, const int64_t* __restrict__ off, const 
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= cnnz) return;
   double acc = 0.0;
-  const int64_t p1 = off[e + 1];
-  for (int64_t p = off[e]; p < p1; ++p) {
-    const int2 t = pairs[p];
-    double prod = xv[(int64_t)t.x * vs] * yv[(int64_t)t.y * vs];
-    acc = acc + prod;
+  const int64_t p0 = off[e], p1 = off[e + 1];
+  // 4 terms in flight: unconditional loads at clamped positions, the adds
+  // masked and in order
+  constexpr int U = 4;
+  for (int64_t p = p0; p < p1; p += U) {
+    int2 t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = pairs[min(p + u, p1 - 1)];
+    double prod[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) prod[u] = xv[(int64_t)t[u].x * vs] * yv[(int64_t)t[u].y * vs];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = p + u < p1 ? acc + prod[u] : acc;
   }
   cv[e * vs] = acc;
 }
