@@ -134,11 +134,19 @@ __global__ void k_diag(int n, const int* __restrict__ rp, const int* __restrict_
 __global__ void k_rho(int n, const int* __restrict__ rp, const double* __restrict__ v, int vs,
                       const int* __restrict__ diagpos, unsigned long long* out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) s += fabs(v[(int64_t)k * vs]);
-  double r = s / fabs(v[(int64_t)diagpos[i] * vs]);
-  atomicMax(out, (unsigned long long)__double_as_longlong(r));
+  unsigned long long bits = 0;  // +0.0: below every ratio
+  if (i < n) {
+    double s = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) s += fabs(v[(int64_t)k * vs]);
+    const double r = s / fabs(v[(int64_t)diagpos[i] * vs]);
+    bits = (unsigned long long)__double_as_longlong(r);
+  }
+  // wavefront maximum first: one atomic per wave instead of one per row
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long other = __shfl_xor(bits, o, 64);
+    bits = other > bits ? other : bits;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(out, bits);
 }
 
 // ------------------------------------------------------- strength graph
