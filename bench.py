@@ -367,6 +367,39 @@ def run_small(args, dev):
             "rel_resid": info["rel_resid"]}
 
 
+def run_plain_cg(args, dev):
+    """Unpreconditioned CG (precondition = 0) on tridiag(-1, 2.5, -1) with
+    10^7 unknowns, b ~ N(0,1) seed 32, to 1e-10 (the library as a plain
+    Krylov solver; the sliced operator sweep with the CG update)."""
+    import numpy as np
+    import torch
+    from paper_2606_09001_amd import matrices as M
+    from paper_2606_09001_amd.solver import AmgHierarchy, finalize
+    n = 10_000_000
+    rp, ci, v = M.tridiagonal(n, 2.5)
+    d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v, M.rhs_normal(n, 32))]
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    H = AmgHierarchy(d[0], d[1], d[2], precondition=0)
+    _, info = H.solve(d[3], 1e-10, out=x)
+    torch.cuda.synchronize()
+    k = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(k):
+        _, info = H.solve(d[3], 1e-10, out=x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / k
+    gbs = info["iters"] * H.kernel_bytes(None, 0) / (ms * 1e-3) / 1e9
+    log(f"plain CG tridiag 1e7: {ms:.2f} ms/solve ({1e3 / ms:.1f} solves/s), iters {info['iters']}, "
+        f"{gbs:.0f} GB/s over the solve")
+    H.close()
+    finalize()
+    return {"workload": "plain CG (no preconditioner) on tridiag(-1, 2.5, -1), n = 10^7, b ~ N(0,1) seed 32, tol 1e-10",
+            "ms_per_solve": round(ms, 3), "solves_per_s": round(1e3 / ms, 2), "iters": info["iters"],
+            "rel_resid": info["rel_resid"], "solve_hbm_gbs": round(gbs, 1), "solve_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def run_adjoint(args, dev):
     """2D diffusion 512^2 inverse-problem step: values k = exp(theta) assembled
     in torch, forward solve, loss 0.5||u - u_obs||^2, backward (adjoint solve
@@ -643,7 +676,7 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         batched = run_batched(args, dev)
-    diffusion = adjoint = small = None
+    diffusion = adjoint = small = plain = None
     if not args.no_extra:
         from paper_2606_09001_amd.solver import finalize
         finalize()
@@ -651,6 +684,7 @@ def main():
         diffusion = run_diffusion(args, dev)
         adjoint = run_adjoint(args, dev)
         small = run_small(args, dev)
+        plain = run_plain_cg(args, dev)
 
     f64, f32 = res["fp64"], res["fp32"]
     out = {
@@ -688,6 +722,7 @@ def main():
         "diffusion": diffusion,
         "adjoint": adjoint,
         "poisson2d_32": small,
+        "plain_cg_tridiag_1e7": plain,
         "ceilings": ceilings,
     }
     print(json.dumps(out), flush=True)

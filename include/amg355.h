@@ -80,6 +80,8 @@ typedef struct {
                           joined to the caller's stream by events); 0: launch every kernel */
   int autotune;        /* 1: time candidate kernel shapes per matrix at setup and keep the fastest
                           (cached across runs in $AMG_TUNE_CACHE if set); 0 (default): row-length rule */
+  int precondition;    /* 1 (default): AMG V-cycle preconditioner; 0: plain CG (z = r; the setup keeps
+                          level 0 only; one right-hand side and one system only) */
 } amg_params;
 
 typedef struct {

@@ -48,7 +48,7 @@ class amg_params(C.Structure):
         ("vcycle_prec", C.c_int), ("transfer_bf16", C.c_int), ("theta", C.c_double), ("max_coarse", C.c_int),
         ("max_levels", C.c_int), ("smoother", C.c_int), ("omega", C.c_double), ("nu_pre", C.c_int),
         ("nu_post", C.c_int), ("maxiter", C.c_int), ("flexible", C.c_int), ("symmetric", C.c_int),
-        ("check_every", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int),
+        ("check_every", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int), ("precondition", C.c_int),
     ]
 
 

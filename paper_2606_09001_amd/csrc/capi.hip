@@ -91,13 +91,15 @@ uint64_t params_hash(const amg_params& p) {
   h = mix(h, (uint64_t)p.nu_pre);
   h = mix(h, (uint64_t)p.nu_post);
   h = mix(h, (uint64_t)p.autotune);
+  h = mix(h, (uint64_t)p.precondition);
   return h;
 }
 
 bool same_setup_params(const amg_params& a, const amg_params& b) {
   return a.vcycle_prec == b.vcycle_prec && a.transfer_bf16 == b.transfer_bf16 && a.theta == b.theta &&
          a.max_coarse == b.max_coarse && a.max_levels == b.max_levels && a.smoother == b.smoother &&
-         a.omega == b.omega && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post && a.autotune == b.autotune;
+         a.omega == b.omega && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post && a.autotune == b.autotune &&
+         a.precondition == b.precondition;
 }
 
 amg_status check_params(const amg_params& p) {
@@ -107,6 +109,7 @@ amg_status check_params(const amg_params& p) {
   if (p.nu_pre < 1 || p.nu_post < 1 || p.nu_pre > 8 || p.nu_post > 8) return AMG_ERR_INVALID_ARG;
   if (!(p.omega > 0.0) || !(p.theta >= 0.0) || p.maxiter < 0) return AMG_ERR_INVALID_ARG;
   if (p.symmetric != 1) return AMG_ERR_INVALID_ARG;
+  if (p.precondition != 0 && p.precondition != 1) return AMG_ERR_INVALID_ARG;
   return AMG_OK;
 }
 
@@ -167,6 +170,7 @@ void amg_params_default(amg_params* p) {
   p->check_every = 0;
   p->use_graphs = 1;
   p->autotune = 0;
+  p->precondition = 1;
 }
 
 amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int32_t* d_row_ptr,

@@ -1238,7 +1238,7 @@ void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const doubl
   for (size_t l = 0;; ++l) {
     Level& L = H.lv[l];
     level_numerics(H, L, s);
-    bool last = L.n <= H.prm.max_coarse || (int)(l + 1) >= H.prm.max_levels;
+    bool last = L.n <= H.prm.max_coarse || (int)(l + 1) >= H.prm.max_levels || !H.prm.precondition;
     if (!last) {
       strength_graph(H, L, s);
       L.nagg = aggregate(H, L, s);
@@ -1251,7 +1251,7 @@ void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const doubl
     }
     transfer_and_galerkin(H, l, true, s);
   }
-  coarse_setup(H, s);
+  if (H.prm.precondition) coarse_setup(H, s);
   precision_copies(H, s);
   sliced_copies(H, true, s);
   alloc_cycle_vectors(H);
@@ -1268,7 +1268,7 @@ void refresh_hierarchy(Hierarchy& H, const double* d_val, hipStream_t s) {
     if (l + 1 == H.lv.size()) break;
     transfer_and_galerkin(H, l, false, s);
   }
-  coarse_setup(H, s);
+  if (H.prm.precondition) coarse_setup(H, s);
   precision_copies(H, s);
   sliced_copies(H, false, s);
   AMG_HIP(hipStreamSynchronize(s));

@@ -554,6 +554,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int n, double* __restrict_
   publish_partials<1>(d, partials);
 }
 
+// z = r (the identity preconditioner of plain CG).
+__global__ void __launch_bounds__(kBlock) k_copy_z(int n, const double* __restrict__ r, double* __restrict__ z,
+                                                   const Ctl* __restrict__ ctl) {
+  if (ctl && ctl->done) return;
+  const int base = vec_base();
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) z[i] = r[i];
+  }
+}
+
 // x0 = sw o r (first V-cycle of a solve or restart).
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_sw_mul(int n, const T* __restrict__ sw, const double* __restrict__ r,
@@ -840,6 +852,17 @@ void vcycle_impl(Hierarchy& H, const CycleArgs& a, hipStream_t s) {
   const int nl = (int)H.lv.size();
   Coarse& C = H.co;
   Ctl* ctl = a.ctl;
+  if (!H.prm.precondition) {
+    // plain CG: z = r
+    const int n = H.n;
+    hipLaunchKernelGGL(k_copy_z, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, a.r0, a.z0, ctl);
+    if (a.red) {
+      const int g = vec_grid(n);
+      hipLaunchKernelGGL(k_dots_rz, dim3(g), dim3(kBlock), 0, s, n, a.r0, a.z0, a.q ? a.q : a.z0, ctl, a.partials);
+      launch_fin_beta(ctl, a.partials, g, a.first, 2, s);
+    }
+    return;
+  }
   if (nl == 1) {
     {
       InstScope is(H, KID_COARSE, 0, s, a.ctl);
@@ -1299,6 +1322,8 @@ double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible) {
 // Bytes of one PCG iteration (SpMV+dot, update, V-cycle, direction update).
 double iteration_bytes(const Hierarchy& H, int flexible) {
   const int nl = (int)H.lv.size();
+  if (!H.prm.precondition)  // plain CG: z = r (16n), <r,z>, <z,q> partials (24n)
+    return kernel_bytes(H, KID_SPMV_DOT, 0, flexible) + kernel_bytes(H, KID_CG_UPDATE, 0, flexible) + 40.0 * H.n;
   double b = kernel_bytes(H, KID_SPMV_DOT, 0, flexible) + kernel_bytes(H, KID_CG_UPDATE, 0, flexible) +
              kernel_bytes(H, KID_XPAY, 0, flexible) + kernel_bytes(H, KID_COARSE, nl - 1, flexible);
   for (int l = 0; l < nl - 1; ++l) {

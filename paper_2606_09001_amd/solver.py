@@ -20,7 +20,8 @@ __all__ = ["AmgHierarchy", "solve", "amg_solve", "AmgSolve", "make_params", "fin
            "set_cache_capacity", "make_preconditioner"]
 
 _PARAM_KEYS = ("vcycle_prec", "transfer_bf16", "theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre",
-               "nu_post", "maxiter", "flexible", "symmetric", "check_every", "use_graphs", "autotune")
+               "nu_post", "maxiter", "flexible", "symmetric", "check_every", "use_graphs", "autotune",
+               "precondition")
 
 
 def make_params(**kw) -> _lib.amg_params:

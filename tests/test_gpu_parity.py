@@ -329,3 +329,49 @@ def test_level0_sweep_form(case, form):
         assert nnz <= st["sliced_len"][0] <= nnz * 9 // 8
     else:
         assert st["sliced_len"][0] == 0
+
+
+@pytest.mark.parametrize("case", ["poisson2d_32", "tridiag_3000", "diffusion2d_64"])
+def test_plain_cg_matches_oracle(case):
+    """precondition = 0: plain CG (z = r) on a level-0-only setup, against the
+    oracle's unpreconditioned CG: counts within 1 + 1 %, iterate parity at a
+    fixed count."""
+    import oracle
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    rp, ci, v = CASES[case]()
+    n = len(rp) - 1
+    b = M.rhs_normal(n, 31)
+    O = oracle.OracleHierarchy(rp, ci, v)
+    H = AmgHierarchy(dev(rp), dev(ci), dev(v), precondition=0, maxiter=5000)
+    assert H.stats()["num_levels"] == 1
+    x, info = H.solve(dev(b), 1e-10)
+    xo, io = O.pcg(b, tol=1e-10, maxiter=5000, precondition=False)
+    assert info["status"] == 0 and io["status"] == 0
+    # hundreds of unpreconditioned iterations amplify the rounding difference
+    # of the dot-product folds: counts agree to one percent (plus one)
+    assert abs(info["iters"] - io["iters"]) <= 1 + io["iters"] // 100, (info["iters"], io["iters"])
+    assert oracle.rel_residual(rp, ci, v, b, host(x)) <= 1e-10
+    k = min(io["iters"], 40)
+    Hk = AmgHierarchy(dev(rp), dev(ci), dev(v), precondition=0, maxiter=k)
+    xk, ik = Hk.solve(dev(b), 0.0)
+    xok, _ = O.pcg(b, tol=0.0, maxiter=k, precondition=False)
+    assert ik["iters"] == k
+    assert np.linalg.norm(host(xk) - xok) <= 1e-9 * np.linalg.norm(xok)
+    # the identity preconditioner applied alone
+    z = host(H.apply_vcycle(dev(b)))
+    assert np.array_equal(z, b)
+
+
+def test_plain_cg_large_tridiagonal():
+    """Plain CG on tridiag(-1, 2.5, -1) with 10^7 unknowns (no coarse factor
+    is formed): converges, true residual from the oracle's SpMV."""
+    import oracle
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    n = 10_000_000
+    rp, ci, v = M.tridiagonal(n, 2.5)
+    b = M.rhs_normal(n, 32)
+    H = AmgHierarchy(dev(rp), dev(ci), dev(v), precondition=0)
+    x, info = H.solve(dev(b), 1e-10)
+    assert info["status"] == 0 and info["rel_resid"] <= 1e-10
+    assert oracle.rel_residual(rp, ci, v, b, host(x)) <= 1e-10
+    assert H.stats()["form_a"][0] == 3

@@ -38,7 +38,7 @@ def test_params_default_and_status_strings():
     L.amg_params_default(C.byref(p))
     assert p.vcycle_prec == _lib.AMG_PREC_FP64 and p.max_coarse == 256 and p.max_levels == 20
     assert p.omega == pytest.approx(2.0 / 3.0) and p.nu_pre == 1 and p.nu_post == 1
-    assert p.theta == 0.0 and p.symmetric == 1 and p.flexible == -1
+    assert p.theta == 0.0 and p.symmetric == 1 and p.flexible == -1 and p.precondition == 1
     for st, name in [(0, "AMG_OK"), (1, "AMG_NOT_CONVERGED"), (-1, "AMG_ERR_INVALID_ARG"),
                      (-4, "AMG_ERR_BREAKDOWN"), (-7, "AMG_ERR_COARSE_TOO_LARGE")]:
         assert _lib.status_string(st) == name
@@ -63,6 +63,9 @@ def test_setup_rejects_bad_arguments_before_touching_a_device():
     p.symmetric = 0
     assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
     p.symmetric = 1
+    p.precondition = 2
+    assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    p.precondition = 1
     p.max_levels = 99
     assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
     assert L.amg_solve(None, 1, 1, 1e-8, 1, None, None) == _lib.AMG_ERR_INVALID_ARG
