@@ -1,5 +1,5 @@
-// FP64 CPU oracle for smoothed-aggregation AMG-preconditioned CG and its
-// adjoint.  TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check
+// FP64 CPU oracle for smoothed-aggregation AMG-preconditioned CG and
+// BiCGSTAB and their adjoints.  TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check
 // and the benchmark's CPU-baseline leg load this library; the product path
 // never does.  It shares no code, header or table with the HIP library.
 //
@@ -11,7 +11,9 @@
 // the smoothed-aggregation definition written out below (strength graph,
 // distance-2 maximal independent set roots in decreasing-key order,
 // aggregates, smoothed prolongator, Galerkin product, damped-Jacobi V(1,1),
-// PCG).
+// PCG; for a nonsymmetric A: an LU coarse solve, right-preconditioned
+// BiCGSTAB -- the paper's default solver, Section 2.2 -- and an adjoint on the
+// explicit transpose, Section 2.2 "Automatic differentiation").
 //
 // Build: g++ -O2 -std=c++17 -ffp-contract=off -shared -fPIC (no FMA
 // contraction: every product and sum is rounded on its own).
@@ -19,7 +21,8 @@
 // Parity pins: see the oracle tests (closed-form Laplacian spectrum,
 // manufactured eigenvector solutions, brute-force MIS-2 characterisation,
 // dense Galerkin products, dense V-cycle symmetry/SPD, SciPy CG iterates,
-// dense adjoint gradients and central finite differences).
+// dense adjoint gradients and central finite differences; SciPy BiCGSTAB
+// iterates, LAPACK LU and inverses, dense nonsymmetric adjoints).
 
 #include <algorithm>
 #include <cmath>
@@ -58,6 +61,7 @@ struct Params {
   int smoother;  // 0 damped Jacobi, 1 L1-Jacobi
   double omega;
   int nu_pre, nu_post;
+  int symmetric;  // 1: Cholesky coarse factor; 0: LU with partial pivoting
 };
 
 struct Level {
@@ -74,7 +78,8 @@ struct Level {
 struct Hier {
   Params prm;
   std::vector<Level> lv;        // lv.back() is the coarsest level
-  std::vector<double> L;        // dense Cholesky factor of the coarsest A, row-major lower
+  std::vector<double> L;        // dense factor of the coarsest A, row-major: Cholesky (lower) or packed LU
+  std::vector<int> piv;         // LU only: row exchanged with row k at elimination step k
   int nL = 0;
 };
 
@@ -355,9 +360,61 @@ int coarse_factor(Hier& H) {
   return OR_OK;
 }
 
+// Dense LU with partial pivoting of the coarsest matrix (Gaussian
+// elimination with row interchanges, one column at a time): at step k the
+// pivot is the first row i >= k of largest |w_ik|; rows k and pivot are
+// exchanged over the full width, the multipliers w_ik / w_kk are stored below
+// the diagonal, and every w_ij with i, j > k loses multiplier times w_kj.
+int coarse_lu(Hier& H) {
+  const Csr& A = H.lv.back().A;
+  int n = A.nrows;
+  if (n > kMaxDenseCoarse) return OR_ERR_COARSE_TOO_LARGE;
+  H.nL = n;
+  std::vector<double> W((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) W[(size_t)i * n + A.ci[k]] = A.v[k];
+  H.piv.assign(n, 0);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::fabs(W[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double a = std::fabs(W[(size_t)i * n + k]);
+      if (a > best) { best = a; p = i; }
+    }
+    if (!(best > 0.0)) return OR_ERR_BREAKDOWN;  // singular (or NaN) coarse matrix
+    H.piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(W[(size_t)k * n + j], W[(size_t)p * n + j]);
+    double ukk = W[(size_t)k * n + k];
+    for (int i = k + 1; i < n; ++i) W[(size_t)i * n + k] = W[(size_t)i * n + k] / ukk;
+    for (int i = k + 1; i < n; ++i) {
+      double l = W[(size_t)i * n + k];
+      for (int j = k + 1; j < n; ++j) W[(size_t)i * n + j] = W[(size_t)i * n + j] - l * W[(size_t)k * n + j];
+    }
+  }
+  H.L = W;
+  return OR_OK;
+}
+
 void coarse_solve(const Hier& H, const double* b, double* x) {
   int n = H.nL;
   const std::vector<double>& L = H.L;
+  if (!H.prm.symmetric) {
+    // P A = L U: y = P b, L y' = y (unit lower), U x = y'
+    std::vector<double> y(b, b + n);
+    for (int k = 0; k < n; ++k) std::swap(y[k], y[H.piv[k]]);
+    for (int i = 0; i < n; ++i) {
+      double s = y[i];
+      for (int j = 0; j < i; ++j) s -= L[(size_t)i * n + j] * y[j];
+      y[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int j = i + 1; j < n; ++j) s -= L[(size_t)i * n + j] * x[j];
+      x[i] = s / L[(size_t)i * n + i];
+    }
+    return;
+  }
   std::vector<double> y(n);
   for (int i = 0; i < n; ++i) {
     double s = b[i];
@@ -411,7 +468,7 @@ int build_levels(Hier& H, bool refresh) {
     }
     ++l;
   }
-  return coarse_factor(H);
+  return prm.symmetric ? coarse_factor(H) : coarse_lu(H);
 }
 
 // ---------------------------------------------------------------- solve
@@ -538,18 +595,121 @@ int pcg(const Hier& H, const double* bptr, double* xptr, double tol, int maxiter
   return status == OR_OK || trr <= thresh ? OR_OK : OR_NOT_CONVERGED;
 }
 
+// Right-preconditioned BiCGSTAB (van der Vorst, 1992) from x0 = 0, the
+// paper's default Krylov method (Section 2.2).  Shadow residual r^ = r0.
+// One iteration:
+//   rho = <r^, r>;  p = r (first) or r + beta (p - omega v),
+//                   beta = (rho / rho_old) (alpha / omega)
+//   y = M p;  v = A y;  alpha = rho / <r^, v>
+//   x = x + alpha y;  s = r - alpha v        (stop here if ||s|| is small)
+//   z = M s;  t = A z;  omega = <t, s> / <t, t>
+//   x = x + omega z;  r = s - omega t
+// Iterations count full steps (a stop at s counts its step).  Stops when
+// ||s||^2 or ||r||^2 <= tol^2 ||b||^2; then the true residual b - A x is
+// formed and, if it misses the tolerance, the method restarts from it
+// (r^ = r = b - A x; at most 5 times).  Breakdown: rho, <r^, v>, <t, t> or
+// omega zero or NaN.  hist (optional, maxiter entries): relative recursive
+// residual at the end of each step.
+int bicgstab(const Hier& H, const double* bptr, double* xptr, double tol, int maxiter, int use_prec,
+             int* iters_out, double* relres_out, double* hist) {
+  const Csr& A = H.lv[0].A;
+  int n = A.nrows;
+  std::vector<double> b(bptr, bptr + n), x(n, 0.0), r(n), rh(n), p(n, 0.0), v(n, 0.0), y(n), s(n), z(n), t(n);
+  double bb = dot(b, b);
+  *iters_out = 0;
+  if (!(bb == bb)) { std::copy(x.begin(), x.end(), xptr); *relres_out = NAN; return OR_ERR_BREAKDOWN; }
+  if (bb == 0.0) {
+    std::copy(x.begin(), x.end(), xptr);
+    *relres_out = 0.0;
+    return OR_OK;
+  }
+  double thresh = (tol * tol) * bb;
+  r = b;
+  int iters = 0, replacements = 0, status = OR_NOT_CONVERGED;
+  bool breakdown = false;
+  for (;;) {
+    rh = r;
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    bool first = true, conv = false;
+    while (iters < maxiter) {
+      double rho = dot(rh, r);
+      if (!(rho != 0.0) || !(rho == rho)) { breakdown = true; break; }
+      if (first) {
+        p = r;
+        first = false;
+      } else {
+        double beta = (rho / rho_old) * (alpha / omega);
+        for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+      }
+      apply_prec(H, use_prec, p, y, iters);
+      spmv(A, y.data(), v.data());
+      double rv = dot(rh, v);
+      if (!(rv != 0.0) || !(rv == rv)) { breakdown = true; break; }
+      alpha = rho / rv;
+      for (int i = 0; i < n; ++i) {
+        x[i] = x[i] + alpha * y[i];
+        s[i] = r[i] - alpha * v[i];
+      }
+      ++iters;
+      double ss = dot(s, s);
+      if (ss <= thresh) {
+        r = s;
+        if (hist) hist[iters - 1] = std::sqrt(ss / bb);
+        conv = true;
+        break;
+      }
+      apply_prec(H, use_prec, s, z, iters);
+      spmv(A, z.data(), t.data());
+      double tt = dot(t, t), ts = dot(t, s);
+      if (!(tt > 0.0)) { breakdown = true; break; }
+      omega = ts / tt;
+      if (!(omega != 0.0) || !(omega == omega)) { breakdown = true; break; }
+      for (int i = 0; i < n; ++i) {
+        x[i] = x[i] + omega * z[i];
+        r[i] = s[i] - omega * t[i];
+      }
+      double rr = dot(r, r);
+      if (hist) hist[iters - 1] = std::sqrt(rr / bb);
+      if (rr <= thresh) { conv = true; break; }
+      if (!(rr == rr)) { breakdown = true; break; }
+      rho_old = rho;
+    }
+    if (breakdown || !conv) break;
+    std::vector<double> Ax(n);
+    spmv(A, x.data(), Ax.data());
+    for (int i = 0; i < n; ++i) r[i] = b[i] - Ax[i];
+    double trr = dot(r, r);
+    if (trr <= thresh) { status = OR_OK; break; }
+    if (replacements >= 5 || iters >= maxiter) break;
+    ++replacements;
+  }
+  std::vector<double> Ax(n);
+  spmv(A, x.data(), Ax.data());
+  double trr = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double d = b[i] - Ax[i];
+    trr += d * d;
+  }
+  *relres_out = std::sqrt(trr / bb);
+  *iters_out = iters;
+  std::copy(x.begin(), x.end(), xptr);
+  if (breakdown) return OR_ERR_BREAKDOWN;
+  return status == OR_OK || trr <= thresh ? OR_OK : OR_NOT_CONVERGED;
+}
+
 }  // namespace
 
 // ================================================================ C API
 extern "C" {
 
 void* or_setup(int n, const int* rp, const int* ci, const double* v, double theta, int max_coarse, int max_levels,
-               int smoother, double omega, int nu_pre, int nu_post, int* status) {
+               int smoother, double omega, int nu_pre, int nu_post, int symmetric, int* status) {
   int st = validate_csr(n, rp, ci);
-  if (st == OR_OK && (max_levels < 1 || max_coarse < 1 || nu_pre < 1 || nu_post < 1)) st = OR_ERR_INVALID_ARG;
+  if (st == OR_OK && (max_levels < 1 || max_coarse < 1 || nu_pre < 1 || nu_post < 1 || (symmetric != 0 && symmetric != 1)))
+    st = OR_ERR_INVALID_ARG;
   if (st != OR_OK) { *status = st; return nullptr; }
   Hier* H = new Hier;
-  H->prm = Params{theta, max_coarse, max_levels, smoother, omega, nu_pre, nu_post};
+  H->prm = Params{theta, max_coarse, max_levels, smoother, omega, nu_pre, nu_post, symmetric};
   H->lv.emplace_back();
   Csr& A = H->lv[0].A;
   A.nrows = A.ncols = n;
@@ -614,6 +774,34 @@ int or_coarse_factor(void* h, double* Lout) {
   return H->nL;
 }
 
+// LU pivots of the coarsest level (nonsymmetric hierarchies; returns nL, or
+// 0 for a Cholesky factor).
+int or_coarse_pivots(void* h, int* piv) {
+  Hier* H = (Hier*)h;
+  if (H->prm.symmetric) return 0;
+  std::copy(H->piv.begin(), H->piv.end(), piv);
+  return H->nL;
+}
+
+int or_bicgstab(void* h, const double* b, double* x, double tol, int maxiter, int use_prec, int* iters,
+                double* relres, double* hist) {
+  return bicgstab(*(Hier*)h, b, x, tol, maxiter, use_prec, iters, relres, hist);
+}
+
+// Explicit transpose of an n x n CSR matrix (rows of the result list source
+// rows ascending): the operator of the nonsymmetric adjoint, Eq. (1).
+void or_transpose(int n, const int* rp, const int* ci, const double* v, int* rpT, int* ciT, double* vT) {
+  Csr A;
+  A.nrows = A.ncols = n;
+  A.rp.assign(rp, rp + n + 1);
+  A.ci.assign(ci, ci + rp[n]);
+  A.v.assign(v, v + rp[n]);
+  Csr T = transpose(A);
+  std::copy(T.rp.begin(), T.rp.end(), rpT);
+  std::copy(T.ci.begin(), T.ci.end(), ciT);
+  std::copy(T.v.begin(), T.v.end(), vT);
+}
+
 int or_vcycle(void* h, const double* b, double* x) {
   vcycle(*(Hier*)h, 0, b, x);
   return OR_OK;
@@ -624,8 +812,9 @@ int or_pcg(void* h, const double* b, double* x, double tol, int maxiter, int fle
   return pcg(*(Hier*)h, b, x, tol, maxiter, flexible, use_prec, iters, relres, hist, conj);
 }
 
-// Adjoint (Eq. (1)): A^T lambda = g.  The oracle requires a symmetric A, so
-// the adjoint solve runs PCG with A's own hierarchy and the same settings.
+// Adjoint (Eq. (1)) of a symmetric A: A^T lambda = g is solved by PCG with
+// A's own hierarchy and the same settings.  (A nonsymmetric A's adjoint is
+// solved on the hierarchy of its explicit transpose, or_transpose.)
 int or_solve_adjoint(void* h, const double* g, double* lam, double tol, int maxiter, int flexible, int* iters,
                      double* relres) {
   return pcg(*(Hier*)h, g, lam, tol, maxiter, flexible, 1, iters, relres, nullptr, nullptr);

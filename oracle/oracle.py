@@ -10,7 +10,7 @@ import os
 
 import numpy as np
 
-__all__ = ["OracleHierarchy", "spmv", "pattern_grad", "rel_residual", "node_key", "validate",
+__all__ = ["OracleHierarchy", "spmv", "pattern_grad", "rel_residual", "node_key", "validate", "transpose",
            "diffusion_theta_grad", "OR_OK", "OR_NOT_CONVERGED", "OR_ERR_INVALID_ARG", "OR_ERR_ZERO_DIAG",
            "OR_ERR_PATTERN_MISMATCH", "OR_ERR_BREAKDOWN", "OR_ERR_COARSE_TOO_LARGE", "load"]
 
@@ -40,7 +40,7 @@ def load():
     L = C.CDLL(path)
     L.or_setup.restype = C.c_void_p
     L.or_setup.argtypes = [C.c_int, _ip, _ip, _dp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
-                           C.c_int, C.POINTER(C.c_int)]
+                           C.c_int, C.c_int, C.POINTER(C.c_int)]
     L.or_update_values.restype = C.c_int
     L.or_update_values.argtypes = [C.c_void_p, _dp]
     L.or_destroy.argtypes = [C.c_void_p]
@@ -52,6 +52,12 @@ def load():
     L.or_export_level.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 14
     L.or_coarse_factor.restype = C.c_int
     L.or_coarse_factor.argtypes = [C.c_void_p, _dp]
+    L.or_coarse_pivots.restype = C.c_int
+    L.or_coarse_pivots.argtypes = [C.c_void_p, _ip]
+    L.or_bicgstab.restype = C.c_int
+    L.or_bicgstab.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
+                              C.POINTER(C.c_double), C.c_void_p]
+    L.or_transpose.argtypes = [C.c_int, _ip, _ip, _dp, _ip, _ip, _dp]
     L.or_vcycle.restype = C.c_int
     L.or_vcycle.argtypes = [C.c_void_p, _dp, _dp]
     L.or_pcg.restype = C.c_int
@@ -91,17 +97,26 @@ class OracleError(RuntimeError):
 
 
 class OracleHierarchy:
-    """FP64 SA-AMG hierarchy built on the host by the oracle."""
+    """FP64 SA-AMG hierarchy built on the host by the oracle.
+
+    symmetric=False: the coarsest level gets an LU factorization with partial
+    pivoting instead of Cholesky, and the adjoint is solved on the hierarchy
+    of the explicit transpose (built on first use with the same parameters).
+    """
 
     def __init__(self, row_ptr, col, val, theta=0.0, max_coarse=256, max_levels=20, smoother="jacobi",
-                 omega=2.0 / 3.0, nu_pre=1, nu_post=1):
+                 omega=2.0 / 3.0, nu_pre=1, nu_post=1, symmetric=True):
         L = load()
         self.rp, self.ci, self.v = _i32(row_ptr), _i32(col), _f64(val)
         self.n = len(self.rp) - 1
+        self.symmetric = bool(symmetric)
+        self._kw = dict(theta=theta, max_coarse=max_coarse, max_levels=max_levels, smoother=smoother, omega=omega,
+                        nu_pre=nu_pre, nu_post=nu_post)
+        self._adj = None
         st = C.c_int(0)
         sm = {"jacobi": 0, "l1": 1}[smoother]
         h = L.or_setup(self.n, self.rp, self.ci, self.v, float(theta), int(max_coarse), int(max_levels), sm,
-                       float(omega), int(nu_pre), int(nu_post), C.byref(st))
+                       float(omega), int(nu_pre), int(nu_post), int(self.symmetric), C.byref(st))
         if not h:
             raise OracleError(st.value, "setup")
         self._h = h
@@ -151,10 +166,18 @@ class OracleHierarchy:
         return out
 
     def coarse_factor(self):
+        """Cholesky factor (lower) or, for symmetric=False, the packed LU
+        factor (unit-lower multipliers below the diagonal, U on and above)."""
         n = self.level_sizes(self.num_levels - 1)["n"]
         Lf = np.zeros(n * n)
         self._L.or_coarse_factor(self._h, Lf)
         return Lf.reshape(n, n)
+
+    def coarse_pivots(self):
+        """LU pivot rows (row exchanged with row k at step k); None for Cholesky."""
+        n = self.level_sizes(self.num_levels - 1)["n"]
+        piv = np.zeros(n, np.int32)
+        return piv if self._L.or_coarse_pivots(self._h, piv) else None
 
     # -- numerics
     def update_values(self, val):
@@ -162,6 +185,8 @@ class OracleHierarchy:
         st = self._L.or_update_values(self._h, self.v)
         if st:
             raise OracleError(st, "update_values")
+        if self._adj is not None:
+            self._adj.update_values(transpose(self.rp, self.ci, self.v)[2])
 
     def vcycle(self, b):
         b = _f64(b)
@@ -193,7 +218,35 @@ class OracleHierarchy:
             info["conj"] = conj[:max(it.value - 1, 0)].copy()
         return x, info
 
-    def solve_adjoint(self, g, tol=1e-8, maxiter=1000, flexible=False):
+    def bicgstab(self, b, tol=1e-8, maxiter=1000, precondition=True, history=False):
+        """Right-preconditioned BiCGSTAB from x0 = 0; returns (x, info) like pcg."""
+        b = _f64(b)
+        x = np.zeros(self.n)
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        hist = np.zeros(max(maxiter, 1)) if history else None
+        st = self._L.or_bicgstab(self._h, b, x, float(tol), int(maxiter), int(bool(precondition)), C.byref(it),
+                                 C.byref(rr), _ptr(hist))
+        info = dict(iters=it.value, rel_resid=rr.value, status=st)
+        if history:
+            info["history"] = hist[:it.value].copy()
+        return x, info
+
+    def transpose_hierarchy(self):
+        """Hierarchy of A^T with the same parameters (nonsymmetric adjoint)."""
+        if self._adj is None:
+            rpT, ciT, vT = transpose(self.rp, self.ci, self.v)
+            self._adj = OracleHierarchy(rpT, ciT, vT, symmetric=False, **self._kw)
+        return self._adj
+
+    def solve_adjoint(self, g, tol=1e-8, maxiter=1000, flexible=False, solver="pcg"):
+        """A^T lambda = g (Eq. (1)).  Symmetric A: A's own hierarchy; otherwise
+        the hierarchy of the explicit transpose.  solver: "pcg" or "bicgstab"
+        (a nonsymmetric A always takes BiCGSTAB)."""
+        if not self.symmetric:
+            return self.transpose_hierarchy().bicgstab(g, tol=tol, maxiter=maxiter)
+        if solver == "bicgstab":
+            return self.bicgstab(g, tol=tol, maxiter=maxiter)
         g = _f64(g)
         lam = np.zeros(self.n)
         it = C.c_int(0)
@@ -219,6 +272,17 @@ def pattern_grad(rp, ci, lam, x):
     g = np.zeros(len(ci))
     load().or_pattern_grad(len(rp) - 1, rp, ci, lam, x, g)
     return g
+
+
+def transpose(rp, ci, v):
+    """Explicit CSR transpose (row_ptr, col, val) of a square CSR matrix."""
+    rp, ci, v = _i32(rp), _i32(ci), _f64(v)
+    n = len(rp) - 1
+    rpT = np.zeros(n + 1, np.int32)
+    ciT = np.zeros(len(ci), np.int32)
+    vT = np.zeros(len(ci))
+    load().or_transpose(n, rp, ci, v, rpT, ciT, vT)
+    return rpT, ciT, vT
 
 
 def rel_residual(rp, ci, v, b, x):

@@ -26,7 +26,8 @@ import numpy as np
 __all__ = [
     "stencil_offsets", "poisson", "diffusion", "diffusion_face_coeffs",
     "diffusion_values_torch", "tridiagonal", "grf", "rhs_normal", "rhs_ones",
-    "expected_nnz", "grid_coords", "csr_to_dense",
+    "expected_nnz", "grid_coords", "csr_to_dense", "convection_diffusion", "recirculating_wind",
+    "drop_entries",
 ]
 
 
@@ -92,6 +93,59 @@ def poisson(N: int, d: int):
     for off, a, sgn in stencil_offsets(N, d):
         vals.append(np.full(n, float(2 * d) if sgn == 0 else -1.0))
     return _pack_stencil(N, d, vals)
+
+
+def convection_diffusion(N: int, d: int, wind):
+    """-Laplace(u) + w . grad(u) with first-order upwind differences, scaled
+    like ``poisson`` (by h^2): a nonsymmetric M-matrix with a symmetric
+    pattern.  Row i, axis a, w = w_a(x_i):
+        diagonal          2d + h sum_a |w_a|
+        neighbour -e_a    -1 - h max(w_a, 0)
+        neighbour +e_a    -1 - h max(-w_a, 0)
+    ``wind`` holds d entries (axis 0 = x), each a constant or an array of
+    the n unknowns' values; the cell Peclet number is h |w_a| / 2.
+    """
+    n = N ** d
+    h = 1.0 / (N + 1)
+    w = [np.broadcast_to(np.asarray(wa, dtype=np.float64), (n,)) for wa in wind]
+    assert len(w) == d
+    vals = []
+    for off, a, sgn in stencil_offsets(N, d):
+        if sgn == 0:
+            dg = np.full(n, float(2 * d))
+            for wa in w:
+                dg = dg + h * np.abs(wa)
+            vals.append(dg)
+        elif sgn < 0:
+            vals.append(-1.0 - h * np.maximum(w[a], 0.0))
+        else:
+            vals.append(-1.0 - h * np.maximum(-w[a], 0.0))
+    return _pack_stencil(N, d, vals)
+
+
+def recirculating_wind(N: int, d: int, speed: float):
+    """Rotating flow w = speed (sin(pi x) cos(pi y), -cos(pi x) sin(pi y), 0)."""
+    c = grid_coords(N, d)
+    x, y = c[0], c[1]
+    w = [speed * np.sin(np.pi * x) * np.cos(np.pi * y), -speed * np.cos(np.pi * x) * np.sin(np.pi * y)]
+    w += [np.zeros_like(x)] * (d - 2)
+    return w
+
+
+def drop_entries(row_ptr, col, val, frac: float, seed: int):
+    """Structurally nonsymmetric variant: removes a seeded random fraction of
+    the strictly upper off-diagonal entries (numpy default_rng(seed)); the
+    diagonal and the lower part are kept, so diagonal dominance is kept."""
+    row_ptr = np.asarray(row_ptr)
+    n = len(row_ptr) - 1
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    rng = np.random.default_rng(seed)
+    drop = (np.asarray(col) > rows) & (rng.random(len(col)) < frac)
+    keep = ~drop
+    counts = np.bincount(rows[keep], minlength=n)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp[1:])
+    return rp.astype(np.int32), np.asarray(col)[keep].astype(np.int32), np.ascontiguousarray(np.asarray(val)[keep])
 
 
 def diffusion_face_coeffs(k: np.ndarray):
