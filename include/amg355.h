@@ -1,6 +1,6 @@
 /*
- * amg355.h - C ABI of the MI355X (gfx950) smoothed-aggregation AMG-PCG
- * library with adjoint solves.
+ * amg355.h - C ABI of the MI355X (gfx950) smoothed-aggregation AMG library
+ * (preconditioned CG and BiCGSTAB) with adjoint solves.
  *
  * What the calls compute (the paper delegates the numerical method to its
  * backend; the operations below are the ones its interface exposes):
@@ -9,7 +9,11 @@
  *   - a setup cached per sparsity pattern; a cache hit with new values updates
  *     the coefficients in place and repeats the numeric setup -- Section 2.1
  *     ("C++/CUDA backend")
- *   - the adjoint solve A^T lambda = dL/dx            -- Eq. (1)
+ *   - the adjoint solve A^T lambda = dL/dx            -- Eq. (1); a
+ *     nonsymmetric A gets an explicit transpose A^T and its own hierarchy
+ *     (Section 2.2, "Automatic differentiation")
+ *   - BiCGSTAB with the AMG preconditioner, the paper's default solver for
+ *     general (nonsymmetric) systems                  -- Section 2.2
  *   - the gradients dL/dA = -lambda x^T (restricted to the stored pattern)
  *     and dL/db = lambda                              -- Eq. (2)
  *   - single- and double-precision arithmetic         -- Section 2.2
@@ -49,7 +53,8 @@ typedef enum {
   AMG_ERR_INVALID_ARG = -1,         /* bad pointer/size/params or malformed CSR */
   AMG_ERR_ZERO_DIAG = -2,           /* a row has no stored or a zero diagonal */
   AMG_ERR_PATTERN_MISMATCH = -3,    /* value update with a different pattern */
-  AMG_ERR_BREAKDOWN = -4,           /* p^T A p <= 0, r^T z <= 0, NaN, or a non-SPD coarse matrix */
+  AMG_ERR_BREAKDOWN = -4,           /* p^T A p <= 0, r^T z <= 0, a zero BiCGSTAB scalar, NaN, or a
+                                       non-SPD (symmetric) / singular (nonsymmetric) coarse matrix */
   AMG_ERR_OOM = -5,                 /* device allocation failed */
   AMG_ERR_HIP = -6,                 /* a HIP runtime call failed */
   AMG_ERR_COARSE_TOO_LARGE = -7     /* coarsening stalled above the dense coarse-solve limit */
@@ -58,6 +63,7 @@ typedef enum {
 enum { AMG_PREC_FP64 = 0, AMG_PREC_FP32 = 1 };
 enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_L1 = 1 };
 enum { AMG_CACHE_COLD = 0, AMG_CACHE_HIT = 1, AMG_CACHE_REFRESH = 2 };
+enum { AMG_SOLVER_PCG = 0, AMG_SOLVER_BICGSTAB = 1 };
 
 /* Largest coarsest level that receives a dense factorization. */
 #define AMG_MAX_DENSE_COARSE 4096
@@ -72,20 +78,26 @@ typedef struct {
   int smoother;        /* AMG_SMOOTHER_JACOBI (default, weight omega/a_ii) or AMG_SMOOTHER_L1 */
   double omega;        /* Jacobi damping (default 2/3) */
   int nu_pre, nu_post; /* sweeps before/after the coarse correction (default 1, 1) */
-  int maxiter;         /* PCG iteration limit (default 1000) */
+  int maxiter;         /* Krylov iteration limit (default 1000) */
   int flexible;        /* -1 (default): flexible beta iff the cycle is not FP64; 0 standard; 1 flexible */
-  int symmetric;       /* 1 (default): A = A^T, the adjoint reuses A's hierarchy; 0 is rejected */
+  int symmetric;       /* 1 (default): A = A^T, the adjoint reuses A's hierarchy and the coarsest level
+                          gets a Cholesky factorization.  0: A may be nonsymmetric (needs
+                          solver = AMG_SOLVER_BICGSTAB): LU with partial pivoting on the coarsest level;
+                          the adjoint forms A^T and builds its hierarchy on first use */
   int check_every;     /* PCG iterations queued between convergence checks (default 0 = automatic) */
   int use_graphs;      /* 1 (default): replay HIP-graph captured iterations (on a library stream
                           joined to the caller's stream by events); 0: launch every kernel */
   int autotune;        /* 1: time candidate kernel shapes per matrix at setup and keep the fastest
                           (cached across runs in $AMG_TUNE_CACHE if set); 0 (default): row-length rule */
-  int precondition;    /* 1 (default): AMG V-cycle preconditioner; 0: plain CG (z = r; the setup keeps
-                          level 0 only; one right-hand side and one system only) */
+  int precondition;    /* 1 (default): AMG V-cycle preconditioner; 0: no preconditioner (plain CG or
+                          BiCGSTAB; the setup keeps level 0 only; one right-hand side and one system) */
+  int solver;          /* AMG_SOLVER_PCG (default) or AMG_SOLVER_BICGSTAB (right-preconditioned
+                          BiCGSTAB; one right-hand side and one system) */
 } amg_params;
 
 typedef struct {
-  int iters;           /* products A p performed (sum over restarts) */
+  int iters;           /* PCG: products A p performed; BiCGSTAB: full iterations (two products A y each;
+                          a stop at the half step counts its iteration); sums over restarts */
   double rel_resid;    /* true ||b - A x||_2 / ||b||_2 in FP64 (max over columns for k > 1) */
   int status;          /* amg_status of the solve */
   int cache_event;     /* AMG_CACHE_COLD / HIT / REFRESH of the amg_setup that produced the handle */
@@ -129,9 +141,13 @@ typedef enum {
   AMG_FIELD_R_BF16 = 13,   /* uint16[nnz_p] */
   AMG_FIELD_G_ROWPTR = 14, /* int32[n_l+1]      strength graph */
   AMG_FIELD_G_COL = 15,    /* int32[nnz_g] */
-  AMG_FIELD_COARSE_FACTOR = 16, /* float64[m*m] Cholesky factor of the coarsest A, row-major lower, m = padded size */
-  AMG_FIELD_COARSE_INV = 17,    /* float64[m*m] inverse of the coarsest A */
-  AMG_FIELD_DINV32 = 18    /* float32[n_l] smoother weights of the FP32 cycle */
+  AMG_FIELD_COARSE_FACTOR = 16, /* float64[m*m] factor of the coarsest A, row-major, m = padded size: Cholesky
+                                   (lower) or, nonsymmetric, packed LU (unit-lower multipliers below the
+                                   diagonal, U on and above) */
+  AMG_FIELD_COARSE_INV = 17,    /* float64[m*m] inverse of the coarsest A, transposed (entry (j, i) holds
+                                   (A^-1)_ij; equal to the inverse when A is symmetric) */
+  AMG_FIELD_DINV32 = 18,   /* float32[n_l] smoother weights of the FP32 cycle */
+  AMG_FIELD_COARSE_PIVOTS = 19  /* int32[m] nonsymmetric only: row exchanged with row k at LU step k */
 } amg_field;
 
 /* Fills *p with the defaults listed above. */
@@ -158,7 +174,16 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
  * from d_val (nnz entries) and keeps aggregates and patterns. */
 amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stream);
 
-/* PCG solve A X = B from X0 = 0 for nrhs >= 1 columns (row-major blocks,
+/* Solve A X = B from X0 = 0 with the handle's solver.
+ *
+ * AMG_SOLVER_BICGSTAB (nrhs = 1, one system): right-preconditioned BiCGSTAB
+ * (y = M^-1 p, v = A y, s = r - alpha v, z = M^-1 s, t = A z), shadow residual
+ * r^ = b, scalars formed on the device.  Stops when the recursive ||s||_2 or
+ * ||r||_2 <= tol ||b||_2, verifies the true residual and restarts from it
+ * (at most 5 times) like PCG.  A zero or NaN rho, <r^, v>, <t, t> or omega is
+ * AMG_ERR_BREAKDOWN.
+ *
+ * AMG_SOLVER_PCG: PCG for nrhs >= 1 columns (row-major blocks,
  * nrhs <= 64), preconditioned by one V-cycle per iteration.  With n_systems
  * S > 1, nrhs must equal S and column s is solved with system s.  Columns are
  * independent CG iterations run in one batched launch per step (not block
@@ -171,9 +196,12 @@ amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stre
 amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, int32_t nrhs, amg_info* info,
                      hipStream_t stream);
 
-/* Adjoint solve A^T lambda = g (Eq. (1)) with the same hierarchy, precision
- * and tolerance rule as amg_solve (A is symmetric, so A's own hierarchy is
- * the hierarchy of A^T and no transpose is formed). */
+/* Adjoint solve A^T lambda = g (Eq. (1)) with the same solver, precision and
+ * tolerance rule as amg_solve.  symmetric = 1: A's own hierarchy is the
+ * hierarchy of A^T and no transpose is formed.  symmetric = 0 (nrhs = 1): the
+ * first call forms A^T on the device (stable counting sort by column) and
+ * sets up its hierarchy with the same parameters; both are kept with the
+ * handle and refreshed from A's values after a value update. */
 amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, double tol, int32_t nrhs,
                              amg_info* info, hipStream_t stream);
 

@@ -25,12 +25,14 @@ AMG_PREC_FP64 = 0
 AMG_PREC_FP32 = 1
 AMG_SMOOTHER_JACOBI = 0
 AMG_SMOOTHER_L1 = 1
+AMG_SOLVER_PCG = 0
+AMG_SOLVER_BICGSTAB = 1
 AMG_MAX_LEVELS = 20
 
 FIELDS = {
     "agg": 0, "A_rp": 1, "A_ci": 2, "A_v": 3, "A_v32": 4, "dinv": 5, "P_rp": 6, "P_ci": 7, "P_v": 8,
     "P_bf16": 9, "R_rp": 10, "R_ci": 11, "R_v": 12, "R_bf16": 13, "G_rp": 14, "G_ci": 15,
-    "coarse_factor": 16, "coarse_inv": 17, "sw32": 18,
+    "coarse_factor": 16, "coarse_inv": 17, "sw32": 18, "coarse_pivots": 19,
 }
 
 EXPORTS = [
@@ -49,6 +51,7 @@ class amg_params(C.Structure):
         ("max_levels", C.c_int), ("smoother", C.c_int), ("omega", C.c_double), ("nu_pre", C.c_int),
         ("nu_post", C.c_int), ("maxiter", C.c_int), ("flexible", C.c_int), ("symmetric", C.c_int),
         ("check_every", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int), ("precondition", C.c_int),
+        ("solver", C.c_int),
     ]
 
 

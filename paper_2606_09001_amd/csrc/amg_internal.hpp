@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <functional>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -147,18 +148,20 @@ struct Level {
 struct Coarse {
   int n = 0;        // unknowns of the coarsest level
   int m = 0;        // padded to a multiple of 16
-  DBuf<double> L;   // m*m Cholesky factor (row-major lower)
-  DBuf<double> inv; // m*m inverse of the coarsest matrix (symmetric)
+  DBuf<double> L;   // m*m factor, row-major: Cholesky (lower) or packed LU (nonsymmetric)
+  DBuf<double> inv; // m*m inverse of the coarsest matrix, transposed ((j, i) holds (A^-1)_ij)
+  DBuf<int> piv;    // nonsymmetric: LU row exchanges
   DBuf<float> inv32;
   DBuf<double> work;
 };
 
-// Device control block of one PCG solve (single right-hand side).
+// Device control block of one PCG or BiCGSTAB solve (single right-hand side).
 struct Ctl {
   double bb, thresh;      // ||b||^2, tol^2 ||b||^2
   double rz, pq, rr;      // <r,z>, <p,Ap>, <r,r>
   double rzn, zq;         // new <r,z>, <z,q> (flexible)
   double alpha, beta;
+  double rho, omega;      // BiCGSTAB: <r^, r>, <t, s>/<t, t>
   double trr;             // true residual ||b - A x||^2
   int iters, maxiter;
   int done;               // nonzero: kernels of the current solve return at once
@@ -225,7 +228,9 @@ struct Graphs {
   hipStream_t gs = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t exec[2] = {nullptr, nullptr};   // pair of iterations, by direction-buffer parity
+  hipGraphExec_t bexec = nullptr;                 // one BiCGSTAB iteration
   const void* key_x = nullptr;
+  const void* key_bx = nullptr;
   int key_flex = -1;
   int key_w = 0;
   void reset();
@@ -242,8 +247,15 @@ struct Hierarchy {
   int64_t nnz = 0;
   std::vector<Level> lv;
   Coarse co;
-  // solve workspace (level 0, FP64)
+  // solve workspace (level 0, FP64); BiCGSTAB adds r^, v, y, s, t
   DBuf<double> r, z, p, z2, q;
+  DBuf<double> rh, bv, by, bs, bt2;
+  // nonsymmetric adjoint: A^T (pattern, entry map, values) and its hierarchy,
+  // built on first use and refreshed when A's values have changed since
+  std::unique_ptr<Hierarchy> adj;
+  DBuf<int> trp, tci, tperm;
+  DBuf<double> tval;
+  uint64_t val_version = 0, adj_version = 0;
   DBuf<double> partials;
   DBuf<Ctl> ctl;
   Ctl* h_ctl = nullptr;  // pinned host mirror
@@ -276,6 +288,10 @@ uint64_t pattern_hash(int n, int64_t nnz, const int* d_rp, const int* d_ci, int*
                       hipStream_t s);
 bool pattern_equal(const Hierarchy& H, const int* d_rp, const int* d_ci, int* d_flags, int* h_flags, hipStream_t s);
 bool values_equal(const Hierarchy& H, const double* d_val, int* d_flags, int* h_flags, hipStream_t s);
+// A^T of the level-0 matrix: pattern (trp, tci) and entry map tperm (entry t
+// of A^T is entry tperm[t] of A), then tval = A's values in that order.
+void transpose_pattern(Hierarchy& H, hipStream_t s);
+void transpose_values(Hierarchy& H, hipStream_t s);
 // coarse.hip
 void coarse_setup(Hierarchy& H, hipStream_t s);
 // solve.hip
@@ -287,6 +303,8 @@ void tune_record(const std::string& key, const Shape& sh);
 
 amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int nrhs,
                      amg_info* info, hipStream_t s);
+amg_status bicgstab_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol,
+                          amg_info* info, hipStream_t s);
 void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s);
 void pattern_grad(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, hipStream_t s);
 void graph_stream(Hierarchy& H);

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <list>
+#include <memory>
 #include <mutex>
 
 #include "amg_internal.hpp"
@@ -31,7 +32,12 @@ void Graphs::reset() {
       (void)hipGraphExecDestroy(e);
       e = nullptr;
     }
+  if (bexec) {
+    (void)hipGraphExecDestroy(bexec);
+    bexec = nullptr;
+  }
   key_x = nullptr;
+  key_bx = nullptr;
   key_flex = -1;
   key_w = 0;
 }
@@ -92,6 +98,8 @@ uint64_t params_hash(const amg_params& p) {
   h = mix(h, (uint64_t)p.nu_post);
   h = mix(h, (uint64_t)p.autotune);
   h = mix(h, (uint64_t)p.precondition);
+  h = mix(h, (uint64_t)p.symmetric);
+  h = mix(h, (uint64_t)p.solver);
   return h;
 }
 
@@ -99,7 +107,7 @@ bool same_setup_params(const amg_params& a, const amg_params& b) {
   return a.vcycle_prec == b.vcycle_prec && a.transfer_bf16 == b.transfer_bf16 && a.theta == b.theta &&
          a.max_coarse == b.max_coarse && a.max_levels == b.max_levels && a.smoother == b.smoother &&
          a.omega == b.omega && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post && a.autotune == b.autotune &&
-         a.precondition == b.precondition;
+         a.precondition == b.precondition && a.symmetric == b.symmetric && a.solver == b.solver;
 }
 
 amg_status check_params(const amg_params& p) {
@@ -108,8 +116,11 @@ amg_status check_params(const amg_params& p) {
   if (p.max_levels < 1 || p.max_levels > AMG_MAX_LEVELS || p.max_coarse < 1) return AMG_ERR_INVALID_ARG;
   if (p.nu_pre < 1 || p.nu_post < 1 || p.nu_pre > 8 || p.nu_post > 8) return AMG_ERR_INVALID_ARG;
   if (!(p.omega > 0.0) || !(p.theta >= 0.0) || p.maxiter < 0) return AMG_ERR_INVALID_ARG;
-  if (p.symmetric != 1) return AMG_ERR_INVALID_ARG;
+  if (p.symmetric != 0 && p.symmetric != 1) return AMG_ERR_INVALID_ARG;
   if (p.precondition != 0 && p.precondition != 1) return AMG_ERR_INVALID_ARG;
+  if (p.solver != AMG_SOLVER_PCG && p.solver != AMG_SOLVER_BICGSTAB) return AMG_ERR_INVALID_ARG;
+  // CG needs A = A^T; a nonsymmetric A is solved by BiCGSTAB
+  if (!p.symmetric && p.solver != AMG_SOLVER_BICGSTAB) return AMG_ERR_INVALID_ARG;
   return AMG_OK;
 }
 
@@ -146,6 +157,39 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Hierarchy of A^T for the adjoint of a nonsymmetric A (Eq. (1)): formed on
+// first use with A's parameters, kept with A's hierarchy (not in the cache)
+// and refreshed from A's values when they have changed since.
+Hierarchy& adjoint_hierarchy(Hierarchy& H, hipStream_t s) {
+  if (!H.adj) {
+    auto t0 = std::chrono::steady_clock::now();
+    transpose_pattern(H, s);
+    transpose_values(H, s);
+    std::unique_ptr<Hierarchy> A(new Hierarchy);
+    A->prm = H.prm;
+    A->S = 1;
+    A->n = H.n;
+    A->nnz = H.nnz;
+    A->lv.reserve(AMG_MAX_LEVELS + 1);
+    A->flags.alloc(16);
+    AMG_HIP(hipHostMalloc((void**)&A->h_flags, 64, hipHostMallocDefault));
+    build_hierarchy(*A, H.trp.p, H.tci.p, H.tval.p, s);
+    A->cache_event = AMG_CACHE_COLD;
+    A->setup_ms = ms_since(t0);
+    H.adj = std::move(A);
+    H.adj_version = H.val_version;
+  } else if (H.adj_version != H.val_version) {
+    auto t0 = std::chrono::steady_clock::now();
+    transpose_values(H, s);
+    H.adj->gr.reset();
+    refresh_hierarchy(*H.adj, H.tval.p, s);
+    H.adj->cache_event = AMG_CACHE_REFRESH;
+    H.adj->setup_ms = ms_since(t0);
+    H.adj_version = H.val_version;
+  }
+  return *H.adj;
+}
+
 }  // namespace
 }  // namespace amg
 
@@ -171,6 +215,7 @@ void amg_params_default(amg_params* p) {
   p->use_graphs = 1;
   p->autotune = 0;
   p->precondition = 1;
+  p->solver = AMG_SOLVER_PCG;
 }
 
 amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
@@ -188,6 +233,7 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
     // several systems share one pattern-only aggregation (theta = 0) and the
     // one-sweep cycle of the batched kernels
     if (n_systems > 1 && (prm.theta != 0.0 || prm.nu_pre != 1 || prm.nu_post != 1)) return AMG_ERR_INVALID_ARG;
+    if (n_systems > 1 && prm.solver != AMG_SOLVER_PCG) return AMG_ERR_INVALID_ARG;
     auto t0 = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lock(g_mu);
     ensure_global_flags();
@@ -206,6 +252,7 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
       } else {
         H->gr.reset();
         refresh_hierarchy(*H, d_val, stream);
+        ++H->val_version;
         H->cache_event = AMG_CACHE_REFRESH;
         H->setup_ms = ms_since(t0);
       }
@@ -250,6 +297,7 @@ amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stre
     std::lock_guard<std::mutex> lock(g_mu);
     h->H->gr.reset();
     refresh_hierarchy(*h->H, d_val, stream);
+    ++h->H->val_version;
     h->H->cache_event = AMG_CACHE_REFRESH;
     h->H->setup_ms = ms_since(t0);
     return AMG_OK;
@@ -262,6 +310,10 @@ amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, i
     if (!h || !d_b || !d_x || nrhs < 1 || nrhs > kMaxWidth || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
     Hierarchy& H = *h->H;
     if (H.S > 1 && nrhs != H.S) return AMG_ERR_INVALID_ARG;
+    if (H.prm.solver == AMG_SOLVER_BICGSTAB) {
+      if (nrhs != 1) return AMG_ERR_INVALID_ARG;
+      return bicgstab_solve(H, h->opts, d_b, d_x, tol, info, stream);
+    }
     if (nrhs > 1 || H.S > 1) return pcg_solve_wide(H, h->opts, d_b, d_x, tol, nrhs, info, stream);
     return pcg_solve(H, h->opts, d_b, d_x, tol, nrhs, info, stream);
   });
@@ -269,9 +321,21 @@ amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, i
 
 amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, double tol, int32_t nrhs,
                              amg_info* info, hipStream_t stream) {
-  // A is symmetric (enforced at setup), so A^T lambda = g is solved with A's
-  // own hierarchy and the forward solver settings (Eq. (1)).
-  return amg_solve(h, d_g, d_lambda, tol, nrhs, info, stream);
+  // Symmetric A: A^T lambda = g is solved with A's own hierarchy and the
+  // forward solver settings (Eq. (1)).
+  if (!h || h->H->prm.symmetric) return amg_solve(h, d_g, d_lambda, tol, nrhs, info, stream);
+  return guarded([&]() -> amg_status {
+    if (!d_g || !d_lambda || nrhs != 1 || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
+    Hierarchy& H = *h->H;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Hierarchy& T = adjoint_hierarchy(H, stream);
+    amg_status st = bicgstab_solve(T, h->opts, d_g, d_lambda, tol, info, stream);
+    if (info) {
+      info->cache_event = H.cache_event;
+      info->setup_ms = H.setup_ms;
+    }
+    return st;
+  });
 }
 
 amg_status amg_pattern_grad(amg_handle h, const double* d_lambda, const double* d_x, double* d_grad_val,
@@ -370,6 +434,7 @@ static amg_status field_ptr(const Hierarchy& H, int level, int field, const void
     case AMG_FIELD_G_COL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.gci.p; *count = L.gnnz; *eb = 4; break;
     case AMG_FIELD_COARSE_FACTOR: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.L.p; *count = (int64_t)H.co.m * H.co.m * S; *eb = 8; break;
     case AMG_FIELD_COARSE_INV: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.inv.p; *count = (int64_t)H.co.m * H.co.m * S; *eb = 8; break;
+    case AMG_FIELD_COARSE_PIVOTS: if (!coarsest || H.prm.symmetric) return AMG_ERR_INVALID_ARG; *p = H.co.piv.p; *count = (int64_t)H.co.m * S; *eb = 4; break;
     default: return AMG_ERR_INVALID_ARG;
   }
   return AMG_OK;

@@ -2,7 +2,12 @@
 // coarsest Galerkin matrix (right-looking, 16-column panels; the rank-16
 // trailing updates and the inverse product run on the FP64 matrix cores,
 // v_mfma_f64_16x16x4f64), followed by the explicit inverse so that the
-// per-cycle coarse solve is one dense matrix-vector product.
+// per-cycle coarse solve is one dense matrix-vector product.  A nonsymmetric
+// hierarchy factors the coarsest matrix by LU with partial pivoting instead
+// (Gaussian elimination with row interchanges, one column per step, every
+// entry updated by one rounded product and one rounded difference per step,
+// in the same order as the sequential definition) and stores the transposed
+// inverse, which the coarse-solve kernel reads the same way.
 #include <algorithm>
 
 #include "amg_internal.hpp"
@@ -149,6 +154,105 @@ __global__ void k_gram(int m, const double* __restrict__ X, double* __restrict__
   for (int e = 0; e < 4; ++e) G[(int64_t)(I * 16 + 4 * e + q) * m + J * 16 + r] = acc[e];
 }
 
+constexpr int kLuBlock = 1024;  // one workgroup, sixteen wavefronts
+
+// In-place LU with partial pivoting of the m x m row-major W.  Step k: the
+// pivot is the first row i >= k of largest |w_ik| (lowest index on ties), the
+// two rows are exchanged over the full width, the multipliers w_ik / w_kk go
+// below the diagonal and every w_ij (i, j > k) becomes w_ij - w_ik * w_kj.
+// A zero (or NaN) pivot column sets flags bit 0.  Padding rows/columns are
+// the identity and are never chosen for a column of the matrix.
+__global__ void __launch_bounds__(kLuBlock) k_lu(int m, double* __restrict__ W, int* __restrict__ piv,
+                                                 int* flags) {
+  const int tid = threadIdx.x;
+  constexpr int NW = kLuBlock / 64;
+  __shared__ double s_best[NW];
+  __shared__ int s_row[NW];
+  __shared__ int s_p;
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    // pivot search: thread-local first maximum, then (value, lowest row)
+    double best = -1.0;
+    int br = m;
+    bool nan = false;
+    for (int i = k + tid; i < m; i += kLuBlock) {
+      const double a = fabs(W[(int64_t)i * m + k]);
+      nan |= !(a == a);
+      if (a > best) { best = a; br = i; }
+    }
+    if (nan) s_bad = 1;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int orow = __shfl_xor(br, o, 64);
+      if (ob > best || (ob == best && orow < br)) { best = ob; br = orow; }
+    }
+    if ((tid & 63) == 0) { s_best[tid >> 6] = best; s_row[tid >> 6] = br; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = s_best[0];
+      int r = s_row[0];
+      for (int w = 1; w < NW; ++w)
+        if (s_best[w] > b || (s_best[w] == b && s_row[w] < r)) { b = s_best[w]; r = s_row[w]; }
+      if (!(b > 0.0)) { s_bad = 1; r = k; }
+      s_p = r;
+      piv[k] = r;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != k)
+      for (int j = tid; j < m; j += kLuBlock) {
+        const double t = W[(int64_t)k * m + j];
+        W[(int64_t)k * m + j] = W[(int64_t)p * m + j];
+        W[(int64_t)p * m + j] = t;
+      }
+    __syncthreads();
+    const double ukk = W[(int64_t)k * m + k];
+    const bool ok = ukk != 0.0;
+    for (int i = k + 1 + tid; i < m; i += kLuBlock) W[(int64_t)i * m + k] = ok ? W[(int64_t)i * m + k] / ukk : 0.0;
+    __syncthreads();
+    const int r = m - (k + 1);
+    for (int64_t e = tid; e < (int64_t)r * r; e += kLuBlock) {
+      const int i = k + 1 + (int)(e / r), j = k + 1 + (int)(e % r);
+      const double prod = W[(int64_t)i * m + k] * W[(int64_t)k * m + j];
+      W[(int64_t)i * m + j] = W[(int64_t)i * m + j] - prod;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && s_bad) atomicOr(flags, 1);
+}
+
+// Row j of invT = column j of A^-1: y = P e_j (the recorded exchanges in
+// order), unit-lower forward substitution, then upper back substitution.
+// One thread per column, its row of invT as the work vector.
+__global__ void k_lu_inverse_t(int m, const double* __restrict__ LU, const int* __restrict__ piv,
+                               double* __restrict__ invT) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double* y = invT + (int64_t)j * m;
+  for (int i = 0; i < m; ++i) y[i] = i == j ? 1.0 : 0.0;
+  for (int k = 0; k < m; ++k) {
+    const int p = piv[k];
+    if (p != k) {
+      const double t = y[k];
+      y[k] = y[p];
+      y[p] = t;
+    }
+  }
+  for (int i = 1; i < m; ++i) {
+    double s = y[i];
+    for (int q = 0; q < i; ++q) s -= LU[(int64_t)i * m + q] * y[q];
+    y[i] = s;
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int q = i + 1; q < m; ++q) s -= LU[(int64_t)i * m + q] * y[q];
+    y[i] = s / LU[(int64_t)i * m + i];
+  }
+}
+
 __global__ void k_inv_to_f32(int64_t mm, const double* __restrict__ a, float* __restrict__ b) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < mm) b[t] = (float)a[t];
@@ -168,6 +272,8 @@ void coarse_setup(Hierarchy& H, hipStream_t s) {
   C.L.alloc(mm * S);
   C.inv.alloc(mm * S);
   C.work.alloc(mm);
+  const bool lu = !H.prm.symmetric;
+  if (lu) C.piv.alloc((int64_t)m * S);
   const int grid = (int)std::min<int64_t>((mm + kBlock - 1) / kBlock, 4096);
   const int T = m / 16;
   AMG_HIP(hipMemsetAsync(H.flags.p, 0, sizeof(int), s));
@@ -178,6 +284,12 @@ void coarse_setup(Hierarchy& H, hipStream_t s) {
     hipLaunchKernelGGL(k_densify, dim3(grid), dim3(kBlock), 0, s, C.n, m, Ls);
     hipLaunchKernelGGL(k_scatter, dim3((C.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, C.n, m, L.rp.p, L.ci.p,
                        L.v.p + sy, S, Ls);
+    if (lu) {
+      int* ps = C.piv.p + (int64_t)sy * m;
+      hipLaunchKernelGGL(k_lu, dim3(1), dim3(kLuBlock), 0, s, m, Ls, ps, H.flags.p);
+      hipLaunchKernelGGL(k_lu_inverse_t, dim3((m + 63) / 64), dim3(64), 0, s, m, Ls, ps, Is);
+      continue;
+    }
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kCoBlock), 0, s, m, Ls, H.flags.p);
     hipLaunchKernelGGL(k_tri_inverse, dim3((m + 63) / 64), dim3(64), 0, s, m, Ls, Is);
     hipLaunchKernelGGL(k_transpose, dim3((int)((mm + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, m, Is, C.work.p);
@@ -186,7 +298,8 @@ void coarse_setup(Hierarchy& H, hipStream_t s) {
   AMG_HIP(hipGetLastError());
   AMG_HIP(hipMemcpyAsync(H.h_flags, H.flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
-  if (H.h_flags[0]) throw Error(AMG_ERR_BREAKDOWN, "coarsest matrix is not positive definite");
+  if (H.h_flags[0])
+    throw Error(AMG_ERR_BREAKDOWN, lu ? "coarsest matrix is singular" : "coarsest matrix is not positive definite");
   if (H.fp32()) {
     C.inv32.alloc(mm * S);
     hipLaunchKernelGGL(k_inv_to_f32, dim3((int)((mm * S + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, mm * S,

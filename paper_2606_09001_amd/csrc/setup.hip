@@ -1260,6 +1260,47 @@ void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const doubl
   AMG_HIP(hipStreamSynchronize(s));
 }
 
+// A^T of the level-0 matrix by a stable radix sort of the entries by column:
+// entry t of A^T is entry tperm[t] of A, and within a row of A^T the source
+// rows ascend (the stable sort keeps A's row order), so the result is a valid
+// sorted CSR matrix with every diagonal stored.
+void transpose_pattern(Hierarchy& H, hipStream_t s) {
+  const Level& L = H.lv[0];
+  const int n = L.n;
+  const int64_t nnz = L.nnz;
+  const dim3 b(kBlock);
+  DBuf<int> rowid, iota, keys_out, cnt;
+  rowid.alloc(nnz);
+  iota.alloc(nnz);
+  keys_out.alloc(nnz);
+  H.tperm.alloc(nnz);
+  hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n)), b, 0, s, n, L.rp.p, rowid.p);
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), b, 0, s, nnz, iota.p);
+  int end_bit = 1;
+  while ((1ll << end_bit) < (long long)n) ++end_bit;
+  cub_call([&](void* t, size_t& bb) {
+    return hipcub::DeviceRadixSort::SortPairs(t, bb, L.ci.p, keys_out.p, iota.p, H.tperm.p, (int)nnz, 0, end_bit, s);
+  }, s);
+  cnt.alloc(n + 1);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (n + 1), s));
+  hipLaunchKernelGGL(k_col_count, dim3(grid_for(nnz)), b, 0, s, nnz, L.ci.p, cnt.p);
+  H.trp.alloc(n + 1);
+  exclusive_scan(cnt.p, H.trp.p, n + 1, s);
+  H.tci.alloc(nnz);
+  H.tval.alloc(nnz);
+  hipLaunchKernelGGL(k_r_fill, dim3(grid_for(nnz)), b, 0, s, nnz, H.tperm.p, rowid.p, L.v.p, 1, H.tci.p, H.tval.p);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+// Values of A^T in its entry order from A's current values.
+void transpose_values(Hierarchy& H, hipStream_t s) {
+  const Level& L = H.lv[0];
+  hipLaunchKernelGGL(k_r_fill, dim3(grid_for(L.nnz)), dim3(kBlock), 0, s, L.nnz, H.tperm.p, (const int*)nullptr,
+                     L.v.p, 1, (int*)nullptr, H.tval.p);
+  AMG_HIP(hipGetLastError());
+}
+
 void refresh_hierarchy(Hierarchy& H, const double* d_val, hipStream_t s) {
   Level& L0 = H.lv[0];
   AMG_HIP(hipMemcpyAsync(L0.v.p, d_val, L0.v.bytes(), hipMemcpyDeviceToDevice, s));

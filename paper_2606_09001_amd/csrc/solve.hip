@@ -116,6 +116,29 @@ struct OpTrueResid {
   }
 };
 
+// BiCGSTAB product with its reductions: out = A in, <w, out> and, with
+// NRED = 2, <out, out> (v = A y with <r^, v>; t = A z with <s, t>, <t, t>).
+template <int N>
+struct OpSpmvDots {
+  using PT = double;
+  static constexpr int NRED = N;
+  const double* v;
+  const double* in;
+  double* out;
+  const double* w;
+  struct Row {
+    double w;
+  };
+  __device__ PT prod_v(double a, int j) const { return a * in[j]; }
+  __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
+  __device__ Row row_in(int row) const { return {w[row]}; }
+  __device__ void epi(int row, PT s, const Row& a, double* d) const {
+    out[row] = s;
+    d[0] += a.w * s;
+    if constexpr (N == 2) d[1] += s * s;
+  }
+};
+
 // Pre-smoothing from zero fused with the residual:
 //   x_i = sw_i b_i ;  r_i = b_i - sum_j a_ij (sw_j b_j).
 template <class T, class BT>
@@ -609,6 +632,114 @@ __global__ void __launch_bounds__(kBlock) k_pattern_grad(int n, const int* __res
   for (int k = rp[row] + lane; k < rp[row + 1]; k += G) g[k] = -(li * x[ci[k]]);
 }
 
+// ------------------------------------------------------- BiCGSTAB vectors
+
+// r = b, r^ = b, x = 0, partial <b, b>.
+__global__ void __launch_bounds__(kBlock) k_bi_init(int n, const double* __restrict__ b, double* __restrict__ r,
+                                                    double* __restrict__ rh, double* __restrict__ x,
+                                                    double* __restrict__ partials) {
+  const int base = vec_base();
+  double d[1] = {0.0};
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) {
+      const double bi = b[i];
+      r[i] = bi;
+      rh[i] = bi;
+      x[i] = 0.0;
+      d[0] += bi * bi;
+    }
+  }
+  publish_partials<1>(d, partials);
+}
+
+// p = r on the first iteration of a (re)start, else p = r + beta (p - omega v).
+__global__ void __launch_bounds__(kBlock) k_bi_dir(int n, const double* __restrict__ r,
+                                                   const double* __restrict__ v, double* __restrict__ p,
+                                                   const Ctl* __restrict__ ctl, int first) {
+  if (ctl->done) return;
+  const double beta = ctl->beta, omega = ctl->omega;
+  const int base = vec_base();
+  double rv[kVecPer], vv[kVecPer], pv[kVecPer];
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = min(base + (int)threadIdx.x + u * kBlock, n - 1);
+    rv[u] = r[i];
+    vv[u] = v[i];
+    pv[u] = p[i];
+  }
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) p[i] = first ? rv[u] : rv[u] + beta * (pv[u] - omega * vv[u]);
+  }
+}
+
+// x += alpha y ; s = r - alpha v ; partial <s, s>.
+__global__ void __launch_bounds__(kBlock) k_bi_half(int n, double* __restrict__ x, const double* __restrict__ y,
+                                                    const double* __restrict__ r, const double* __restrict__ v,
+                                                    double* __restrict__ sv, const Ctl* __restrict__ ctl,
+                                                    double* __restrict__ partials) {
+  if (ctl->done) return;
+  const double alpha = ctl->alpha;
+  const int base = vec_base();
+  double xv[kVecPer], yv[kVecPer], rv[kVecPer], vv[kVecPer];
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = min(base + (int)threadIdx.x + u * kBlock, n - 1);
+    xv[u] = x[i];
+    yv[u] = y[i];
+    rv[u] = r[i];
+    vv[u] = v[i];
+  }
+  double d[1] = {0.0};
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) {
+      x[i] = xv[u] + alpha * yv[u];
+      const double si = rv[u] - alpha * vv[u];
+      sv[i] = si;
+      d[0] += si * si;
+    }
+  }
+  publish_partials<1>(d, partials);
+}
+
+// x += omega z ; r = s - omega t ; partials <r, r>, <r^, r>.
+__global__ void __launch_bounds__(kBlock) k_bi_full(int n, double* __restrict__ x, const double* __restrict__ z,
+                                                    const double* __restrict__ sv, const double* __restrict__ t,
+                                                    const double* __restrict__ rh, double* __restrict__ r,
+                                                    const Ctl* __restrict__ ctl, double* __restrict__ partials) {
+  if (ctl->done) return;
+  const double omega = ctl->omega;
+  const int base = vec_base();
+  double xv[kVecPer], zv[kVecPer], sl[kVecPer], tv[kVecPer], hv[kVecPer];
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = min(base + (int)threadIdx.x + u * kBlock, n - 1);
+    xv[u] = x[i];
+    zv[u] = z[i];
+    sl[u] = sv[i];
+    tv[u] = t[i];
+    hv[u] = rh[i];
+  }
+  double d[2] = {0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < kVecPer; ++u) {
+    const int i = base + threadIdx.x + u * kBlock;
+    if (i < n) {
+      x[i] = xv[u] + omega * zv[u];
+      const double ri = sl[u] - omega * tv[u];
+      r[i] = ri;
+      d[0] += ri * ri;
+      d[1] += hv[u] * ri;
+    }
+  }
+  publish_partials<2>(d, partials);
+}
+
 // ------------------------------------------------------- finalize kernels
 
 // Fixed-order fold of gridDim-sized partial arrays by one workgroup; the
@@ -742,6 +873,122 @@ __global__ void __launch_bounds__(kFinBlock) k_fin_trr(Ctl* ctl, const double* _
   double t[1];
   fold_partials<1>(partials, np, t);
   if (threadIdx.x == 0) ctl->trr = t[0];
+}
+
+// BiCGSTAB scalars.  rho = <r^, r> (= ||b||^2 at the start, r^ = r = b).
+__global__ void __launch_bounds__(kFinBlock) k_bfin_init(Ctl* ctl, const double* __restrict__ partials, int np,
+                                                         double tol, int maxiter) {
+  double t[1];
+  fold_partials<1>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double bb = t[0];
+  ctl->bb = bb;
+  ctl->thresh = (tol * tol) * bb;
+  ctl->iters = 0;
+  ctl->maxiter = maxiter;
+  ctl->flexible = 0;
+  ctl->state = 0;
+  ctl->done = 0;
+  ctl->trr = 0.0;
+  ctl->rr = bb;
+  ctl->rho = bb;
+  ctl->alpha = 1.0;
+  ctl->omega = 1.0;
+  ctl->beta = 0.0;
+  if (bb == 0.0) {
+    ctl->state = 3;
+    ctl->done = 1;
+  } else if (!(bb == bb)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  } else if (maxiter <= 0) {
+    ctl->state = 2;
+    ctl->done = 1;
+  }
+}
+
+// alpha = rho / <r^, v>
+__global__ void __launch_bounds__(kFinBlock) k_bfin_alpha(Ctl* ctl, const double* __restrict__ partials, int np) {
+  if (ctl->done) return;
+  double t[1];
+  fold_partials<1>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double rv = t[0];
+  if (!(rv != 0.0) || !(rv == rv)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  } else {
+    ctl->alpha = ctl->rho / rv;
+  }
+}
+
+// ||s||^2: the iteration is counted here; a small s ends the solve with
+// x = x + alpha y (already written).
+__global__ void __launch_bounds__(kFinBlock) k_bfin_half(Ctl* ctl, const double* __restrict__ partials, int np) {
+  if (ctl->done) return;
+  double t[1];
+  fold_partials<1>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double ss = t[0];
+  ctl->rr = ss;
+  ctl->iters += 1;
+  if (ss <= ctl->thresh) {
+    ctl->state = 1;
+    ctl->done = 1;
+  } else if (!(ss == ss)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  }
+}
+
+// omega = <t, s> / <t, t>
+__global__ void __launch_bounds__(kFinBlock) k_bfin_omega(Ctl* ctl, const double* __restrict__ partials, int np) {
+  if (ctl->done) return;
+  double t[2];
+  fold_partials<2>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double ts = t[0], tt = t[1];
+  const double om = ts / tt;
+  if (!(tt > 0.0) || !(om != 0.0) || !(om == om)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  } else {
+    ctl->omega = om;
+  }
+}
+
+// ||r||^2 and the next rho = <r^, r>, beta = (rho / rho_old) (alpha / omega).
+__global__ void __launch_bounds__(kFinBlock) k_bfin_full(Ctl* ctl, const double* __restrict__ partials, int np) {
+  if (ctl->done) return;
+  double t[2];
+  fold_partials<2>(partials, np, t);
+  if (threadIdx.x != 0) return;
+  const double rr = t[0], rho = t[1];
+  ctl->rr = rr;
+  if (rr <= ctl->thresh) {
+    ctl->state = 1;
+    ctl->done = 1;
+  } else if (!(rr == rr)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  } else if (ctl->iters >= ctl->maxiter) {
+    ctl->state = 2;
+    ctl->done = 1;
+  } else if (!(rho != 0.0) || !(rho == rho)) {
+    ctl->state = -1;
+    ctl->done = 1;
+  } else {
+    ctl->beta = (rho / ctl->rho) * (ctl->alpha / ctl->omega);
+    ctl->rho = rho;
+  }
+}
+
+// Restart from the true residual r = b - A x (||r||^2 in trr): r^ = r is
+// copied separately; rho = ||r||^2.
+__global__ void k_bi_restart(Ctl* ctl) {
+  ctl->done = 0;
+  ctl->state = 0;
+  ctl->rho = ctl->trr;
 }
 
 __global__ void k_ctl_restart(Ctl* ctl) {
@@ -1563,6 +1810,160 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
     if (state == 1 && restarts < 5 && c.iters < c.maxiter) {
       ++restarts;
       hipLaunchKernelGGL(k_ctl_restart, dim3(1), dim3(1), 0, s, ctl);
+      continue;
+    }
+    st = AMG_NOT_CONVERGED;
+    break;
+  }
+  if (graphs) {
+    AMG_HIP(hipEventRecord(H.gr.ev_out, s));
+    AMG_HIP(hipStreamWaitEvent(caller, H.gr.ev_out, 0));
+  }
+  const Ctl& c = *H.h_ctl;
+  if (info) {
+    info->iters = c.iters;
+    info->status = st;
+    info->restarts = restarts;
+    info->rel_resid = c.state == 3 ? 0.0 : (c.bb > 0 ? std::sqrt(c.trr / c.bb) : 0.0);
+    if (st == AMG_ERR_BREAKDOWN) info->rel_resid = NAN;
+    info->cache_event = H.cache_event;
+    info->setup_ms = H.setup_ms;
+    info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+// Right-preconditioned BiCGSTAB (van der Vorst, 1992), the paper's default
+// Krylov method (Section 2.2), from x0 = 0 with shadow residual r^ = b.
+// One iteration, every scalar formed on the device:
+//   p = r + beta (p - omega v)        k_bi_dir   (p = r after a (re)start)
+//   y = M^-1 p                        V-cycle
+//   v = A y, <r^, v>                  sweep      -> alpha = rho / <r^, v>
+//   x += alpha y, s = r - alpha v     k_bi_half  -> ||s|| test, iteration count
+//   z = M^-1 s                        V-cycle
+//   t = A z, <s, t>, <t, t>           sweep      -> omega
+//   x += omega z, r = s - omega t     k_bi_full  -> ||r|| test, rho, beta
+// Stopping, verification and restarts follow pcg_solve.
+amg_status bicgstab_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol,
+                          amg_info* info, hipStream_t caller) {
+  auto t0 = std::chrono::steady_clock::now();
+  Level& L0 = H.lv[0];
+  const int n = H.n;
+  const bool graphs = o.use_graphs && H.inst.kernel < 0;
+  if (!H.rh.p) {
+    H.rh.alloc(n);
+    H.bv.alloc(n);
+    H.by.alloc(n);
+    H.bs.alloc(n);
+    H.bt2.alloc(n);
+    AMG_HIP(hipMemsetAsync(H.bv.p, 0, H.bv.bytes(), caller));
+  }
+  hipStream_t s = caller;
+  if (graphs) {
+    graph_stream(H);
+    AMG_HIP(hipEventRecord(H.gr.ev_in, caller));
+    AMG_HIP(hipStreamWaitEvent(H.gr.gs, H.gr.ev_in, 0));
+    s = H.gr.gs;
+    if (H.gr.key_bx != d_x && H.gr.bexec) {
+      (void)hipGraphExecDestroy(H.gr.bexec);
+      H.gr.bexec = nullptr;
+    }
+    H.gr.key_bx = d_x;
+  }
+  Ctl* ctl = H.ctl.p;
+  double* part = H.partials.p;
+  double* r = H.r.p;
+  double* p = H.p.p;
+  double* z = H.z.p;
+  double* rh = H.rh.p;
+  double* v = H.bv.p;
+  double* y = H.by.p;
+  double* sv = H.bs.p;
+  double* t = H.bt2.p;
+  const int gv = vec_grid(n);
+  hipLaunchKernelGGL(k_bi_init, dim3(gv), dim3(kBlock), 0, s, n, d_b, r, rh, d_x, part);
+  hipLaunchKernelGGL(k_bfin_init, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv, tol, o.maxiter);
+  AMG_HIP(hipGetLastError());
+  auto iteration = [&](int first, hipStream_t st) {
+    hipLaunchKernelGGL(k_bi_dir, dim3(gv), dim3(kBlock), 0, st, n, r, v, p, ctl, first);
+    vcycle(H, CycleArgs{p, y, nullptr, ctl, part, 0, 0, 0}, st);
+    int np;
+    {
+      InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
+      np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpSpmvDots<1>{L0.av(), y, v, rh}, ctl, part, st);
+    }
+    hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(kFinBlock), 0, st, ctl, part, np);
+    hipLaunchKernelGGL(k_bi_half, dim3(gv), dim3(kBlock), 0, st, n, d_x, y, r, v, sv, ctl, part);
+    hipLaunchKernelGGL(k_bfin_half, dim3(1), dim3(kFinBlock), 0, st, ctl, part, gv);
+    vcycle(H, CycleArgs{sv, z, nullptr, ctl, part, 0, 0, 0}, st);
+    {
+      InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
+      np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpSpmvDots<2>{L0.av(), z, t, sv}, ctl, part, st);
+    }
+    hipLaunchKernelGGL(k_bfin_omega, dim3(1), dim3(kFinBlock), 0, st, ctl, part, np);
+    hipLaunchKernelGGL(k_bi_full, dim3(gv), dim3(kBlock), 0, st, n, d_x, z, sv, t, rh, r, ctl, part);
+    hipLaunchKernelGGL(k_bfin_full, dim3(1), dim3(kFinBlock), 0, st, ctl, part, gv);
+  };
+  int restarts = 0;
+  amg_status st = AMG_OK;
+  for (;;) {
+    int first = 1;
+    int chunk = o.check_every > 0 ? o.check_every : 2;
+    int it_prev = -1;
+    double rr_prev = 0.0;
+    for (;;) {
+      int left = chunk;
+      if (first) {
+        iteration(1, s);
+        first = 0;
+        --left;
+      }
+      if (graphs && left > 0) {
+        if (!H.gr.bexec) capture_graph(s, H.gr.bexec, [&] { iteration(0, s); });
+        for (; left > 0; --left) AMG_HIP(hipGraphLaunch(H.gr.bexec, s));
+      }
+      for (; left > 0; --left) iteration(0, s);
+      AMG_HIP(hipGetLastError());
+      read_ctl(H, s);
+      if (H.h_ctl->done) break;
+      if (o.check_every <= 0) {
+        // chunk sized from the observed decay of the residual norm, as in PCG
+        const Ctl& c = *H.h_ctl;
+        if (it_prev < 0) {
+          it_prev = 0;
+          rr_prev = c.bb;
+        }
+        int next = 2;
+        if (c.thresh <= 0.0) {
+          next = 16;
+        } else if (c.iters > it_prev && rr_prev > 0.0 && c.rr > 0.0) {
+          const double rate = std::log(c.rr / rr_prev) / (double)(c.iters - it_prev);
+          if (rate < -1e-3) next = (int)std::min(32.0, std::ceil(std::log(c.thresh / c.rr) / rate));
+        }
+        it_prev = c.iters;
+        rr_prev = c.rr;
+        next = std::min(next, std::max(1, c.maxiter - c.iters));
+        chunk = std::max(1, std::min(next, 16));
+      }
+    }
+    const int state = H.h_ctl->state;
+    if (state == 3) break;  // b = 0
+    if (state < 0) {
+      st = AMG_ERR_BREAKDOWN;
+      break;
+    }
+    const int np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpTrueResid{L0.av(), d_x, d_b, r}, nullptr, part, s);
+    hipLaunchKernelGGL(k_fin_trr, dim3(1), dim3(kFinBlock), 0, s, ctl, part, np);
+    read_ctl(H, s);
+    const Ctl& c = *H.h_ctl;
+    if (c.trr <= c.thresh) {
+      st = AMG_OK;
+      break;
+    }
+    if (state == 1 && restarts < 5 && c.iters < c.maxiter) {
+      ++restarts;
+      hipLaunchKernelGGL(k_bi_restart, dim3(1), dim3(1), 0, s, ctl);
+      hipLaunchKernelGGL(k_copy_z, dim3(gv), dim3(kBlock), 0, s, n, r, rh, (const Ctl*)nullptr);
       continue;
     }
     st = AMG_NOT_CONVERGED;

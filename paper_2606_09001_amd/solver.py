@@ -21,13 +21,13 @@ __all__ = ["AmgHierarchy", "solve", "amg_solve", "AmgSolve", "make_params", "fin
 
 _PARAM_KEYS = ("vcycle_prec", "transfer_bf16", "theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre",
                "nu_post", "maxiter", "flexible", "symmetric", "check_every", "use_graphs", "autotune",
-               "precondition")
+               "precondition", "solver")
 
 
 def make_params(**kw) -> _lib.amg_params:
     """amg_params with the library defaults, overridden by keyword (Section 2.2:
-    users set only the parameters they change).  Accepts 'fp64'/'fp32' for
-    vcycle_prec and 'jacobi'/'l1' for smoother."""
+    users set only the parameters they change).  Accepts 'pcg'/'bicgstab' for
+    solver, 'fp64'/'fp32' for vcycle_prec and 'jacobi'/'l1' for smoother."""
     L = _lib.load()
     p = _lib.amg_params()
     L.amg_params_default(C.byref(p))
@@ -38,6 +38,11 @@ def make_params(**kw) -> _lib.amg_params:
             v = {"fp64": _lib.AMG_PREC_FP64, "fp32": _lib.AMG_PREC_FP32, "mixed": _lib.AMG_PREC_FP32}[v]
         if k == "smoother" and isinstance(v, str):
             v = {"jacobi": _lib.AMG_SMOOTHER_JACOBI, "l1": _lib.AMG_SMOOTHER_L1}[v]
+        if k == "solver" and isinstance(v, str):
+            v = {"pcg": _lib.AMG_SOLVER_PCG, "cg": _lib.AMG_SOLVER_PCG,
+                 "bicgstab": _lib.AMG_SOLVER_BICGSTAB, "pbicgstab": _lib.AMG_SOLVER_BICGSTAB}[v.lower()]
+        if k == "symmetric":
+            v = int(bool(v))
         setattr(p, k, v)
     return p
 
@@ -225,7 +230,8 @@ class AmgSolve(torch.autograd.Function):
     """x = A^-1 b with A = CSR(row_ptr, col, val), differentiable in val and b.
 
     Backward (Eq. (1)-(2)): A^T lambda = dL/dx on the cached hierarchy
-    (A symmetric: A's own hierarchy, no transpose formed); grad_val =
+    (A symmetric: A's own hierarchy, no transpose formed; symmetric=False:
+    the hierarchy of the explicit transpose, formed once); grad_val =
     -(lambda_i x_j) on the stored entries; grad_b = lambda.
     """
 

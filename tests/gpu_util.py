@@ -3,7 +3,7 @@ hierarchy with an oracle hierarchy built from the same seeded inputs)."""
 import numpy as np
 import torch
 
-ORACLE_KEYS = ("theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre", "nu_post")
+ORACLE_KEYS = ("theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre", "nu_post", "symmetric")
 
 
 def dev(a):

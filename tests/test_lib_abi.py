@@ -39,6 +39,7 @@ def test_params_default_and_status_strings():
     assert p.vcycle_prec == _lib.AMG_PREC_FP64 and p.max_coarse == 256 and p.max_levels == 20
     assert p.omega == pytest.approx(2.0 / 3.0) and p.nu_pre == 1 and p.nu_post == 1
     assert p.theta == 0.0 and p.symmetric == 1 and p.flexible == -1 and p.precondition == 1
+    assert p.solver == _lib.AMG_SOLVER_PCG
     for st, name in [(0, "AMG_OK"), (1, "AMG_NOT_CONVERGED"), (-1, "AMG_ERR_INVALID_ARG"),
                      (-4, "AMG_ERR_BREAKDOWN"), (-7, "AMG_ERR_COARSE_TOO_LARGE")]:
         assert _lib.status_string(st) == name
@@ -60,8 +61,16 @@ def test_setup_rejects_bad_arguments_before_touching_a_device():
     p.nu_pre = 2    # and V(1,1)
     assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 2, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
     p.nu_pre = 1
-    p.symmetric = 0
+    p.symmetric = 0  # CG needs A = A^T: a nonsymmetric A takes BiCGSTAB
     assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    p.symmetric = 2
+    p.solver = _lib.AMG_SOLVER_BICGSTAB
+    assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    p.symmetric = 0  # BiCGSTAB: one system only
+    assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 2, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    p.solver = 2
+    assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
+    p.solver = _lib.AMG_SOLVER_PCG
     p.symmetric = 1
     p.precondition = 2
     assert L.amg_setup(C.byref(p), 4, 4, 1, 1, 1, 1, None, C.byref(h)) == _lib.AMG_ERR_INVALID_ARG
@@ -77,5 +86,7 @@ def test_make_params_overrides():
     from paper_2606_09001_amd.solver import make_params
     p = make_params(vcycle_prec="fp32", smoother="l1", omega=0.5, max_coarse=64)
     assert p.vcycle_prec == 1 and p.smoother == 1 and p.omega == 0.5 and p.max_coarse == 64
+    p = make_params(solver="bicgstab", symmetric=False)
+    assert p.solver == 1 and p.symmetric == 0
     with pytest.raises(TypeError):
         make_params(bogus=1)
