@@ -400,6 +400,73 @@ def run_plain_cg(args, dev):
             "rel_resid": info["rel_resid"], "solve_hbm_gbs": round(gbs, 1), "solve_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def run_nonsym(args, dev):
+    """Nonsymmetric system: 3D upwind convection-diffusion 128^3 with a
+    recirculating wind (speed 300, cell Peclet up to ~1.2), b ~ N(0,1) seed
+    61, right-preconditioned BiCGSTAB + SA-AMG (LU coarse solve) to 1e-8 with
+    the FP64 and the FP32 cycle; the adjoint A^T lambda = g: first call (device
+    transpose + hierarchy of A^T + solve) and warm calls.  True residuals are
+    recomputed with the oracle's SpMV."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2606_09001_amd import matrices as M
+    from paper_2606_09001_amd.solver import AmgHierarchy, finalize
+    N = args.nonsym_grid
+    rp, ci, v = M.convection_diffusion(N, 3, M.recirculating_wind(N, 3, 300.0))
+    n = len(rp) - 1
+    b = M.rhs_normal(n, 61)
+    g = M.rhs_normal(n, 62)
+    d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v, b, g)]
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    lam = torch.empty_like(x)
+    out = {"workload": f"3D upwind convection-diffusion {N}^3 ({n} unknowns, {len(ci)} nnz), recirculating wind "
+                       f"speed 300, b ~ N(0,1) seed 61, SA-AMG (LU coarse) + BiCGSTAB to {args.tol:g}"}
+    k = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for prec in ("fp64", "fp32"):
+        t0 = time.time()
+        H = AmgHierarchy(d[0], d[1], d[2], symmetric=False, solver="bicgstab", vcycle_prec=prec)
+        torch.cuda.synchronize()
+        setup_ms = (time.time() - t0) * 1e3
+        _, info = H.solve(d[3], args.tol, out=x)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(k):
+            _, info = H.solve(d[3], args.tol, out=x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / k
+        rel = oracle.rel_residual(rp, ci, v, b, x.cpu().numpy())
+        r = {"ms_per_solve": round(ms, 3), "solves_per_s": round(1e3 / ms, 2), "iters": info["iters"],
+             "rel_resid": info["rel_resid"], "oracle_rel_resid": rel, "setup_ms": round(setup_ms, 1),
+             "levels": H.stats()["num_levels"]}
+        if prec == "fp64":
+            t0 = time.time()
+            _, ai = H.solve_adjoint(d[4], args.tol, out=lam)
+            torch.cuda.synchronize()
+            first_ms = (time.time() - t0) * 1e3
+            e0.record()
+            for _ in range(k):
+                _, ai = H.solve_adjoint(d[4], args.tol, out=lam)
+            e1.record()
+            torch.cuda.synchronize()
+            ams = e0.elapsed_time(e1) / k
+            rpT, ciT, vT = oracle.transpose(rp, ci, v)
+            arel = oracle.rel_residual(rpT, ciT, vT, g, lam.cpu().numpy())
+            r.update({"adjoint_first_ms": round(first_ms, 1), "adjoint_ms": round(ams, 3),
+                      "adjoint_iters": ai["iters"], "adjoint_oracle_rel_resid": arel})
+            log(f"nonsym {prec}: adjoint first call (transpose + A^T setup + solve) {first_ms:.1f} ms, "
+                f"warm {ams:.2f} ms, iters {ai['iters']}, true residual {arel:.2e}")
+        out[prec] = r
+        log(f"nonsym {prec}: setup {setup_ms:.1f} ms, {ms:.2f} ms/solve ({1e3 / ms:.1f} solves/s), "
+            f"iters {info['iters']}, true residual {rel:.2e}")
+        H.close()
+        finalize()
+    out["speedup_fp32_cycle"] = round(out["fp64"]["ms_per_solve"] / out["fp32"]["ms_per_solve"], 4)
+    return out
+
+
 def run_adjoint(args, dev):
     """2D diffusion 512^2 inverse-problem step: values k = exp(theta) assembled
     in torch, forward solve, loss 0.5||u - u_obs||^2, backward (adjoint solve
@@ -470,6 +537,7 @@ def main():
     ap.add_argument("--diffusion-only", action="store_true",
                     help="only the 192^3 diffusion workload (with the counter calibration kernel); for profiling")
     ap.add_argument("--diffusion-grid", type=int, default=192)
+    ap.add_argument("--nonsym-grid", type=int, default=128)
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write profiles/ summaries from rocprofv3 output of this script (no GPU)")
     ap.add_argument("--summary-tag", default="poisson3d_128")
@@ -676,7 +744,7 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         batched = run_batched(args, dev)
-    diffusion = adjoint = small = plain = None
+    diffusion = adjoint = small = plain = nonsym = None
     if not args.no_extra:
         from paper_2606_09001_amd.solver import finalize
         finalize()
@@ -685,6 +753,7 @@ def main():
         adjoint = run_adjoint(args, dev)
         small = run_small(args, dev)
         plain = run_plain_cg(args, dev)
+        nonsym = run_nonsym(args, dev)
 
     f64, f32 = res["fp64"], res["fp32"]
     out = {
@@ -723,6 +792,7 @@ def main():
         "adjoint": adjoint,
         "poisson2d_32": small,
         "plain_cg_tridiag_1e7": plain,
+        "nonsymmetric_bicgstab": nonsym,
         "ceilings": ceilings,
     }
     print(json.dumps(out), flush=True)
