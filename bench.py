@@ -361,10 +361,29 @@ def run_small(args, dev):
     ms = e0.elapsed_time(e1) / k
     log(f"poisson 32^2: {ms * 1e3:.0f} us/solve ({1e3 / ms:.0f} solves/s), iters {info['iters']}")
     H.close()
+    out = {"workload": "2D Poisson 5-point 32^2 (1024 unknowns), b ~ N(0,1) seed 0, tol 1e-10, FP64",
+           "ms_per_solve": round(ms, 4), "solves_per_s": round(1e3 / ms, 1), "iters": info["iters"],
+           "rel_resid": info["rel_resid"]}
+    # Section 3.1's example: b = 1, tol 1e-6, BiCGSTAB with and without the AMG preconditioner
+    ones = torch.ones(n, dtype=torch.float64, device=dev)
+    sec = {}
+    for pre in (1, 0):
+        Hb = AmgHierarchy(d[0], d[1], d[2], solver="bicgstab", precondition=pre)
+        _, ib = Hb.solve(ones, 1e-6, out=x)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(k):
+            _, ib = Hb.solve(ones, 1e-6, out=x)
+        e1.record()
+        torch.cuda.synchronize()
+        mb = e0.elapsed_time(e1) / k
+        sec["amg" if pre else "none"] = {"iters": ib["iters"], "rel_resid": ib["rel_resid"], "ms_per_solve": round(mb, 4)}
+        Hb.close()
+    log(f"poisson 32^2 b = 1 BiCGSTAB tol 1e-6: AMG {sec['amg']['iters']} iterations, "
+        f"none {sec['none']['iters']} (paper, with its backend's AMG: 6 and 37)")
+    out["section_3_1_bicgstab_ones_1e-6"] = sec
     finalize()
-    return {"workload": "2D Poisson 5-point 32^2 (1024 unknowns), b ~ N(0,1) seed 0, tol 1e-10, FP64",
-            "ms_per_solve": round(ms, 4), "solves_per_s": round(1e3 / ms, 1), "iters": info["iters"],
-            "rel_resid": info["rel_resid"]}
+    return out
 
 
 def run_plain_cg(args, dev):
@@ -465,6 +484,36 @@ def run_nonsym(args, dev):
         finalize()
     out["speedup_fp32_cycle"] = round(out["fp64"]["ms_per_solve"] / out["fp32"]["ms_per_solve"], 4)
     return out
+
+
+def run_plain_bicgstab(args, dev):
+    """Unpreconditioned BiCGSTAB on tridiag(-1, 2.5, -1), n = 10^7 (the
+    paper's Fig. 2 system family), b ~ N(0,1) seed 32, to 1e-10."""
+    import torch
+    from paper_2606_09001_amd import matrices as M
+    from paper_2606_09001_amd.solver import AmgHierarchy, finalize
+    n = 10_000_000
+    rp, ci, v = M.tridiagonal(n, 2.5)
+    d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v, M.rhs_normal(n, 32))]
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    H = AmgHierarchy(d[0], d[1], d[2], precondition=0, solver="bicgstab")
+    _, info = H.solve(d[3], 1e-10, out=x)
+    torch.cuda.synchronize()
+    k = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(k):
+        _, info = H.solve(d[3], 1e-10, out=x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / k
+    log(f"plain BiCGSTAB tridiag 1e7: {ms:.2f} ms/solve ({1e3 / ms:.1f} solves/s), iters {info['iters']}")
+    H.close()
+    finalize()
+    return {"workload": "plain BiCGSTAB (no preconditioner) on tridiag(-1, 2.5, -1), n = 10^7, b ~ N(0,1) seed 32, "
+                        "tol 1e-10",
+            "ms_per_solve": round(ms, 3), "solves_per_s": round(1e3 / ms, 2), "iters": info["iters"],
+            "rel_resid": info["rel_resid"]}
 
 
 def run_adjoint(args, dev):
@@ -744,7 +793,7 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         batched = run_batched(args, dev)
-    diffusion = adjoint = small = plain = nonsym = None
+    diffusion = adjoint = small = plain = plain_bi = nonsym = None
     if not args.no_extra:
         from paper_2606_09001_amd.solver import finalize
         finalize()
@@ -753,6 +802,7 @@ def main():
         adjoint = run_adjoint(args, dev)
         small = run_small(args, dev)
         plain = run_plain_cg(args, dev)
+        plain_bi = run_plain_bicgstab(args, dev)
         nonsym = run_nonsym(args, dev)
 
     f64, f32 = res["fp64"], res["fp32"]
@@ -792,6 +842,7 @@ def main():
         "adjoint": adjoint,
         "poisson2d_32": small,
         "plain_cg_tridiag_1e7": plain,
+        "plain_bicgstab_tridiag_1e7": plain_bi,
         "nonsymmetric_bicgstab": nonsym,
         "ceilings": ceilings,
     }
