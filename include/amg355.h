@@ -11,9 +11,9 @@
  *     ("C++/CUDA backend")
  *   - the adjoint solve A^T lambda = dL/dx            -- Eq. (1); a
  *     nonsymmetric A gets an explicit transpose A^T and its own hierarchy
- *     (Section 2.2, "Automatic differentiation")
+ *     (Section 2.1)
  *   - BiCGSTAB with the AMG preconditioner, the paper's default solver for
- *     general (nonsymmetric) systems                  -- Section 2.2
+ *     general (nonsymmetric) systems                  -- Section 2.1
  *   - the gradients dL/dA = -lambda x^T (restricted to the stored pattern)
  *     and dL/db = lambda                              -- Eq. (2)
  *   - single- and double-precision arithmetic         -- Section 2.2

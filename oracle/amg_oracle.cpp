@@ -12,8 +12,8 @@
 // distance-2 maximal independent set roots in decreasing-key order,
 // aggregates, smoothed prolongator, Galerkin product, damped-Jacobi V(1,1),
 // PCG; for a nonsymmetric A: an LU coarse solve, right-preconditioned
-// BiCGSTAB -- the paper's default solver, Section 2.2 -- and an adjoint on the
-// explicit transpose, Section 2.2 "Automatic differentiation").
+// BiCGSTAB -- the paper's default solver, Section 2.1 -- and an adjoint on the
+// explicit transpose, Section 2.1 with Eq. (1)).
 //
 // Build: g++ -O2 -std=c++17 -ffp-contract=off -shared -fPIC (no FMA
 // contraction: every product and sum is rounded on its own).
@@ -596,7 +596,7 @@ int pcg(const Hier& H, const double* bptr, double* xptr, double tol, int maxiter
 }
 
 // Right-preconditioned BiCGSTAB (van der Vorst, 1992) from x0 = 0, the
-// paper's default Krylov method (Section 2.2).  Shadow residual r^ = r0.
+// paper's default Krylov method (Section 2.1).  Shadow residual r^ = r0.
 // One iteration:
 //   rho = <r^, r>;  p = r (first) or r + beta (p - omega v),
 //                   beta = (rho / rho_old) (alpha / omega)

@@ -1834,7 +1834,7 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
 }
 
 // Right-preconditioned BiCGSTAB (van der Vorst, 1992), the paper's default
-// Krylov method (Section 2.2), from x0 = 0 with shadow residual r^ = b.
+// Krylov method (Section 2.1), from x0 = 0 with shadow residual r^ = b.
 // One iteration, every scalar formed on the device:
 //   p = r + beta (p - omega v)        k_bi_dir   (p = r after a (re)start)
 //   y = M^-1 p                        V-cycle
@@ -1880,13 +1880,19 @@ amg_status bicgstab_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, d
   double* y = H.by.p;
   double* sv = H.bs.p;
   double* t = H.bt2.p;
+  // no preconditioner: y = p and z = s are the same vectors (no copies)
+  const bool prec = H.prm.precondition != 0;
+  if (!prec) {
+    y = p;
+    z = sv;
+  }
   const int gv = vec_grid(n);
   hipLaunchKernelGGL(k_bi_init, dim3(gv), dim3(kBlock), 0, s, n, d_b, r, rh, d_x, part);
   hipLaunchKernelGGL(k_bfin_init, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv, tol, o.maxiter);
   AMG_HIP(hipGetLastError());
   auto iteration = [&](int first, hipStream_t st) {
     hipLaunchKernelGGL(k_bi_dir, dim3(gv), dim3(kBlock), 0, st, n, r, v, p, ctl, first);
-    vcycle(H, CycleArgs{p, y, nullptr, ctl, part, 0, 0, 0}, st);
+    if (prec) vcycle(H, CycleArgs{p, y, nullptr, ctl, part, 0, 0, 0}, st);
     int np;
     {
       InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
@@ -1895,7 +1901,7 @@ amg_status bicgstab_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, d
     hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(kFinBlock), 0, st, ctl, part, np);
     hipLaunchKernelGGL(k_bi_half, dim3(gv), dim3(kBlock), 0, st, n, d_x, y, r, v, sv, ctl, part);
     hipLaunchKernelGGL(k_bfin_half, dim3(1), dim3(kFinBlock), 0, st, ctl, part, gv);
-    vcycle(H, CycleArgs{sv, z, nullptr, ctl, part, 0, 0, 0}, st);
+    if (prec) vcycle(H, CycleArgs{sv, z, nullptr, ctl, part, 0, 0, 0}, st);
     {
       InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
       np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpSpmvDots<2>{L0.av(), z, t, sv}, ctl, part, st);
