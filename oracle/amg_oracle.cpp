@@ -848,6 +848,60 @@ double or_rel_residual(int n, const int* rp, const int* ci, const double* v, con
   return std::sqrt(rr / bb);
 }
 
+// ------------------------------------------------ matrix-free assembly
+// Graph-colored probing (Section 2.1, "Matrix-free operator support";
+// Curtis, Powell and Reid 1974): a partition of the columns into groups in
+// which no two columns share a row, so that one operator application to the
+// 0/1 sum of a group's unit vectors yields every entry of those columns.
+
+// Greedy coloring in decreasing node-key order (the same keys as the
+// aggregation): each column takes the smallest color not used by any
+// already colored column that shares a row with it.  Returns the number of
+// colors.
+int or_color_columns(int n, const int* rp, const int* ci, int* color) {
+  Csr A;
+  A.nrows = A.ncols = n;
+  A.rp.assign(rp, rp + n + 1);
+  A.ci.assign(ci, ci + rp[n]);
+  A.v.assign(rp[n], 0.0);
+  Csr T = transpose(A);  // column j -> its rows
+  std::vector<int> order(n);
+  for (int j = 0; j < n; ++j) order[j] = j;
+  std::sort(order.begin(), order.end(), [](int a, int b) { return node_key(a) > node_key(b); });
+  for (int j = 0; j < n; ++j) color[j] = -1;
+  std::vector<int> seen(n + 1, -1);  // seen[c] == j: color c is used next to column j
+  int ncolors = 0;
+  for (int j : order) {
+    for (int a = T.rp[j]; a < T.rp[j + 1]; ++a) {
+      int i = T.ci[a];
+      for (int b = A.rp[i]; b < A.rp[i + 1]; ++b) {
+        int c = color[A.ci[b]];
+        if (c >= 0) seen[c] = j;
+      }
+    }
+    int c = 0;
+    while (seen[c] == j) ++c;
+    color[j] = c;
+    ncolors = std::max(ncolors, c + 1);
+  }
+  return ncolors;
+}
+
+// val[k] = Y[color(col k)][row k]: Y = A V with probe c = sum of the unit
+// vectors of the columns of color c, stored [ncolors][n].
+void or_probe_assemble(int n, const int* rp, const int* ci, const int* color, const double* Y, double* val) {
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) val[k] = Y[(size_t)color[ci[k]] * n + i];
+}
+
+// Adjoint of the assembly: dY = 0, then dY[color(col k)][row k] = dval[k].
+void or_probe_scatter(int n, const int* rp, const int* ci, const int* color, int ncolors, const double* dval,
+                      double* dY) {
+  std::fill(dY, dY + (size_t)ncolors * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) dY[(size_t)color[ci[k]] * n + i] = dval[k];
+}
+
 uint64_t or_node_key(int i) { return node_key(i); }
 
 int or_validate(int n, const int* rp, const int* ci) { return validate_csr(n, rp, ci); }

@@ -11,6 +11,7 @@ import os
 import numpy as np
 
 __all__ = ["OracleHierarchy", "spmv", "pattern_grad", "rel_residual", "node_key", "validate", "transpose",
+           "color_columns", "probe_vectors", "probe_assemble", "probe_scatter",
            "diffusion_theta_grad", "OR_OK", "OR_NOT_CONVERGED", "OR_ERR_INVALID_ARG", "OR_ERR_ZERO_DIAG",
            "OR_ERR_PATTERN_MISMATCH", "OR_ERR_BREAKDOWN", "OR_ERR_COARSE_TOO_LARGE", "load"]
 
@@ -70,6 +71,10 @@ def load():
     L.or_spmv.argtypes = [C.c_int, _ip, _ip, _dp, _dp, _dp]
     L.or_rel_residual.restype = C.c_double
     L.or_rel_residual.argtypes = [C.c_int, _ip, _ip, _dp, _dp, _dp]
+    L.or_color_columns.restype = C.c_int
+    L.or_color_columns.argtypes = [C.c_int, _ip, _ip, _ip]
+    L.or_probe_assemble.argtypes = [C.c_int, _ip, _ip, _ip, _dp, _dp]
+    L.or_probe_scatter.argtypes = [C.c_int, _ip, _ip, _ip, C.c_int, _dp, _dp]
     L.or_node_key.restype = C.c_uint64
     L.or_node_key.argtypes = [C.c_int]
     L.or_validate.restype = C.c_int
@@ -288,6 +293,42 @@ def transpose(rp, ci, v):
 def rel_residual(rp, ci, v, b, x):
     rp, ci, v, b, x = _i32(rp), _i32(ci), _f64(v), _f64(b), _f64(x)
     return float(load().or_rel_residual(len(rp) - 1, rp, ci, v, b, x))
+
+
+def color_columns(rp, ci):
+    """(color[n], ncolors): greedy column coloring in decreasing key order
+    (no two columns of one color share a row)."""
+    rp, ci = _i32(rp), _i32(ci)
+    n = len(rp) - 1
+    color = np.zeros(n, np.int32)
+    nc = load().or_color_columns(n, rp, ci, color)
+    return color, int(nc)
+
+
+def probe_vectors(color, ncolors):
+    """V[c][j] = 1 if column j has color c (the probe vectors, [ncolors][n])."""
+    color = np.asarray(color)
+    V = np.zeros((ncolors, len(color)))
+    V[color, np.arange(len(color))] = 1.0
+    return V
+
+
+def probe_assemble(rp, ci, color, Y):
+    """CSR values from the probe products Y = A V^T ([ncolors][n])."""
+    rp, ci, color = _i32(rp), _i32(ci), _i32(color)
+    Y = _f64(Y)
+    val = np.zeros(len(ci))
+    load().or_probe_assemble(len(rp) - 1, rp, ci, color, Y.ravel(), val)
+    return val
+
+
+def probe_scatter(rp, ci, color, ncolors, dval):
+    """Adjoint of probe_assemble: dY ([ncolors][n])."""
+    rp, ci, color, dval = _i32(rp), _i32(ci), _i32(color), _f64(dval)
+    n = len(rp) - 1
+    dY = np.zeros(ncolors * n)
+    load().or_probe_scatter(n, rp, ci, color, int(ncolors), dval, dY)
+    return dY.reshape(ncolors, n)
 
 
 def node_key(i: int) -> int:
