@@ -226,6 +226,42 @@ amg_status amg_pattern_grad_batched(amg_handle h, const double* d_lambda, const 
  * cycle precision inside): the preconditioner as an operator. */
 amg_status amg_apply_vcycle(amg_handle h, const double* d_r, double* d_z, hipStream_t stream);
 
+/* ---- matrix-free operators (Section 2.1, "Matrix-free operator support") ----
+ * An operator given as a callable x -> A x with a known CSR pattern is
+ * materialized by graph-colored probing (Curtis-Powell-Reid): the columns are
+ * colored so that no two columns of a color share a row, the operator is
+ * applied once to each color's 0/1 probe vector, and every stored entry is
+ * read off the products: a_ij = (A v_color(j))_i.  The caller applies the
+ * operator (it is the caller's code); the library colors, builds the probes
+ * and assembles.  Probe and product blocks are stored [ncolors][n] (one
+ * contiguous vector per color).  The pattern follows the CSR conventions
+ * above (sorted columns, every diagonal stored) and is validated.
+ *
+ * Coloring: greedy in decreasing node-key order (the keys of the
+ * aggregation), each column taking the smallest color not used by an
+ * already colored column that shares a row with it; deterministic.
+ * d_color: int32[n] device output; *ncolors: host output (the stream is
+ * synchronised). */
+amg_status amg_color_columns(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
+                             int32_t* d_color, int32_t* ncolors, hipStream_t stream);
+
+/* d_V (float64[ncolors*n], device): V[c*n + j] = 1 if color[j] == c, else 0.
+ * A color outside [0, ncolors) is AMG_ERR_INVALID_ARG (nothing written). */
+amg_status amg_probe_vectors(int32_t n, const int32_t* d_color, int32_t ncolors, double* d_V, hipStream_t stream);
+
+/* d_val[k] = d_Y[color[col k]*n + row k] for every stored entry k, where d_Y
+ * (float64[ncolors*n]) holds the products A V_c.  Exact (no arithmetic): the
+ * result equals A's values when the pattern covers A's nonzeros. */
+amg_status amg_probe_assemble(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
+                              const int32_t* d_color, int32_t ncolors, const double* d_Y, double* d_val,
+                              hipStream_t stream);
+
+/* Adjoint of amg_probe_assemble (for gradients through the operator):
+ * d_dY = 0, then d_dY[color[col k]*n + row k] = d_dval[k]. */
+amg_status amg_probe_scatter(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
+                             const int32_t* d_color, int32_t ncolors, const double* d_dval, double* d_dY,
+                             hipStream_t stream);
+
 /* Hierarchy statistics (Section 2.2 diagnostics). */
 amg_status amg_hierarchy_stats(amg_handle h, amg_hier_stats* out);
 

@@ -39,7 +39,8 @@ EXPORTS = [
     "amg_params_default", "amg_setup", "amg_update_values", "amg_solve", "amg_solve_adjoint", "amg_pattern_grad",
     "amg_apply_vcycle", "amg_hierarchy_stats", "amg_field_info", "amg_export_field", "amg_destroy", "amg_finalize",
     "amg_cache_size", "amg_set_cache_capacity", "amg_status_string", "amg_instrument", "amg_instrument_read",
-    "amg_kernel_bytes", "amg_pattern_grad_batched", "amg_solve_columns",
+    "amg_kernel_bytes", "amg_pattern_grad_batched", "amg_solve_columns", "amg_color_columns",
+    "amg_probe_vectors", "amg_probe_assemble", "amg_probe_scatter",
 ]
 
 KERNELS = {"spmv_dot": 0, "pre": 1, "post": 2, "restrict": 3, "prolong": 4, "cg_update": 5, "xpay": 6, "coarse": 7}
@@ -120,6 +121,10 @@ def load():
     L.amg_kernel_bytes.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(dbl)]
     L.amg_pattern_grad_batched.argtypes = [vp, vp, vp, i32, vp, vp]
     L.amg_solve_columns.argtypes = [vp, i32, vp, vp, vp]
+    L.amg_color_columns.argtypes = [i32, i64, vp, vp, vp, C.POINTER(i32), vp]
+    L.amg_probe_vectors.argtypes = [i32, vp, i32, vp, vp]
+    L.amg_probe_assemble.argtypes = [i32, i64, vp, vp, vp, i32, vp, vp, vp]
+    L.amg_probe_scatter.argtypes = [i32, i64, vp, vp, vp, i32, vp, vp, vp]
     L.amg_status_string.argtypes = [C.c_int]
     L.amg_status_string.restype = C.c_char_p
     for name in EXPORTS:

@@ -292,6 +292,17 @@ bool values_equal(const Hierarchy& H, const double* d_val, int* d_flags, int* h_
 // of A^T is entry tperm[t] of A), then tval = A's values in that order.
 void transpose_pattern(Hierarchy& H, hipStream_t s);
 void transpose_values(Hierarchy& H, hipStream_t s);
+// Sorted CSR pattern of A^T (n x n, nnz entries) and the entry map perm.
+void transpose_csr_pattern(int n, int64_t nnz, const int* rp, const int* ci, DBuf<int>& trp, DBuf<int>& tci,
+                           DBuf<int>& perm, hipStream_t s);
+// probe.hip: matrix-free assembly by graph-colored probing
+int color_columns(int n, int64_t nnz, const int* rp, const int* ci, int* color, int* d_flags, int* h_flags,
+                  hipStream_t s);
+void probe_vectors(int n, const int* color, int ncolors, double* V, int* d_flags, int* h_flags, hipStream_t s);
+void probe_assemble(int n, const int* rp, const int* ci, const int* color, int ncolors, const double* Y, double* val,
+                    int* d_flags, int* h_flags, hipStream_t s);
+void probe_scatter(int n, const int* rp, const int* ci, const int* color, int ncolors, const double* dval,
+                   double* dY, int* d_flags, int* h_flags, hipStream_t s);
 // coarse.hip
 void coarse_setup(Hierarchy& H, hipStream_t s);
 // solve.hip

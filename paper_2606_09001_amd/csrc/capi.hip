@@ -380,6 +380,59 @@ amg_status amg_apply_vcycle(amg_handle h, const double* d_r, double* d_z, hipStr
   });
 }
 
+amg_status amg_color_columns(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
+                             int32_t* d_color, int32_t* ncolors, hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!d_row_ptr || !d_col || !d_color || !ncolors || n <= 0 || nnz < n || nnz >= (int64_t)INT32_MAX)
+      return AMG_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_mu);
+    ensure_global_flags();
+    validate_csr(n, nnz, d_row_ptr, d_col, g_flags.d, g_flags.h, stream);
+    *ncolors = color_columns(n, nnz, d_row_ptr, d_col, d_color, g_flags.d, g_flags.h, stream);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_probe_vectors(int32_t n, const int32_t* d_color, int32_t ncolors, double* d_V, hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!d_color || !d_V || n <= 0 || ncolors <= 0) return AMG_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_mu);
+    ensure_global_flags();
+    probe_vectors(n, d_color, ncolors, d_V, g_flags.d, g_flags.h, stream);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_probe_assemble(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
+                              const int32_t* d_color, int32_t ncolors, const double* d_Y, double* d_val,
+                              hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!d_row_ptr || !d_col || !d_color || !d_Y || !d_val || n <= 0 || nnz < n || nnz >= (int64_t)INT32_MAX ||
+        ncolors <= 0)
+      return AMG_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_mu);
+    ensure_global_flags();
+    validate_csr(n, nnz, d_row_ptr, d_col, g_flags.d, g_flags.h, stream);
+    probe_assemble(n, d_row_ptr, d_col, d_color, ncolors, d_Y, d_val, g_flags.d, g_flags.h, stream);
+    return AMG_OK;
+  });
+}
+
+amg_status amg_probe_scatter(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
+                             const int32_t* d_color, int32_t ncolors, const double* d_dval, double* d_dY,
+                             hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (!d_row_ptr || !d_col || !d_color || !d_dval || !d_dY || n <= 0 || nnz < n || nnz >= (int64_t)INT32_MAX ||
+        ncolors <= 0)
+      return AMG_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_mu);
+    ensure_global_flags();
+    validate_csr(n, nnz, d_row_ptr, d_col, g_flags.d, g_flags.h, stream);
+    probe_scatter(n, d_row_ptr, d_col, d_color, ncolors, d_dval, d_dY, g_flags.d, g_flags.h, stream);
+    return AMG_OK;
+  });
+}
+
 amg_status amg_hierarchy_stats(amg_handle h, amg_hier_stats* out) {
   if (!h || !out) return AMG_ERR_INVALID_ARG;
   const Hierarchy& H = *h->H;

@@ -433,6 +433,13 @@ __global__ void k_r_fill(int64_t m, const int* __restrict__ perm, const int* __r
   rv[t * vs] = pv[(int64_t)k * vs];
 }
 
+// Columns of a transposed pattern: entry t holds the source row of entry perm[t].
+__global__ void k_t_cols(int64_t m, const int* __restrict__ perm, const int* __restrict__ rowid,
+                         int* __restrict__ tci) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < m) tci[t] = rowid[perm[t]];
+}
+
 // ------------------------------------------------- canonical products
 
 // Position of column J in the sorted column list [lo, hi), or -1.
@@ -1260,36 +1267,43 @@ void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const doubl
   AMG_HIP(hipStreamSynchronize(s));
 }
 
-// A^T of the level-0 matrix by a stable radix sort of the entries by column:
-// entry t of A^T is entry tperm[t] of A, and within a row of A^T the source
-// rows ascend (the stable sort keeps A's row order), so the result is a valid
-// sorted CSR matrix with every diagonal stored.
-void transpose_pattern(Hierarchy& H, hipStream_t s) {
-  const Level& L = H.lv[0];
-  const int n = L.n;
-  const int64_t nnz = L.nnz;
+// Pattern of A^T by a stable radix sort of the entries by column: entry t of
+// A^T is entry perm[t] of A, and within a row of A^T the source rows ascend
+// (the stable sort keeps A's row order), so the result is a sorted CSR
+// pattern (with every diagonal stored when A has them).
+void transpose_csr_pattern(int n, int64_t nnz, const int* rp, const int* ci, DBuf<int>& trp, DBuf<int>& tci,
+                           DBuf<int>& perm, hipStream_t s) {
   const dim3 b(kBlock);
   DBuf<int> rowid, iota, keys_out, cnt;
-  rowid.alloc(nnz);
-  iota.alloc(nnz);
-  keys_out.alloc(nnz);
-  H.tperm.alloc(nnz);
-  hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n)), b, 0, s, n, L.rp.p, rowid.p);
+  rowid.alloc(std::max<int64_t>(nnz, 1));
+  iota.alloc(std::max<int64_t>(nnz, 1));
+  keys_out.alloc(std::max<int64_t>(nnz, 1));
+  perm.alloc(std::max<int64_t>(nnz, 1));
+  hipLaunchKernelGGL(k_row_ids, dim3(grid_for(n)), b, 0, s, n, rp, rowid.p);
   hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), b, 0, s, nnz, iota.p);
   int end_bit = 1;
   while ((1ll << end_bit) < (long long)n) ++end_bit;
   cub_call([&](void* t, size_t& bb) {
-    return hipcub::DeviceRadixSort::SortPairs(t, bb, L.ci.p, keys_out.p, iota.p, H.tperm.p, (int)nnz, 0, end_bit, s);
+    return hipcub::DeviceRadixSort::SortPairs(t, bb, ci, keys_out.p, iota.p, perm.p, (int)nnz, 0, end_bit, s);
   }, s);
   cnt.alloc(n + 1);
   AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (n + 1), s));
-  hipLaunchKernelGGL(k_col_count, dim3(grid_for(nnz)), b, 0, s, nnz, L.ci.p, cnt.p);
-  H.trp.alloc(n + 1);
-  exclusive_scan(cnt.p, H.trp.p, n + 1, s);
-  H.tci.alloc(nnz);
-  H.tval.alloc(nnz);
-  hipLaunchKernelGGL(k_r_fill, dim3(grid_for(nnz)), b, 0, s, nnz, H.tperm.p, rowid.p, L.v.p, 1, H.tci.p, H.tval.p);
+  hipLaunchKernelGGL(k_col_count, dim3(grid_for(nnz)), b, 0, s, nnz, ci, cnt.p);
+  trp.alloc(n + 1);
+  exclusive_scan(cnt.p, trp.p, n + 1, s);
+  tci.alloc(std::max<int64_t>(nnz, 1));
+  hipLaunchKernelGGL(k_t_cols, dim3(grid_for(nnz)), b, 0, s, nnz, perm.p, rowid.p, tci.p);
   AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+// A^T of the level-0 matrix (pattern, entry map, values) for the adjoint of
+// a nonsymmetric A.
+void transpose_pattern(Hierarchy& H, hipStream_t s) {
+  const Level& L = H.lv[0];
+  transpose_csr_pattern(L.n, L.nnz, L.rp.p, L.ci.p, H.trp, H.tci, H.tperm, s);
+  H.tval.alloc(L.nnz);
+  transpose_values(H, s);
   AMG_HIP(hipStreamSynchronize(s));
 }
 

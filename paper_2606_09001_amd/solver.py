@@ -17,7 +17,7 @@ import torch
 from . import _lib
 
 __all__ = ["AmgHierarchy", "solve", "amg_solve", "AmgSolve", "make_params", "finalize", "cache_size",
-           "set_cache_capacity", "make_preconditioner"]
+           "set_cache_capacity", "make_preconditioner", "MatrixFreeOperator", "detect_pattern"]
 
 _PARAM_KEYS = ("vcycle_prec", "transfer_bf16", "theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre",
                "nu_post", "maxiter", "flexible", "symmetric", "check_every", "use_graphs", "autotune",
@@ -266,6 +266,103 @@ class AmgSolve(torch.autograd.Function):
 def amg_solve(row_ptr, col, val, b, tol: float = 1e-8, **params):
     """Differentiable solve (autograd through val and b)."""
     return AmgSolve.apply(row_ptr, col, val, b, tol, tuple(sorted(params.items())))
+
+
+class _ProbeAssemble(torch.autograd.Function):
+    """CSR values gathered from the probe products Y ([ncolors][n]); the
+    backward is the assembly's adjoint (scatter), so gradients reach the
+    operator's parameters through the caller's own autograd graph."""
+
+    @staticmethod
+    def forward(ctx, Y, op):
+        L = _lib.load()
+        Y = _dev_f64(Y, "Y")
+        val = torch.empty(op.nnz, dtype=torch.float64, device=Y.device)
+        _lib.check(L.amg_probe_assemble(op.n, op.nnz, op.row_ptr.data_ptr(), op.col.data_ptr(),
+                                        op.color.data_ptr(), op.ncolors, Y.data_ptr(), val.data_ptr(), _stream()),
+                   "amg_probe_assemble")
+        ctx.op = op
+        return val
+
+    @staticmethod
+    def backward(ctx, dval):
+        op = ctx.op
+        L = _lib.load()
+        dval = _dev_f64(dval, "dval")
+        dY = torch.empty(op.ncolors, op.n, dtype=torch.float64, device=dval.device)
+        _lib.check(L.amg_probe_scatter(op.n, op.nnz, op.row_ptr.data_ptr(), op.col.data_ptr(), op.color.data_ptr(),
+                                       op.ncolors, dval.data_ptr(), dY.data_ptr(), _stream()), "amg_probe_scatter")
+        return dY, None
+
+
+class MatrixFreeOperator:
+    """A linear operator given as a callable x -> A x (torch, on the device)
+    together with its CSR sparsity pattern, materialized by graph-colored
+    probing (Section 2.1, "Matrix-free operator support").
+
+    The column coloring and the probe vectors are computed once per pattern
+    (the paper's cache_coloring / with_cache); ``assemble(matvec)`` applies
+    the operator once per color and gathers the values, differentiably.  Use
+    ``solve`` / ``amg_solve_op`` to solve with the assembled matrix."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, matvec=None):
+        L = _lib.load()
+        self.row_ptr = _dev_i32(row_ptr, "row_ptr")
+        self.col = _dev_i32(col, "col")
+        self.n = self.row_ptr.numel() - 1
+        self.nnz = self.col.numel()
+        self.matvec = matvec
+        self.color = torch.empty(self.n, dtype=torch.int32, device=self.row_ptr.device)
+        nc = C.c_int32(0)
+        _lib.check(L.amg_color_columns(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                                       self.color.data_ptr(), C.byref(nc), _stream()), "amg_color_columns")
+        self.ncolors = nc.value
+        self.probes = torch.empty(self.ncolors, self.n, dtype=torch.float64, device=self.row_ptr.device)
+        _lib.check(L.amg_probe_vectors(self.n, self.color.data_ptr(), self.ncolors, self.probes.data_ptr(),
+                                       _stream()), "amg_probe_vectors")
+
+    def with_operator(self, matvec) -> "MatrixFreeOperator":
+        """The same pattern and coloring for another operator (e.g. new parameters)."""
+        op = object.__new__(MatrixFreeOperator)
+        op.__dict__.update(self.__dict__)
+        op.matvec = matvec
+        return op
+
+    def assemble(self, matvec=None) -> torch.Tensor:
+        """CSR values of the operator: one application per color."""
+        f = matvec if matvec is not None else self.matvec
+        if f is None:
+            raise ValueError("no operator to assemble")
+        Y = torch.stack([f(self.probes[c]) for c in range(self.ncolors)])
+        return _ProbeAssemble.apply(Y, self)
+
+    def csr(self, matvec=None):
+        return self.row_ptr, self.col, self.assemble(matvec)
+
+    def solve(self, b: torch.Tensor, tol: float = 1e-8, **params):
+        """Differentiable solve A x = b with the assembled operator."""
+        return amg_solve(self.row_ptr, self.col, self.assemble(), b, tol, **params)
+
+
+def detect_pattern(matvec, n: int, device="cuda"):
+    """Sparsity pattern of an operator by probing with one-hot vectors (the
+    paper's fallback when the operator cannot be traced): n applications, so
+    meant for modest n.  Returns (row_ptr, col) with every diagonal included."""
+    rows, cols = [], []
+    with torch.no_grad():
+        for j in range(n):
+            e = torch.zeros(n, dtype=torch.float64, device=device)
+            e[j] = 1.0
+            nz = torch.nonzero(matvec(e) != 0).flatten()
+            rows.append(nz)
+            cols.append(torch.full_like(nz, j))
+    r = torch.cat(rows + [torch.arange(n, device=device)])
+    c = torch.cat(cols + [torch.arange(n, device=device)])
+    key = torch.unique(r.to(torch.int64) * n + c.to(torch.int64))   # sorted: by row, then column
+    r, c = key // n, key % n
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    row_ptr[1:] = torch.cumsum(torch.bincount(r, minlength=n), 0)
+    return row_ptr.to(torch.int32), c.to(torch.int32)
 
 
 def make_preconditioner(row_ptr, col, val, **params):
