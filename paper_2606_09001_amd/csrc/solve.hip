@@ -654,37 +654,50 @@ __global__ void __launch_bounds__(kBlock) k_bi_init(int n, const double* __restr
   publish_partials<1>(d, partials);
 }
 
-// p = r on the first iteration of a (re)start, else p = r + beta (p - omega v).
+// p = r on the first iteration of a (re)start, else p = r + beta (p - omega v);
+// with x0, also the next V-cycle's level-0 pre-smoothed iterate x0 = sw o p
+// (cycle precision T), so that its first sweep only forms the residual.
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_bi_dir(int n, const double* __restrict__ r,
                                                    const double* __restrict__ v, double* __restrict__ p,
+                                                   const T* __restrict__ sw, T* __restrict__ x0,
                                                    const Ctl* __restrict__ ctl, int first) {
   if (ctl->done) return;
   const double beta = ctl->beta, omega = ctl->omega;
   const int base = vec_base();
   double rv[kVecPer], vv[kVecPer], pv[kVecPer];
+  T wv[kVecPer];
 #pragma unroll
   for (int u = 0; u < kVecPer; ++u) {
     const int i = min(base + (int)threadIdx.x + u * kBlock, n - 1);
     rv[u] = r[i];
     vv[u] = v[i];
     pv[u] = p[i];
+    wv[u] = x0 ? sw[i] : (T)0;
   }
 #pragma unroll
   for (int u = 0; u < kVecPer; ++u) {
     const int i = base + threadIdx.x + u * kBlock;
-    if (i < n) p[i] = first ? rv[u] : rv[u] + beta * (pv[u] - omega * vv[u]);
+    if (i < n) {
+      const double pi = first ? rv[u] : rv[u] + beta * (pv[u] - omega * vv[u]);
+      p[i] = pi;
+      if (x0) x0[i] = wv[u] * (T)pi;
+    }
   }
 }
 
-// x += alpha y ; s = r - alpha v ; partial <s, s>.
+// x += alpha y ; s = r - alpha v ; partial <s, s>; with x0 also x0 = sw o s.
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_bi_half(int n, double* __restrict__ x, const double* __restrict__ y,
                                                     const double* __restrict__ r, const double* __restrict__ v,
-                                                    double* __restrict__ sv, const Ctl* __restrict__ ctl,
+                                                    double* __restrict__ sv, const T* __restrict__ sw,
+                                                    T* __restrict__ x0, const Ctl* __restrict__ ctl,
                                                     double* __restrict__ partials) {
   if (ctl->done) return;
   const double alpha = ctl->alpha;
   const int base = vec_base();
   double xv[kVecPer], yv[kVecPer], rv[kVecPer], vv[kVecPer];
+  T wv[kVecPer];
 #pragma unroll
   for (int u = 0; u < kVecPer; ++u) {
     const int i = min(base + (int)threadIdx.x + u * kBlock, n - 1);
@@ -692,6 +705,7 @@ __global__ void __launch_bounds__(kBlock) k_bi_half(int n, double* __restrict__ 
     yv[u] = y[i];
     rv[u] = r[i];
     vv[u] = v[i];
+    wv[u] = x0 ? sw[i] : (T)0;
   }
   double d[1] = {0.0};
 #pragma unroll
@@ -701,6 +715,7 @@ __global__ void __launch_bounds__(kBlock) k_bi_half(int n, double* __restrict__ 
       x[i] = xv[u] + alpha * yv[u];
       const double si = rv[u] - alpha * vv[u];
       sv[i] = si;
+      if (x0) x0[i] = wv[u] * (T)si;
       d[0] += si * si;
     }
   }
@@ -1890,18 +1905,39 @@ amg_status bicgstab_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, d
   hipLaunchKernelGGL(k_bi_init, dim3(gv), dim3(kBlock), 0, s, n, d_b, r, rh, d_x, part);
   hipLaunchKernelGGL(k_bfin_init, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv, tol, o.maxiter);
   AMG_HIP(hipGetLastError());
+  // with a multilevel cycle the vector kernels also write the level-0
+  // pre-smoothed iterate of the V-cycle that follows them
+  const bool x0w = prec && H.lv.size() > 1;
+  auto launch_dir = [&](int first, hipStream_t st) {
+    Level& L0c = H.lv[0];
+    if (H.fp32())
+      hipLaunchKernelGGL(k_bi_dir<float>, dim3(gv), dim3(kBlock), 0, st, n, r, v, p, Bufs<float>::sw(L0c),
+                         x0w ? Bufs<float>::x(L0c) : nullptr, ctl, first);
+    else
+      hipLaunchKernelGGL(k_bi_dir<double>, dim3(gv), dim3(kBlock), 0, st, n, r, v, p, Bufs<double>::sw(L0c),
+                         x0w ? Bufs<double>::x(L0c) : nullptr, ctl, first);
+  };
+  auto launch_half = [&](hipStream_t st) {
+    Level& L0c = H.lv[0];
+    if (H.fp32())
+      hipLaunchKernelGGL(k_bi_half<float>, dim3(gv), dim3(kBlock), 0, st, n, d_x, y, r, v, sv, Bufs<float>::sw(L0c),
+                         x0w ? Bufs<float>::x(L0c) : nullptr, ctl, part);
+    else
+      hipLaunchKernelGGL(k_bi_half<double>, dim3(gv), dim3(kBlock), 0, st, n, d_x, y, r, v, sv,
+                         Bufs<double>::sw(L0c), x0w ? Bufs<double>::x(L0c) : nullptr, ctl, part);
+  };
   auto iteration = [&](int first, hipStream_t st) {
-    hipLaunchKernelGGL(k_bi_dir, dim3(gv), dim3(kBlock), 0, st, n, r, v, p, ctl, first);
-    if (prec) vcycle(H, CycleArgs{p, y, nullptr, ctl, part, 0, 0, 0}, st);
+    launch_dir(first, st);
+    if (prec) vcycle(H, CycleArgs{p, y, nullptr, ctl, part, 0, 0, x0w ? 1 : 0}, st);
     int np;
     {
       InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
       np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpSpmvDots<1>{L0.av(), y, v, rh}, ctl, part, st);
     }
     hipLaunchKernelGGL(k_bfin_alpha, dim3(1), dim3(kFinBlock), 0, st, ctl, part, np);
-    hipLaunchKernelGGL(k_bi_half, dim3(gv), dim3(kBlock), 0, st, n, d_x, y, r, v, sv, ctl, part);
+    launch_half(st);
     hipLaunchKernelGGL(k_bfin_half, dim3(1), dim3(kFinBlock), 0, st, ctl, part, gv);
-    if (prec) vcycle(H, CycleArgs{sv, z, nullptr, ctl, part, 0, 0, 0}, st);
+    if (prec) vcycle(H, CycleArgs{sv, z, nullptr, ctl, part, 0, 0, x0w ? 1 : 0}, st);
     {
       InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
       np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpSpmvDots<2>{L0.av(), z, t, sv}, ctl, part, st);
