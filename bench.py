@@ -67,6 +67,12 @@ FINE_KERNELS = {  # tag -> (regex on the demangled name); level 0 = the largest 
     "pre_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpResid<double, double> >",
     "post_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpPost<double, double, double, 1> >",
 }
+BICG_KERNELS = {  # the BiCGSTAB solve's level-0 sweeps (FP64 cycle)
+    "A_y_dot_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpSpmvDots<1> >",
+    "A_z_dots_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpSpmvDots<2> >",
+    "pre_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpResid<double, double> >",
+    "post_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpPost<double, double, double, 0> >",
+}
 
 
 def _csv_rows(d, suffix):
@@ -112,7 +118,8 @@ def summarize_profiles(a):
                      f"{float(r['MinNs']) / 1e3:8.2f} {float(r['MaxNs']) / 1e3:8.2f}  {r['Name'][:150]}")
     lines += ["", "level-0 sweeps, FP64 solve (largest grid of each kernel; working dispatches only):"]
     summary = {}
-    for k, pat in FINE_KERNELS.items():
+    table = BICG_KERNELS if "bicgstab" in tag else FINE_KERNELS
+    for k, pat in table.items():
         sel = _level0(trace, pat, "Grid_Size_X")
         durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
         w = _working(durs)
@@ -651,6 +658,8 @@ def main():
     ap.add_argument("--diffusion-only", action="store_true",
                     help="only the 192^3 diffusion workload (with the counter calibration kernel); for profiling")
     ap.add_argument("--diffusion-grid", type=int, default=192)
+    ap.add_argument("--nonsym-only", action="store_true",
+                    help="only the nonsymmetric BiCGSTAB and matrix-free workloads; for profiling")
     ap.add_argument("--nonsym-grid", type=int, default=128)
     ap.add_argument("--summarize-profiles", action="store_true",
                     help="write profiles/ summaries from rocprofv3 output of this script (no GPU)")
@@ -740,6 +749,10 @@ def main():
         log(f"streaming ceilings (2 GiB): read {read_gbs:.0f} GB/s, copy {copy2_gbs:.0f} GB/s (read+write)")
         del a, bcp
         torch.cuda.empty_cache()
+    if args.nonsym_only:
+        print(json.dumps({"nonsymmetric_bicgstab": run_nonsym(args, dev), "matrix_free_assembly": run_matfree(args, dev)}),
+              flush=True)
+        return
     if args.diffusion_only:
         print(json.dumps({"diffusion": run_diffusion(args, dev)}), flush=True)
         return

@@ -57,6 +57,33 @@ def test_nonsymmetric_hierarchy_and_lu_bitexact(case):
     assert np.max(np.abs(invT.T - ref)) <= 1e-10 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("variant", ["theta_0.25", "l1_v22"])
+def test_nonsymmetric_setup_variants(variant):
+    """A strength threshold (edges kept by |a_ij| >= theta sqrt|a_ii a_jj|,
+    then the union with the transpose's) and the L1 smoother with V(2,2) on a
+    nonsymmetric A: hierarchy bit-exact, BiCGSTAB iterates and solutions."""
+    import oracle
+    kw = dict(KW)
+    if variant == "theta_0.25":
+        kw["theta"] = 0.25
+        rp, ci, v = CASES["cd2d_64_recirc"]()
+    else:
+        kw.update(smoother="l1", nu_pre=2, nu_post=2)
+        rp, ci, v = CASES["cd2d_64_dropped"]()
+    n = len(rp) - 1
+    H, O = pair(rp, ci, v, **kw)
+    assert_hierarchy_bitexact(H, O)
+    b = M.rhs_normal(n, 53)
+    x, info = H.solve(dev(b), 1e-10)
+    xo, io = O.bicgstab(b, tol=1e-10)
+    assert info["status"] == 0 and _count_close(info["iters"], io["iters"]), (info, io)
+    assert oracle.rel_residual(rp, ci, v, b, host(x)) <= 1e-10
+    Hk, _ = pair(rp, ci, v, maxiter=3, **kw)
+    xk, _ = Hk.solve(dev(b), 0.0)
+    xok, _ = O.bicgstab(b, tol=0.0, maxiter=3)
+    assert np.linalg.norm(host(xk) - xok) <= 1e-9 * np.linalg.norm(xok)
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_bicgstab_matches_oracle(case):
     rp, ci, v = CASES[case]()
