@@ -503,6 +503,102 @@ __global__ void k_spgemm_cols(int nrows, const int* __restrict__ xrp, const int*
   }
 }
 
+// Row i of C = X Y with one wavefront per row (rows with many candidates,
+// such as R (A P)): the candidate columns (the concatenated rows of Y
+// selected by row i of X) are staged in LDS, bitonic-sorted and the distinct
+// ones counted (COLS = 0, cnt[i]; block nrows writes cnt[nrows] = 0) or
+// written in ascending order (COLS = 1).  Rows with more than kSymCap
+// candidates take the sequential merge of k_spgemm_count / k_spgemm_cols in
+// lane 0.  The result is the same pattern as those kernels'.
+constexpr int kSymCap = 4096;
+
+__device__ inline int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+template <int COLS>
+__global__ void __launch_bounds__(64) k_spgemm_sym_w(int nrows, const int* __restrict__ xrp,
+                                                     const int* __restrict__ xci, const int* __restrict__ yrp,
+                                                     const int* __restrict__ yci, const int* __restrict__ crp,
+                                                     int* __restrict__ out) {
+  __shared__ int sv[kSymCap];
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= nrows) {
+    if (!COLS && i == nrows && lane == 0) out[nrows] = 0;
+    return;
+  }
+  const int a0 = xrp[i], a1 = xrp[i + 1];
+  int total = 0;
+  for (int base = a0; base < a1; base += 64) {
+    const int a = base + lane;
+    int k = 0, len = 0;
+    if (a < a1) {
+      k = xci[a];
+      len = yrp[k + 1] - yrp[k];
+    }
+    const int incl = wave_incl_scan(len);
+    const int off = total + incl - len;
+    if (a < a1 && off + len <= kSymCap)
+      for (int t = 0; t < len; ++t) sv[off + t] = yci[yrp[k] + t];
+    total += __shfl(incl, 63, 64);
+  }
+  if (total > kSymCap) {
+    // sequential k-way merge (lane 0)
+    if (lane != 0) return;
+    int prev = -1, c = 0, pos = COLS ? crp[i] : 0;
+    for (;;) {
+      int nxt = INT_MAX;
+      for (int a = a0; a < a1; ++a) {
+        const int k = xci[a];
+        nxt = min(nxt, next_col(yci, yrp[k], yrp[k + 1], prev));
+      }
+      if (nxt == INT_MAX) break;
+      if (COLS) out[pos++] = nxt;
+      ++c;
+      prev = nxt;
+    }
+    if (!COLS) out[i] = c;
+    return;
+  }
+  int S = 1;
+  while (S < total) S <<= 1;
+  for (int t = total + lane; t < S; t += 64) sv[t] = INT_MAX;
+  __syncthreads();
+  for (int kk = 2; kk <= S; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < S; t += 64) {
+        const int u = t ^ j;
+        if (u > t) {
+          const int x = sv[t], y = sv[u];
+          const bool up = (t & kk) == 0;
+          if ((x > y) == up) {
+            sv[t] = y;
+            sv[u] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  int pos = COLS ? crp[i] : 0, c = 0;
+  for (int t0 = 0; t0 < total; t0 += 64) {
+    const int t = t0 + lane;
+    const bool first = t < total && (t == 0 || sv[t] != sv[t - 1]);
+    const unsigned long long m = __ballot(first);
+    if (COLS && first) out[pos + __popcll(m & ((1ull << lane) - 1ull))] = sv[t];
+    pos += __popcll(m);
+    c += __popcll(m);
+  }
+  if (!COLS && lane == 0) out[i] = c;
+}
+
 // Values of C = X Y in canonical order: for every output column J
 // (ascending), acc = +0.0 and for every k of row i of X in ascending order
 // with y_kJ stored, acc += x_ik * y_kJ (product rounded, then sum rounded).
@@ -1029,8 +1125,8 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     C.n = nc;
     DBuf<int> cnt;
     cnt.alloc(nc + 1);
-    hipLaunchKernelGGL(k_spgemm_count, dim3(grid_for(nc + 1)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p,
-                       cnt.p);
+    hipLaunchKernelGGL(k_spgemm_sym_w<0>, dim3(nc + 1), dim3(64), 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.aprp.p,
+                       Lr.apci.p, (const int*)nullptr, cnt.p);
     C.rp.alloc(nc + 1);
     exclusive_scan(cnt.p, C.rp.p, nc + 1, s);
     C.nnz = read_int(C.rp.p + nc, s);
@@ -1038,8 +1134,8 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     C.v.alloc(C.nnz * S);
   }
   if (symbolic) {
-    // column pattern of the coarse operator (thread per row), values below
-    hipLaunchKernelGGL(k_spgemm_cols, dim3(grid_for(nc)), b, 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p,
+    // column pattern of the coarse operator (wavefront per row), values below
+    hipLaunchKernelGGL(k_spgemm_sym_w<1>, dim3(nc), dim3(64), 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p,
                        C.rp.p, C.ci.p);
     // product maps for the refreshes (8 bytes per term; the budget keeps each
     // map within 128 bytes per fine-level nonzero: about 1.6 GB in all for
