@@ -183,7 +183,7 @@ def csr_equivalent_bytes(name, level, st):
     if level != 0 or name not in ("spmv_dot", "pre", "post"):
         return None
     n, nnz = st["n"][0], st["nnz"][0]
-    vec = {"spmv_dot": 32.0, "pre": 24.0, "post": 32.0}[name] * n
+    vec = {"spmv_dot": 40.0, "pre": 24.0, "post": 32.0}[name] * n
     return 12.0 * nnz + 4.0 * (n + 1) + vec
 
 
@@ -482,6 +482,22 @@ def run_nonsym(args, dev):
             arel = oracle.rel_residual(rpT, ciT, vT, g, lam.cpu().numpy())
             r.update({"adjoint_first_ms": round(first_ms, 1), "adjoint_ms": round(ams, 3),
                       "adjoint_iters": ai["iters"], "adjoint_oracle_rel_resid": arel})
+            # the two product sweeps (v = A y with <r^, v>; t = A z with <s, t>, <t, t>),
+            # timed in-solve; each streams the operator plus one gathered vector,
+            # one row vector and one output: the bytes of the residual sweep
+            H.instrument("spmv_dot", 0)
+            for _ in range(2):
+                H.solve(d[3], args.tol, out=x)
+            ir = H.instrument_read()
+            H.instrument(None)
+            nbytes = H.kernel_bytes("pre", 0)
+            if ir["launches"]:
+                gbs = nbytes / (ir["avg_ms"] * 1e-3) / 1e9
+                r["product_sweep"] = {"avg_us": round(ir["avg_ms"] * 1e3, 2), "launches": ir["launches"],
+                                      "bytes_per_launch": nbytes, "gbs": round(gbs, 1),
+                                      "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+                log(f"nonsym product sweep L0: {ir['avg_ms'] * 1e3:.1f} us, {nbytes / 1e6:.1f} MB -> {gbs:.0f} GB/s "
+                    f"({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
             log(f"nonsym {prec}: adjoint first call (transpose + A^T setup + solve) {first_ms:.1f} ms, "
                 f"warm {ams:.2f} ms, iters {ai['iters']}, true residual {arel:.2e}")
         out[prec] = r

@@ -274,7 +274,7 @@ amg_status amg_export_field(amg_handle h, int level, int field, void* d_dst, siz
 /* ---- measurement (diagnostics; no effect on results) ----
  * Kernel ids for amg_instrument / amg_kernel_bytes. */
 enum {
-  AMG_KERNEL_SPMV_DOT = 0,   /* p = z + beta p, q = A p, <p,q> (level 0, one fused sweep) */
+  AMG_KERNEL_SPMV_DOT = 0,   /* p = z + beta p, q = A z + beta q (= A p), <p,q> (level 0, one fused sweep) */
   AMG_KERNEL_PRE = 1,        /* residual of the pre-smoothed iterate x = sw o b */
   AMG_KERNEL_POST = 2,       /* post-smoothing sweep (level 0: writes z, reduces <r,z>) */
   AMG_KERNEL_RESTRICT = 3,   /* b_{l+1} = R_l r_l */

@@ -68,9 +68,11 @@ inline int round8(int64_t g) {
 //   static constexpr int NRED     number of dot products reduced
 
 // Direction update fused with the product: p' = z + beta p (p' = z on the
-// first iteration of a (re)start), q = A p', <p', q>; p' goes to a second
-// buffer because neighbouring rows still gather the old p.  beta is read
-// from the device control block.
+// first iteration of a (re)start) and q' = A p', <p', q'>.  q' is formed as
+// A z + beta q (the same vector in exact arithmetic, since q = A p), so the
+// sweep gathers z only; p and q are read at the row itself (q is updated in
+// place by the row's own thread).  p' goes to the second direction buffer.
+// beta is read from the device control block.
 struct OpSpmvXpayDev {
   using PT = double;
   static constexpr int NRED = 1;
@@ -82,16 +84,20 @@ struct OpSpmvXpayDev {
   const Ctl* ctl;
   int first;
   struct Row {
-    double pr;
+    double pr, qo, beta;
   };
-  __device__ double dir(int j, double beta) const { return first ? z[j] : z[j] + beta * p[j]; }
-  __device__ PT prod_v(double a, int j) const { return a * dir(j, ctl->beta); }
+  __device__ PT prod_v(double a, int j) const { return a * z[j]; }
   __device__ PT prod(int k, int j) const { return prod_v(v[k], j); }
-  __device__ Row row_in(int row) const { return {dir(row, ctl->beta)}; }
+  __device__ Row row_in(int row) const {
+    if (first) return {z[row], 0.0, 0.0};
+    const double beta = ctl->beta;
+    return {z[row] + beta * p[row], q[row], beta};
+  }
   __device__ void epi(int row, PT s, const Row& a, double* d) const {
     pn[row] = a.pr;
-    q[row] = s;
-    d[0] += a.pr * s;
+    const double qn = first ? s : s + a.beta * a.qo;
+    q[row] = qn;
+    d[0] += a.pr * qn;
   }
 };
 
@@ -1554,8 +1560,9 @@ double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible) {
   const bool has_next = level + 1 < nl;
   const bool next_coarsest = level + 2 == nl;
   switch (kid) {
-    // direction update fused with the product: gathers z and old p, writes new p and q
-    case KID_SPMV_DOT: return MA(8.0) + 32.0 * n;
+    // direction update fused with the product: gathers z, reads old p and q,
+    // writes new p and q
+    case KID_SPMV_DOT: return MA(8.0) + 40.0 * n;
     // residual of the pre-smoothed iterate: reads b, gathers x, writes r
     case KID_PRE: return MA(v) + (bw + 2.0 * v) * n;
     case KID_POST: {
