@@ -277,3 +277,39 @@ def test_nonsymmetric_autograd():
     gref = -(lam[rows] * xr[ci])
     assert np.max(np.abs(host(val.grad) - gref)) <= 1e-8 * np.abs(gref).max()
     assert np.max(np.abs(host(bb.grad) - lam)) <= 1e-8 * np.abs(lam).max()
+
+
+def _tiny_cases():
+    import scipy.sparse as sp
+
+    def csr(A):
+        A = sp.csr_matrix(A)
+        A.sort_indices()
+        return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+    iso = sp.block_diag([sp.diags(np.arange(1, 11) * 1.0), sp.csr_matrix(M.csr_to_dense(*M.poisson(12, 2)))])
+    return {
+        "n1": (csr(np.array([[3.0]])), True),
+        "n2_nonsym": (csr(np.array([[4.0, -1.0], [-2.5, 3.0]])), False),
+        "diag_50": (csr(sp.diags(np.linspace(1, 5, 50))), True),
+        "isolated_rows_plus_poisson": (csr(iso), True),
+    }
+
+
+@pytest.mark.parametrize("name", ["n1", "n2_nonsym", "diag_50", "isolated_rows_plus_poisson"])
+def test_tiny_and_degenerate_systems(name):
+    """One unknown, two unknowns (nonsymmetric), a diagonal matrix (every node
+    isolated: no coarsening) and isolated rows beside a Laplacian (singleton
+    aggregates): hierarchy bit-exact, PCG (symmetric cases) and BiCGSTAB
+    against the oracle."""
+    (rp, ci, v), sym = _tiny_cases()[name]
+    n = len(rp) - 1
+    b = M.rhs_normal(n, 3)
+    runs = [("bicgstab", False)] + ([("pcg", True)] if sym else [])
+    for solver, symflag in runs:
+        H, O = pair(rp, ci, v, max_coarse=8, symmetric=symflag, solver=solver)
+        assert_hierarchy_bitexact(H, O)
+        x, info = H.solve(dev(b), 1e-12)
+        xo, io = (O.pcg(b, tol=1e-12) if solver == "pcg" else O.bicgstab(b, tol=1e-12))
+        assert info["status"] == 0 and io["status"] == 0, (solver, info, io)
+        assert abs(info["iters"] - io["iters"]) <= 1, (solver, info["iters"], io["iters"])
+        assert np.linalg.norm(host(x) - xo) <= 1e-9 * np.linalg.norm(xo), solver
