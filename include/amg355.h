@@ -199,7 +199,7 @@ amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, i
 /* Adjoint solve A^T lambda = g (Eq. (1)) with the same solver, precision and
  * tolerance rule as amg_solve.  symmetric = 1: A's own hierarchy is the
  * hierarchy of A^T and no transpose is formed.  symmetric = 0 (nrhs = 1): the
- * first call forms A^T on the device (stable counting sort by column) and
+ * first call forms A^T on the device (stable radix sort of the entries by column) and
  * sets up its hierarchy with the same parameters; both are kept with the
  * handle and refreshed from A's values after a value update. */
 amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, double tol, int32_t nrhs,
