@@ -504,30 +504,24 @@ __global__ void k_spgemm_cols(int nrows, const int* __restrict__ xrp, const int*
 }
 
 // Row i of C = X Y with one wavefront per row (rows with many candidates,
-// such as R (A P)): the candidate columns (the concatenated rows of Y
-// selected by row i of X) are staged in LDS, bitonic-sorted and the distinct
-// ones counted (COLS = 0, cnt[i]; block nrows writes cnt[nrows] = 0) or
-// written in ascending order (COLS = 1).  Rows with more than kSymCap
-// candidates take the sequential merge of k_spgemm_count / k_spgemm_cols in
-// lane 0.  The result is the same pattern as those kernels'.
-constexpr int kSymCap = 4096;
-
-__device__ inline int wave_incl_scan(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
+// such as R (A P)): every candidate column (the rows of Y selected by row i
+// of X, split across the lanes) is inserted into an LDS hash set (open
+// addressing, linear probing, compare-and-swap), so each distinct column is
+// kept once however many candidates repeat it.  COLS = 0 counts them
+// (cnt[i]; block nrows writes cnt[nrows] = 0); COLS = 1 compacts them and
+// sorts them ascending (a bitonic network across the lanes, or in LDS beyond
+// 64 columns).  A row with more than kSymTab / 2 distinct columns stops
+// inserting and takes the sequential merge of k_spgemm_count /
+// k_spgemm_cols in lane 0.  The result is the same pattern as those kernels'.
+constexpr int kSymTab = 2048;
 
 template <int COLS>
 __global__ void __launch_bounds__(64) k_spgemm_sym_w(int nrows, const int* __restrict__ xrp,
                                                      const int* __restrict__ xci, const int* __restrict__ yrp,
                                                      const int* __restrict__ yci, const int* __restrict__ crp,
                                                      int* __restrict__ out) {
-  __shared__ int sv[kSymCap];
+  __shared__ int tab[kSymTab];
+  __shared__ int s_cnt, s_over;
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   if (i >= nrows) {
@@ -535,21 +529,34 @@ __global__ void __launch_bounds__(64) k_spgemm_sym_w(int nrows, const int* __res
     return;
   }
   const int a0 = xrp[i], a1 = xrp[i + 1];
-  int total = 0;
-  for (int base = a0; base < a1; base += 64) {
-    const int a = base + lane;
-    int k = 0, len = 0;
-    if (a < a1) {
-      k = xci[a];
-      len = yrp[k + 1] - yrp[k];
-    }
-    const int incl = wave_incl_scan(len);
-    const int off = total + incl - len;
-    if (a < a1 && off + len <= kSymCap)
-      for (int t = 0; t < len; ++t) sv[off + t] = yci[yrp[k] + t];
-    total += __shfl(incl, 63, 64);
+  for (int t = lane; t < kSymTab; t += 64) tab[t] = -1;
+  if (lane == 0) {
+    s_cnt = 0;
+    s_over = 0;
   }
-  if (total > kSymCap) {
+  __syncthreads();
+  // inserts stop once kSymTab / 2 distinct columns are in; a lane already
+  // probing adds at most one more, so the table never fills and every probe
+  // sequence ends
+  for (int a = a0 + lane; a < a1; a += 64) {
+    const int k = xci[a];
+    for (int q = yrp[k]; q < yrp[k + 1]; ++q) {
+      if (__hip_atomic_load(&s_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+      const int c = yci[q];
+      unsigned h = ((unsigned)c * 2654435761u) & (kSymTab - 1);
+      for (;;) {
+        const int old = atomicCAS(&tab[h], -1, c);
+        if (old == -1) {
+          if (atomicAdd(&s_cnt, 1) + 1 > kSymTab / 2) atomicOr(&s_over, 1);
+          break;
+        }
+        if (old == c) break;
+        h = (h + 1) & (kSymTab - 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (s_over) {
     // sequential k-way merge (lane 0)
     if (lane != 0) return;
     int prev = -1, c = 0, pos = COLS ? crp[i] : 0;
@@ -567,36 +574,60 @@ __global__ void __launch_bounds__(64) k_spgemm_sym_w(int nrows, const int* __res
     if (!COLS) out[i] = c;
     return;
   }
+  const int distinct = s_cnt;
+  if (!COLS) {
+    if (lane == 0) out[i] = distinct;
+    return;
+  }
+  // compact the occupied slots to the front, in place: chunk t0's writes go
+  // below t0 + 64, to slots already read (each chunk is read before it writes)
+  int w = 0;
+  for (int t0 = 0; t0 < kSymTab; t0 += 64) {
+    const int c = tab[t0 + lane];
+    const bool occ = c >= 0;
+    const unsigned long long m = __ballot(occ);
+    const int slot = w + __popcll(m & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (occ) tab[slot] = c;
+    __syncthreads();
+    w += __popcll(m);
+  }
+  const int pos = crp[i];
+  if (distinct <= 64) {
+    // bitonic sort across the lanes (INT_MAX padding sorts last)
+    int v = lane < distinct ? tab[lane] : INT_MAX;
+    for (int kk = 2; kk <= 64; kk <<= 1) {
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        const int o = __shfl_xor(v, j, 64);
+        const bool lower = (lane & j) == 0;
+        const bool up = (lane & kk) == 0;
+        v = (lower == up) ? min(v, o) : max(v, o);
+      }
+    }
+    if (lane < distinct) out[pos + lane] = v;
+    return;
+  }
   int S = 1;
-  while (S < total) S <<= 1;
-  for (int t = total + lane; t < S; t += 64) sv[t] = INT_MAX;
+  while (S < distinct) S <<= 1;
+  for (int t = distinct + lane; t < S; t += 64) tab[t] = INT_MAX;
   __syncthreads();
   for (int kk = 2; kk <= S; kk <<= 1) {
     for (int j = kk >> 1; j > 0; j >>= 1) {
       for (int t = lane; t < S; t += 64) {
         const int u = t ^ j;
         if (u > t) {
-          const int x = sv[t], y = sv[u];
+          const int x = tab[t], y = tab[u];
           const bool up = (t & kk) == 0;
           if ((x > y) == up) {
-            sv[t] = y;
-            sv[u] = x;
+            tab[t] = y;
+            tab[u] = x;
           }
         }
       }
       __syncthreads();
     }
   }
-  int pos = COLS ? crp[i] : 0, c = 0;
-  for (int t0 = 0; t0 < total; t0 += 64) {
-    const int t = t0 + lane;
-    const bool first = t < total && (t == 0 || sv[t] != sv[t - 1]);
-    const unsigned long long m = __ballot(first);
-    if (COLS && first) out[pos + __popcll(m & ((1ull << lane) - 1ull))] = sv[t];
-    pos += __popcll(m);
-    c += __popcll(m);
-  }
-  if (!COLS && lane == 0) out[i] = c;
+  for (int t = lane; t < distinct; t += 64) out[pos + t] = tab[t];
 }
 
 // Values of C = X Y in canonical order: for every output column J
