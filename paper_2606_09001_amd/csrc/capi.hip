@@ -327,9 +327,15 @@ amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, 
   return guarded([&]() -> amg_status {
     if (!d_g || !d_lambda || nrhs != 1 || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
     Hierarchy& H = *h->H;
-    std::lock_guard<std::mutex> lock(g_mu);
-    Hierarchy& T = adjoint_hierarchy(H, stream);
-    amg_status st = bicgstab_solve(T, h->opts, d_g, d_lambda, tol, info, stream);
+    Hierarchy* T;
+    {
+      // the lock covers building or refreshing A^T's hierarchy (shared state
+      // of the cached hierarchy); the solve itself runs outside it, like
+      // amg_solve
+      std::lock_guard<std::mutex> lock(g_mu);
+      T = &adjoint_hierarchy(H, stream);
+    }
+    amg_status st = bicgstab_solve(*T, h->opts, d_g, d_lambda, tol, info, stream);
     if (info) {
       info->cache_event = H.cache_event;
       info->setup_ms = H.setup_ms;
