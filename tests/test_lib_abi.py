@@ -90,3 +90,21 @@ def test_make_params_overrides():
     assert p.solver == 1 and p.symmetric == 0
     with pytest.raises(TypeError):
         make_params(bogus=1)
+
+
+def test_matrix_free_entry_points_reject_bad_arguments_before_touching_a_device():
+    from paper_2606_09001_amd import _lib
+    L = _lib.load()
+    nc = C.c_int32(0)
+    E = _lib.AMG_ERR_INVALID_ARG
+    assert L.amg_color_columns(0, 0, 1, 1, 1, C.byref(nc), None) == E          # n <= 0
+    assert L.amg_color_columns(4, 3, 1, 1, 1, C.byref(nc), None) == E          # nnz < n
+    assert L.amg_color_columns(4, 4, None, 1, 1, C.byref(nc), None) == E       # null row_ptr
+    assert L.amg_color_columns(4, 4, 1, 1, 1, None, None) == E                 # null ncolors
+    assert L.amg_probe_vectors(4, 1, 0, 1, None) == E                          # ncolors <= 0
+    assert L.amg_probe_vectors(4, None, 2, 1, None) == E
+    assert L.amg_probe_assemble(4, 4, 1, 1, 1, 0, 1, 1, None) == E             # ncolors <= 0
+    assert L.amg_probe_assemble(4, 4, 1, 1, 1, 2, None, 1, None) == E          # null Y
+    assert L.amg_probe_scatter(4, 4, 1, 1, 1, 2, 1, None, None) == E           # null dY
+    assert L.amg_probe_scatter(-1, 4, 1, 1, 1, 2, 1, 1, None) == E
+    assert L.amg_solve_adjoint(None, 1, 1, 1e-8, 1, None, None) == E
