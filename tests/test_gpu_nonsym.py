@@ -313,3 +313,40 @@ def test_tiny_and_degenerate_systems(name):
         assert info["status"] == 0 and io["status"] == 0, (solver, info, io)
         assert abs(info["iters"] - io["iters"]) <= 1, (solver, info["iters"], io["iters"])
         assert np.linalg.norm(host(x) - xo) <= 1e-9 * np.linalg.norm(xo), solver
+
+
+def test_bicgstab_autotuned_refreshed_and_fp32_graphs():
+    """BiCGSTAB with autotuned sweep shapes, after a value refresh (forward
+    solve), and with the FP32 cycle replayed from captured iterations against
+    direct launches."""
+    import oracle
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    rp, ci, v = CASES["cd3d_24_recirc"]()
+    n = len(rp) - 1
+    b = M.rhs_normal(n, 54)
+    O = oracle.OracleHierarchy(rp, ci, v, symmetric=False, max_coarse=64)
+    # autotuned shapes: same hierarchy, solution within the FP64 bar
+    Ht = AmgHierarchy(dev(rp), dev(ci), dev(v), autotune=1, **KW)
+    x, info = Ht.solve(dev(b), 1e-10)
+    xo, io = O.bicgstab(b, tol=1e-10)
+    assert info["status"] == 0 and _count_close(info["iters"], io["iters"])
+    assert np.linalg.norm(host(x) - xo) <= 1e-9 * np.linalg.norm(xo)
+    # value refresh, then a forward solve against the refreshed oracle
+    v2 = v * (1.0 + 0.15 * np.random.default_rng(12).random(len(v)))
+    Ht.update_values(dev(v2))
+    O.update_values(v2)
+    x2, i2 = Ht.solve(dev(b), 1e-10)
+    xo2, io2 = O.bicgstab(b, tol=1e-10)
+    assert i2["status"] == 0 and i2["cache_event"] == 2 and _count_close(i2["iters"], io2["iters"])
+    assert np.linalg.norm(host(x2) - xo2) <= 1e-9 * np.linalg.norm(xo2)
+    assert oracle.rel_residual(rp, ci, v2, b, host(x2)) <= 1e-10
+    # FP32 cycle: captured iterations equal direct launches bit for bit
+    Hg = AmgHierarchy(dev(rp), dev(ci), dev(v), vcycle_prec="fp32", use_graphs=1, check_every=2, **KW)
+    He = AmgHierarchy(dev(rp), dev(ci), dev(v), vcycle_prec="fp32", use_graphs=0, check_every=2, **KW)
+    for seed in (55, 56):
+        bb = dev(M.rhs_normal(n, seed))
+        xe, ie = He.solve(bb, 1e-9)
+        torch.randn(1 << 18, device="cuda", dtype=torch.float64).sum()
+        xg, ig = Hg.solve(bb, 1e-9)
+        torch.cuda.synchronize()
+        assert ie["iters"] == ig["iters"] and ig["status"] == 0 and torch.equal(xe, xg)
