@@ -26,3 +26,13 @@ def gpu_available():
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _hip_library_built():
+    """Build libamg355.so in-tree when it is absent (a fresh checkout); an
+    existing build is used as it is."""
+    from paper_2606_09001_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2606_09001_amd.csrc import build
+        build.build()
