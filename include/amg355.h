@@ -176,7 +176,9 @@ amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stre
 
 /* Solve A X = B from X0 = 0 with the handle's solver.
  *
- * AMG_SOLVER_BICGSTAB (nrhs = 1, one system): right-preconditioned BiCGSTAB
+ * AMG_SOLVER_BICGSTAB (one system; nrhs > 1 columns of a row-major block
+ * are solved one after another, with per-column outcomes in
+ * amg_solve_columns and the maximum / worst in info): right-preconditioned BiCGSTAB
  * (y = M^-1 p, v = A y, s = r - alpha v, z = M^-1 s, t = A z), shadow residual
  * r^ = b, scalars formed on the device.  Stops when the recursive ||s||_2 or
  * ||r||_2 <= tol ||b||_2, verifies the true residual and restarts from it
@@ -198,7 +200,8 @@ amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, i
 
 /* Adjoint solve A^T lambda = g (Eq. (1)) with the same solver, precision and
  * tolerance rule as amg_solve.  symmetric = 1: A's own hierarchy is the
- * hierarchy of A^T and no transpose is formed.  symmetric = 0 (nrhs = 1): the
+ * hierarchy of A^T and no transpose is formed.  symmetric = 0 (BiCGSTAB, its
+ * column rule for nrhs > 1): the
  * first call forms A^T on the device (stable radix sort of the entries by column) and
  * sets up its hierarchy with the same parameters; both are kept with the
  * handle and refreshed from A's values after a value update. */

@@ -157,6 +157,66 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Column c of a row-major [n][W] block to a contiguous vector and back.
+__global__ void k_col_get(int n, int W, int c, const double* __restrict__ B, double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = B[(int64_t)i * W + c];
+}
+
+__global__ void k_col_put(int n, int W, int c, const double* __restrict__ v, double* __restrict__ B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) B[(int64_t)i * W + c] = v[i];
+}
+
+// BiCGSTAB for W right-hand sides of one matrix ([n][W] blocks): the columns
+// are solved one after another, each by the single-column solve (the
+// paper's batch support maps the solver over the right-hand sides
+// sequentially, Section 2.2); per-column outcomes go to `rec` for
+// amg_solve_columns, info holds the maximum iteration count and residual and
+// the worst status.
+amg_status bicgstab_columns(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int W,
+                            amg_info* info, hipStream_t s, Batch& rec) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int n = H.n;
+  DBuf<double> bc, xc;
+  bc.alloc(n);
+  xc.alloc(n);
+  const int g = (n + 255) / 256;
+  rec.col_iters.assign(W, 0);
+  rec.col_status.assign(W, AMG_OK);
+  rec.col_relres.assign(W, 0.0);
+  int maxit = 0, restarts = 0;
+  double maxrr = 0.0;
+  amg_status st = AMG_OK;
+  for (int c = 0; c < W; ++c) {
+    hipLaunchKernelGGL(k_col_get, dim3(g), dim3(256), 0, s, n, W, c, d_b, bc.p);
+    AMG_HIP(hipGetLastError());
+    amg_info ci{};
+    const amg_status cs = bicgstab_solve(H, o, bc.p, xc.p, tol, &ci, s);
+    hipLaunchKernelGGL(k_col_put, dim3(g), dim3(256), 0, s, n, W, c, xc.p, d_x);
+    AMG_HIP(hipGetLastError());
+    rec.col_iters[c] = ci.iters;
+    rec.col_status[c] = cs;
+    rec.col_relres[c] = ci.rel_resid;
+    maxit = std::max(maxit, ci.iters);
+    restarts += ci.restarts;
+    if (cs != AMG_ERR_BREAKDOWN) maxrr = std::max(maxrr, ci.rel_resid);
+    if (cs == AMG_ERR_BREAKDOWN) st = AMG_ERR_BREAKDOWN;
+    else if (cs == AMG_NOT_CONVERGED && st == AMG_OK) st = AMG_NOT_CONVERGED;
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = maxit;
+    info->status = st;
+    info->restarts = restarts;
+    info->rel_resid = st == AMG_ERR_BREAKDOWN ? NAN : maxrr;
+    info->cache_event = H.cache_event;
+    info->setup_ms = H.setup_ms;
+    info->solve_ms = ms_since(t0);
+  }
+  return st;
+}
+
 // Hierarchy of A^T for the adjoint of a nonsymmetric A (Eq. (1)): formed on
 // first use with A's parameters, kept with A's hierarchy (not in the cache)
 // and refreshed from A's values when they have changed since.
@@ -311,8 +371,8 @@ amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, i
     Hierarchy& H = *h->H;
     if (H.S > 1 && nrhs != H.S) return AMG_ERR_INVALID_ARG;
     if (H.prm.solver == AMG_SOLVER_BICGSTAB) {
-      if (nrhs != 1) return AMG_ERR_INVALID_ARG;
-      return bicgstab_solve(H, h->opts, d_b, d_x, tol, info, stream);
+      if (nrhs == 1) return bicgstab_solve(H, h->opts, d_b, d_x, tol, info, stream);
+      return bicgstab_columns(H, h->opts, d_b, d_x, tol, nrhs, info, stream, H.bt);
     }
     if (nrhs > 1 || H.S > 1) return pcg_solve_wide(H, h->opts, d_b, d_x, tol, nrhs, info, stream);
     return pcg_solve(H, h->opts, d_b, d_x, tol, nrhs, info, stream);
@@ -325,7 +385,7 @@ amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, 
   // forward solver settings (Eq. (1)).
   if (!h || h->H->prm.symmetric) return amg_solve(h, d_g, d_lambda, tol, nrhs, info, stream);
   return guarded([&]() -> amg_status {
-    if (!d_g || !d_lambda || nrhs != 1 || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
+    if (!d_g || !d_lambda || nrhs < 1 || nrhs > kMaxWidth || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
     Hierarchy& H = *h->H;
     Hierarchy* T;
     {
@@ -335,7 +395,8 @@ amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, 
       std::lock_guard<std::mutex> lock(g_mu);
       T = &adjoint_hierarchy(H, stream);
     }
-    amg_status st = bicgstab_solve(*T, h->opts, d_g, d_lambda, tol, info, stream);
+    amg_status st = nrhs == 1 ? bicgstab_solve(*T, h->opts, d_g, d_lambda, tol, info, stream)
+                              : bicgstab_columns(*T, h->opts, d_g, d_lambda, tol, nrhs, info, stream, H.bt);
     if (info) {
       info->cache_event = H.cache_event;
       info->setup_ms = H.setup_ms;
