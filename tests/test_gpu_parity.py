@@ -275,7 +275,9 @@ def test_autotuned_shapes_keep_parity(tmp_path, monkeypatch):
     import os
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("AMG_TUNE_CACHE", str(cache))
-    rp, ci, v = M.diffusion(np.exp(M.grf(24, 3, seed=5)))
+    # a pattern no other test tunes: choices already in the process's tuning
+    # map are reused without timing (and so without a cache-file write)
+    rp, ci, v = M.diffusion(np.exp(M.grf(22, 3, seed=5)))
     H, O = _solve_parity(rp, ci, v, M.rhs_normal(len(rp) - 1, 3), 1e-10, autotune=1)
     assert_hierarchy_bitexact(H, O)
     assert os.path.exists(cache) and len(cache.read_text().splitlines()) >= 3
