@@ -1123,22 +1123,47 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
                          L.pv.p + sy, S, (int*)nullptr, L.rv.p + sy);
   }
   AMG_HIP(hipGetLastError());
-  // AP = A P
+  // product maps for the refreshes (8 bytes per term; the budget keeps each
+  // map within 128 bytes per fine-level nonzero: about 1.6 GB in all for
+  // the 128^3 Poisson hierarchy)
+  const int64_t budget = std::max<int64_t>(16 * (int64_t)H.lv[0].nnz, 1 << 20);
+  // AP = A P.  Where rows meet many candidate columns (mean row length of A
+  // times that of P at least 64, the coarser levels) the pattern comes from
+  // the wavefront hash kernels and the values from the product map; short
+  // rows take the thread-per-row merge, which forms the values in the same
+  // pass.  Both give the same sorted pattern and the same canonical values.
+  const bool wide_ap = symbolic && (double)L.nnz * (double)L.pnnz >= 64.0 * (double)n * (double)n;
+  bool apmap = false;
   if (symbolic) {
     DBuf<int> cnt;
     cnt.alloc(n + 1);
-    hipLaunchKernelGGL(k_spgemm_count, dim3(grid_for(n + 1)), b, 0, s, n, L.rp.p, L.ci.p, L.prp.p, L.pci.p, cnt.p);
+    if (wide_ap)
+      hipLaunchKernelGGL(k_spgemm_sym_w<0>, dim3(n + 1), dim3(64), 0, s, n, L.rp.p, L.ci.p, L.prp.p, L.pci.p,
+                         (const int*)nullptr, cnt.p);
+    else
+      hipLaunchKernelGGL(k_spgemm_count, dim3(grid_for(n + 1)), b, 0, s, n, L.rp.p, L.ci.p, L.prp.p, L.pci.p, cnt.p);
     L.aprp.alloc(n + 1);
     exclusive_scan(cnt.p, L.aprp.p, n + 1, s);
     L.apnnz = read_int(L.aprp.p + n, s);
     L.apci.alloc(L.apnnz);
     L.apv.alloc(L.apnnz * S);
+    if (wide_ap) {
+      hipLaunchKernelGGL(k_spgemm_sym_w<1>, dim3(n), dim3(64), 0, s, n, L.rp.p, L.ci.p, L.prp.p, L.pci.p,
+                         L.aprp.p, L.apci.p);
+      AMG_HIP(hipGetLastError());
+      apmap = build_product_map(n, L.apnnz, L.aprp.p, L.apci.p, L.rp.p, L.ci.p, L.prp.p, L.pci.p, budget, L.apmo,
+                                L.apm, s);
+      if (!apmap) {
+        L.apmo.release();
+        L.apm.release();
+      }
+    }
   }
   for (int sy = 0; sy < S; ++sy) {
-    if (symbolic && sy == 0)
+    if (symbolic && sy == 0 && !wide_ap)
       hipLaunchKernelGGL(k_spgemm_fill, dim3(grid_for(n)), b, 0, s, n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p,
                          L.pv.p, L.aprp.p, L.apci.p, L.apv.p, S);
-    else if (L.pmaps)
+    else if (symbolic ? apmap : L.pmaps)
       hipLaunchKernelGGL(k_pm_apply, dim3(grid_for(L.apnnz)), b, 0, s, L.apnnz, L.apmo.p, L.apm.p, L.v.p + sy,
                          L.pv.p + sy, L.apv.p + sy, S);
     else
@@ -1168,12 +1193,10 @@ void transfer_and_galerkin(Hierarchy& H, size_t l, bool symbolic, hipStream_t s)
     // column pattern of the coarse operator (wavefront per row), values below
     hipLaunchKernelGGL(k_spgemm_sym_w<1>, dim3(nc), dim3(64), 0, s, nc, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p,
                        C.rp.p, C.ci.p);
-    // product maps for the refreshes (8 bytes per term; the budget keeps each
-    // map within 128 bytes per fine-level nonzero: about 1.6 GB in all for
-    // the 128^3 Poisson hierarchy)
-    const int64_t budget = std::max<int64_t>(16 * (int64_t)H.lv[0].nnz, 1 << 20);
-    Lr.pmaps = build_product_map(n, Lr.apnnz, Lr.aprp.p, Lr.apci.p, Lr.rp.p, Lr.ci.p, Lr.prp.p, Lr.pci.p, budget,
-                                 Lr.apmo, Lr.apm, s) &&
+    // (the wide levels built the map of AP above)
+    Lr.pmaps = (wide_ap ? apmap
+                        : build_product_map(n, Lr.apnnz, Lr.aprp.p, Lr.apci.p, Lr.rp.p, Lr.ci.p, Lr.prp.p, Lr.pci.p,
+                                            budget, Lr.apmo, Lr.apm, s)) &&
                build_product_map(nc, C.nnz, C.rp.p, C.ci.p, Lr.rrp.p, Lr.rci.p, Lr.aprp.p, Lr.apci.p, budget,
                                  Lr.cmo, Lr.cm, s);
     if (!Lr.pmaps) {
