@@ -484,25 +484,6 @@ __global__ void k_spgemm_count(int nrows, const int* __restrict__ xrp, const int
   cnt[i] = c;
 }
 
-// Column pattern of row i of C = X Y (ascending), no values.
-__global__ void k_spgemm_cols(int nrows, const int* __restrict__ xrp, const int* __restrict__ xci,
-                              const int* __restrict__ yrp, const int* __restrict__ yci, const int* __restrict__ crp,
-                              int* __restrict__ cci) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  int pos = crp[i], prev = -1;
-  for (;;) {
-    int nxt = INT_MAX;
-    for (int a = xrp[i]; a < xrp[i + 1]; ++a) {
-      int k = xci[a];
-      nxt = min(nxt, next_col(yci, yrp[k], yrp[k + 1], prev));
-    }
-    if (nxt == INT_MAX) break;
-    cci[pos++] = nxt;
-    prev = nxt;
-  }
-}
-
 // Row i of C = X Y with one wavefront per row (rows with many candidates,
 // such as R (A P)): every candidate column (the rows of Y selected by row i
 // of X, split across the lanes) is inserted into an LDS hash set (open
@@ -511,8 +492,8 @@ __global__ void k_spgemm_cols(int nrows, const int* __restrict__ xrp, const int*
 // (cnt[i]; block nrows writes cnt[nrows] = 0); COLS = 1 compacts them and
 // sorts them ascending (a bitonic network across the lanes, or in LDS beyond
 // 64 columns).  A row with more than kSymTab / 2 distinct columns stops
-// inserting and takes the sequential merge of k_spgemm_count /
-// k_spgemm_cols in lane 0.  The result is the same pattern as those kernels'.
+// inserting and takes the sequential merge of k_spgemm_count in lane 0.
+// The result is the pattern that merge gives (distinct columns, ascending).
 constexpr int kSymTab = 2048;
 
 template <int COLS>
