@@ -768,6 +768,15 @@ int or_export_level(void* h, int l, int* agg, int* A_rp, int* A_ci, double* A_v,
   return OR_OK;
 }
 
+// Smoother weights of level l (n_l entries): omega/a_ii for damped Jacobi,
+// 1/sum_j |a_ij| for L1-Jacobi.
+int or_export_sw(void* h, int l, double* sw) {
+  Hier* H = (Hier*)h;
+  if (l < 0 || l >= (int)H->lv.size()) return OR_ERR_INVALID_ARG;
+  std::copy(H->lv[l].sw.begin(), H->lv[l].sw.end(), sw);
+  return OR_OK;
+}
+
 int or_coarse_factor(void* h, double* Lout) {
   Hier* H = (Hier*)h;
   std::copy(H->L.begin(), H->L.end(), Lout);

@@ -51,6 +51,8 @@ def load():
     L.or_level_sizes.argtypes = [C.c_void_p, C.c_int, np.ctypeslib.ndpointer(dtype=np.int64)]
     L.or_export_level.restype = C.c_int
     L.or_export_level.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 14
+    L.or_export_sw.restype = C.c_int
+    L.or_export_sw.argtypes = [C.c_void_p, C.c_int, _dp]
     L.or_coarse_factor.restype = C.c_int
     L.or_coarse_factor.argtypes = [C.c_void_p, _dp]
     L.or_coarse_pivots.restype = C.c_int
@@ -146,7 +148,8 @@ class OracleHierarchy:
         return dict(n=int(out[0]), nnz=int(out[1]), nnzP=int(out[2]), nagg=int(out[3]), nnzG=int(out[4]))
 
     def level(self, l):
-        """All arrays of level l as numpy (P/R/agg empty on the coarsest level)."""
+        """All arrays of level l as numpy (P/R/agg empty on the coarsest level;
+        sw = smoother weights)."""
         s = self.level_sizes(l)
         n, nnz, nnzP, nagg, nnzG = s["n"], s["nnz"], s["nnzP"], s["nagg"], s["nnzG"]
         coarsest = (l == self.num_levels - 1)
@@ -166,6 +169,10 @@ class OracleHierarchy:
                                      _ptr(g("G_ci")), _ptr(scal))
         if st:
             raise OracleError(st, "export_level")
+        out["sw"] = np.zeros(n)
+        st = self._L.or_export_sw(self._h, l, out["sw"])
+        if st:
+            raise OracleError(st, "export_sw")
         out["rho"], out["omegaP"] = float(scal[0]), float(scal[1])
         out["n"], out["nagg"] = n, nagg
         return out

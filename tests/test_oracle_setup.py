@@ -43,16 +43,30 @@ def test_key_function(oracle_mod):
     assert ks[1] >> 32 == 0x514E28B7
 
 
-def _check_aggregation(oracle_mod, rp, ci, v, lvl):
-    G = _A(lvl["G_rp"], lvl["G_ci"], np.ones(len(lvl["G_ci"])))
-    A = _A(rp, ci, v)
-    n = A.shape[0]
-    # strength graph at theta = 0: symmetrised off-diagonal pattern
-    off = A.copy()
-    off.setdiag(0)
-    off.eliminate_zeros()
-    Gref = ((abs(off) + abs(off.T)) > 0).astype(float).tocsr()
+def _strength_reference(rp, ci, v, theta):
+    """Strength graph from its definition: the stored off-diagonal entries
+    with |a_ij| >= theta * sqrt(|a_ii a_jj|) (every one when theta = 0),
+    symmetrised (G union G^T); SciPy CSR with sorted columns."""
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    cols = np.asarray(ci)
+    vals = np.asarray(v)
+    diag = np.zeros(n)
+    on = rows == cols
+    diag[rows[on]] = vals[on]
+    off = ~on
+    if theta > 0.0:
+        off &= np.abs(vals) >= theta * np.sqrt(np.abs(diag[rows] * diag[cols]))
+    S = sp.csr_matrix((np.ones(off.sum()), (rows[off], cols[off])), shape=(n, n))
+    Gref = ((S + S.T) > 0).astype(float).tocsr()
     Gref.sort_indices()
+    return Gref
+
+
+def _check_aggregation(oracle_mod, rp, ci, v, lvl, theta=0.0):
+    G = _A(lvl["G_rp"], lvl["G_ci"], np.ones(len(lvl["G_ci"])))
+    n = len(rp) - 1
+    Gref = _strength_reference(rp, ci, v, theta)
     assert np.array_equal(G.indptr, Gref.indptr) and np.array_equal(G.indices, Gref.indices)
     D = shortest_path(G, unweighted=True, directed=False)
     agg = lvl["agg"]
@@ -129,6 +143,78 @@ def test_aggregation_disconnected_and_isolated(oracle_mod):
     lvl = H.level(0)
     assert lvl["agg"][4] not in np.delete(lvl["agg"], 4)   # isolated node is its own aggregate
     _check_aggregation(oracle_mod, A.indptr, A.indices, A.data, lvl)
+
+
+def _random_mixed_sign(n, p, seed):
+    """Random matrix with a symmetric pattern whose off-diagonal values have
+    both signs and unequal magnitudes at (i, j) and (j, i); strictly
+    diagonally dominant with a positive diagonal."""
+    rng = np.random.default_rng(seed)
+    U = sp.random(n, n, density=p, random_state=rng, format="csr")
+    pat = ((U + U.T) != 0).tocoo()
+    keep = pat.row != pat.col
+    rows, cols = pat.row[keep], pat.col[keep]
+    vals = rng.uniform(0.05, 1.0, len(rows)) * rng.choice([-1.0, 1.0], len(rows))
+    O = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A = (O + sp.diags(np.asarray(abs(O).sum(axis=1)).ravel() + 0.5)).tocsr()
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+def _theta_cases():
+    h = 1.0 / 17
+    return {
+        # |a_ij| = 1 = 0.25 sqrt(4 * 4) exactly: the tie keeps every edge
+        "poisson_tie": (M.poisson(8, 2), 0.25, True),
+        "lognormal": (M.diffusion(np.exp(M.grf(16, 2, seed=3))), 0.25, True),
+        # upwind: a_ij and a_ji differ, the symmetrisation decides the x edges and
+        # theta = 0.35 drops the y edges both ways
+        "upwind": (M.convection_diffusion(16, 2, (40.0, 20.0)), 0.35, False),
+        "recirculating": (M.convection_diffusion(16, 2, M.recirculating_wind(16, 2, 120.0)), 0.3, False),
+        "mixed_sign": (_random_mixed_sign(80, 0.08, 11), 0.1, False),
+    }
+
+
+@pytest.mark.parametrize("case", list(_theta_cases()))
+def test_strength_graph_theta_definition(oracle_mod, case):
+    """theta > 0: on every level, the strength graph equals the mask
+    |a_ij| >= theta sqrt(|a_ii a_jj|) of the level's matrix, symmetrised, and
+    the aggregates are the decreasing-key distance-2 MIS aggregation of that
+    graph (brute force)."""
+    (rp, ci, v), theta, symmetric = _theta_cases()[case]
+    H = oracle_mod.OracleHierarchy(rp, ci, v, theta=theta, max_coarse=4, symmetric=symmetric)
+    assert H.num_levels >= 2
+    for l in range(H.num_levels - 1):
+        lvl = H.level(l)
+        _check_aggregation(oracle_mod, lvl["A_rp"], lvl["A_ci"], lvl["A_v"], lvl, theta=theta)
+    G0 = H.level(0)
+    nG, n = len(G0["G_ci"]), len(rp) - 1
+    nfull = len(ci) - n
+    if case == "poisson_tie":
+        assert nG == nfull
+    else:
+        assert 0 < nG < nfull      # the threshold removes some edges and keeps others
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "l1"])
+@pytest.mark.parametrize("case", ["diffusion3", "mixed_sign"])
+def test_smoother_weights_definition(oracle_mod, smoother, case):
+    """Smoother weights on every level: damped Jacobi omega / a_ii; L1-Jacobi
+    1 / sum_j |a_ij| (Baker, Falgout, Kolev, Yang 2011), which ignores omega."""
+    if case == "diffusion3":
+        rp, ci, v = M.diffusion(np.exp(M.grf(10, 3, seed=5)))
+        sym = True
+    else:
+        rp, ci, v = _random_mixed_sign(90, 0.07, 4)
+        sym = False
+    omega = 0.6
+    H = oracle_mod.OracleHierarchy(rp, ci, v, smoother=smoother, omega=omega, max_coarse=8, symmetric=sym)
+    assert H.num_levels >= 2
+    for l in range(H.num_levels):
+        o = H.level(l)
+        A = _A(o["A_rp"], o["A_ci"], o["A_v"]).toarray()
+        ref = omega / np.diag(A) if smoother == "jacobi" else 1.0 / np.abs(A).sum(axis=1)
+        assert np.allclose(o["sw"], ref, rtol=1e-15, atol=0.0), (l, np.max(np.abs(o["sw"] / ref - 1)))
 
 
 def _dense_P(A, agg, nagg, omegaP):

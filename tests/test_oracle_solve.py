@@ -67,6 +67,45 @@ def test_two_level_closed_form(oracle_mod):
     assert np.max(np.abs(B - Bref)) <= 1e-11 * np.abs(Bref).max()
 
 
+def _closed_form_cycle(O, smoother, omega, nu_pre, nu_post):
+    """Dense V(nu_pre, nu_post) preconditioner from its error propagator, built
+    from the coarsest level up: B_L = A_L^-1 and
+    I - B_l A_l = (I - S_l A_l)^nu_post (I - P_l B_{l+1} P_l^T A_l) (I - S_l A_l)^nu_pre
+    with S_l = diag(omega / a_ii) (damped Jacobi) or diag(1 / sum_j |a_ij|) (L1)."""
+    lv = [O.level(l) for l in range(O.num_levels)]
+    A = [_A(o["A_rp"], o["A_ci"], o["A_v"]).toarray() for o in lv]
+    B = np.linalg.inv(A[-1])
+    for l in range(len(lv) - 2, -1, -1):
+        n, nagg, Al = lv[l]["n"], lv[l]["nagg"], A[l]
+        P = sp.csr_matrix((lv[l]["P_v"], lv[l]["P_ci"], lv[l]["P_rp"]), shape=(n, nagg)).toarray()
+        s = omega / np.diag(Al) if smoother == "jacobi" else 1.0 / np.abs(Al).sum(axis=1)
+        I = np.eye(n)
+        Sm = I - s[:, None] * Al
+        E = np.linalg.matrix_power(Sm, nu_post) @ (I - P @ B @ P.T @ Al) @ np.linalg.matrix_power(Sm, nu_pre)
+        B = (I - E) @ np.linalg.inv(Al)
+    return B
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "l1"])
+@pytest.mark.parametrize("nu", [(1, 1), (2, 2), (2, 3), (3, 1)])
+def test_multilevel_cycle_closed_form(oracle_mod, smoother, nu):
+    """The recursive V(nu_pre, nu_post) cycle with either smoother equals the
+    composition of its smoothing and coarse-correction error propagators on a
+    hierarchy of at least three levels."""
+    N = 12
+    rp, ci, v = M.diffusion(np.exp(M.grf(N, 2, seed=9)))
+    omega = 0.6
+    H = oracle_mod.OracleHierarchy(rp, ci, v, max_coarse=12, smoother=smoother, omega=omega, nu_pre=nu[0],
+                                   nu_post=nu[1])
+    assert H.num_levels >= 3
+    Bref = _closed_form_cycle(H, smoother, omega, *nu)
+    B = _dense_prec(H, N * N)
+    assert np.max(np.abs(B - Bref)) <= 1e-11 * np.abs(Bref).max()
+    if nu[0] != nu[1]:
+        # unequal sweep counts: not a symmetric preconditioner
+        assert np.max(np.abs(B - B.T)) > 1e-6 * np.abs(B).max()
+
+
 def test_single_level_is_direct_solve(oracle_mod):
     rp, ci, v = M.poisson(10, 2)       # 100 <= max_coarse: the V-cycle is the Cholesky solve
     H = oracle_mod.OracleHierarchy(rp, ci, v)
