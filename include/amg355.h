@@ -79,7 +79,8 @@ typedef struct {
   double omega;        /* Jacobi damping (default 2/3) */
   int nu_pre, nu_post; /* sweeps before/after the coarse correction (default 1, 1) */
   int maxiter;         /* Krylov iteration limit (default 1000) */
-  int flexible;        /* -1 (default): flexible beta iff the cycle is not FP64; 0 standard; 1 flexible */
+  int flexible;        /* -1 (default): flexible beta iff the cycle is not FP64 or nu_pre != nu_post (the
+                          preconditioner is then not a fixed symmetric operator); 0 standard; 1 flexible */
   int symmetric;       /* 1 (default): A = A^T, the adjoint reuses A's hierarchy and the coarsest level
                           gets a Cholesky factorization.  0: A may be nonsymmetric (needs
                           solver = AMG_SOLVER_BICGSTAB): LU with partial pivoting on the coarsest level;
@@ -147,7 +148,10 @@ typedef enum {
   AMG_FIELD_COARSE_INV = 17,    /* float64[m*m] inverse of the coarsest A, transposed (entry (j, i) holds
                                    (A^-1)_ij; equal to the inverse when A is symmetric) */
   AMG_FIELD_DINV32 = 18,   /* float32[n_l] smoother weights of the FP32 cycle */
-  AMG_FIELD_COARSE_PIVOTS = 19  /* int32[m] nonsymmetric only: row exchanged with row k at LU step k */
+  AMG_FIELD_COARSE_PIVOTS = 19, /* int32[m] nonsymmetric only: row exchanged with row k at LU step k */
+  AMG_FIELD_SW = 20,            /* float64[n_l] smoother weights: omega/a_ii (damped Jacobi) or
+                                   1/sum_j |a_ij| (L1-Jacobi) */
+  AMG_FIELD_COARSE_INV32 = 21   /* float32[m*m] FP32 cycle: AMG_FIELD_COARSE_INV rounded to nearest even */
 } amg_field;
 
 /* Fills *p with the defaults listed above. */
@@ -160,8 +164,14 @@ void amg_params_default(amg_params* p);
  * smoothed prolongator, R = P^T, Galerkin R A P per level, inverse
  * diagonals, coarse factorization).  Hit with identical values: the cached
  * hierarchy is returned.  Hit with new values: the values are refreshed in
- * place (aggregates and all patterns kept).  The handle holds one reference
- * (release with amg_destroy); the cache holds another.
+ * place (aggregates and all patterns kept; with theta > 0 the strength graph
+ * depends on the values, so the hierarchy is set up again from the pattern)
+ * when no other caller's handle holds the hierarchy; when one does, that
+ * hierarchy is left unchanged for it and a new one is built for the new
+ * values and takes its place in the cache (copy on write).  A refresh that
+ * fails part-way (AMG_ERR_ZERO_DIAG, AMG_ERR_BREAKDOWN, ...) drops the
+ * hierarchy from the cache.  The handle holds one reference (release with
+ * amg_destroy); the cache holds another.
  * n_systems = S >= 1 (at most 64): S systems share the pattern and d_val
  * holds their values interleaved, entry k of system s at [k*S + s]; the
  * aggregation is pattern-only (theta must be 0) and each system gets its own
@@ -171,7 +181,13 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
                      amg_handle* out);
 
 /* Value refresh on the same pattern: recomputes every value of the hierarchy
- * from d_val (nnz entries) and keeps aggregates and patterns. */
+ * from d_val (nnz entries) and keeps aggregates and patterns (theta > 0: sets
+ * the hierarchy up again from the pattern).  In place when no other caller's
+ * handle shares the hierarchy; otherwise this handle gets a hierarchy of its
+ * own for the new values and the others keep theirs.  If the refresh fails
+ * part-way, its status is returned, the hierarchy leaves the cache, and
+ * amg_solve / amg_solve_adjoint / amg_apply_vcycle on it return that status
+ * until a later amg_update_values succeeds. */
 amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stream);
 
 /* Solve A X = B from X0 = 0 with the handle's solver.
@@ -315,6 +331,14 @@ amg_status amg_finalize(void);
 /* Number of hierarchies currently in the cache; capacity setter (default 8). */
 int amg_cache_size(void);
 amg_status amg_set_cache_capacity(int capacity);
+
+/* The rounding of the bf16-stored transfer operators of the FP32 cycle
+ * (Section 2.2 single precision; storage only): d_out[i] = the bfloat16
+ * nearest to d_in[i], ties to even; every NaN becomes the quiet NaN 0x7fc0.
+ * d_in: float32[n], d_out: uint16[n] (bfloat16 bit patterns), both device
+ * pointers owned by the caller; n = 0 writes nothing.  Stream-ordered, no
+ * synchronisation. */
+amg_status amg_convert_bf16(const float* d_in, uint16_t* d_out, int64_t n, hipStream_t stream);
 
 /* Human-readable name of a status. */
 const char* amg_status_string(amg_status s);

@@ -724,12 +724,20 @@ void* or_setup(int n, const int* rp, const int* ci, const double* v, double thet
   return H;
 }
 
+// New values on the same pattern.  theta == 0: the strength graph is A's
+// pattern, so aggregates and patterns are kept and only the values of every
+// level are recomputed.  theta > 0: the strength graph depends on the values,
+// so the whole hierarchy is built again (it never depends on earlier values).
 int or_update_values(void* h, const double* v) {
   Hier* H = (Hier*)h;
   Csr& A = H->lv[0].A;
   std::copy(v, v + A.nnz(), A.v.begin());
   for (int i = 0; i < A.nrows; ++i)
     if (diag_of(A, i) == 0.0) return OR_ERR_ZERO_DIAG;
+  if (H->prm.theta > 0.0) {
+    H->lv.resize(1);
+    return build_levels(*H, false);
+  }
   return build_levels(*H, true);
 }
 

@@ -32,7 +32,7 @@ AMG_MAX_LEVELS = 20
 FIELDS = {
     "agg": 0, "A_rp": 1, "A_ci": 2, "A_v": 3, "A_v32": 4, "dinv": 5, "P_rp": 6, "P_ci": 7, "P_v": 8,
     "P_bf16": 9, "R_rp": 10, "R_ci": 11, "R_v": 12, "R_bf16": 13, "G_rp": 14, "G_ci": 15,
-    "coarse_factor": 16, "coarse_inv": 17, "sw32": 18, "coarse_pivots": 19,
+    "coarse_factor": 16, "coarse_inv": 17, "sw32": 18, "coarse_pivots": 19, "sw": 20, "coarse_inv32": 21,
 }
 
 EXPORTS = [
@@ -40,7 +40,7 @@ EXPORTS = [
     "amg_apply_vcycle", "amg_hierarchy_stats", "amg_field_info", "amg_export_field", "amg_destroy", "amg_finalize",
     "amg_cache_size", "amg_set_cache_capacity", "amg_status_string", "amg_instrument", "amg_instrument_read",
     "amg_kernel_bytes", "amg_pattern_grad_batched", "amg_solve_columns", "amg_color_columns",
-    "amg_probe_vectors", "amg_probe_assemble", "amg_probe_scatter",
+    "amg_probe_vectors", "amg_probe_assemble", "amg_probe_scatter", "amg_convert_bf16",
 ]
 
 KERNELS = {"spmv_dot": 0, "pre": 1, "post": 2, "restrict": 3, "prolong": 4, "cg_update": 5, "xpay": 6, "coarse": 7}
@@ -125,6 +125,7 @@ def load():
     L.amg_probe_vectors.argtypes = [i32, vp, i32, vp, vp]
     L.amg_probe_assemble.argtypes = [i32, i64, vp, vp, vp, i32, vp, vp, vp]
     L.amg_probe_scatter.argtypes = [i32, i64, vp, vp, vp, i32, vp, vp, vp]
+    L.amg_convert_bf16.argtypes = [vp, vp, i64, vp]
     L.amg_status_string.argtypes = [C.c_int]
     L.amg_status_string.restype = C.c_char_p
     for name in EXPORTS:

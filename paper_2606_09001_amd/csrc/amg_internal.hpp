@@ -265,6 +265,9 @@ struct Hierarchy {
   uint64_t key = 0;
   int refs = 0;
   bool in_cache = false;
+  // status of a value refresh that failed part-way (the levels then hold a
+  // mix of old and new values): solves refuse with it until a refresh succeeds
+  amg_status broken = AMG_OK;
   int cache_event = AMG_CACHE_COLD;
   double setup_ms = 0.0;
   bool fp32() const { return prm.vcycle_prec == AMG_PREC_FP32; }
@@ -288,6 +291,8 @@ uint64_t pattern_hash(int n, int64_t nnz, const int* d_rp, const int* d_ci, int*
                       hipStream_t s);
 bool pattern_equal(const Hierarchy& H, const int* d_rp, const int* d_ci, int* d_flags, int* h_flags, hipStream_t s);
 bool values_equal(const Hierarchy& H, const double* d_val, int* d_flags, int* h_flags, hipStream_t s);
+// float32 -> bfloat16 bits (f32_to_bf16) of n elements.
+void convert_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
 // A^T of the level-0 matrix: pattern (trp, tci) and entry map tperm (entry t
 // of A^T is entry tperm[t] of A), then tval = A's values in that order.
 void transpose_pattern(Hierarchy& H, hipStream_t s);

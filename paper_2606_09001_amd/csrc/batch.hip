@@ -1034,7 +1034,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
   const int n = H.n;
   const int LWv = pow2_ceil(W);
   const bool multi = H.lv.size() > 1;
-  const int flexible = o.flexible < 0 ? (H.fp32() ? 1 : 0) : o.flexible;
+  const int flexible = o.flexible < 0 ? ((H.fp32() || H.prm.nu_pre != H.prm.nu_post) ? 1 : 0) : o.flexible;
   if (!multi) throw Error(AMG_ERR_INVALID_ARG, "batched solves need at least two levels");
   const bool graphs = o.use_graphs != 0;
   hipStream_t s = caller;

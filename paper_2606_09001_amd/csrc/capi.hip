@@ -68,6 +68,16 @@ void release(Hierarchy* H) {
   if (--H->refs <= 0) delete H;
 }
 
+void uncache(Hierarchy* H) {
+  for (auto it = g_lru.begin(); it != g_lru.end(); ++it)
+    if (*it == H) {
+      g_lru.erase(it);
+      H->in_cache = false;
+      release(H);
+      return;
+    }
+}
+
 void evict_to(int cap) {
   while ((int)g_lru.size() > cap) {
     Hierarchy* H = g_lru.back();
@@ -309,9 +319,23 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
       if (values_equal(*H, d_val, g_flags.d, g_flags.h, stream)) {
         H->cache_event = AMG_CACHE_HIT;
         H->setup_ms = ms_since(t0);
+      } else if (H->refs > 1) {
+        // Other callers' handles still hold this hierarchy for its values:
+        // it stays as it is for them, and a hierarchy of the new values is
+        // built below and takes its place in the cache (copy on write).
+        uncache(H);
+        break;
       } else {
+        // only the cache holds it: the values are refreshed in place
         H->gr.reset();
-        refresh_hierarchy(*H, d_val, stream);
+        try {
+          refresh_hierarchy(*H, d_val, stream);
+        } catch (...) {
+          // part-way refreshed: never handed out again
+          (void)hipStreamSynchronize(stream);
+          uncache(H);
+          throw;
+        }
         ++H->val_version;
         H->cache_event = AMG_CACHE_REFRESH;
         H->setup_ms = ms_since(t0);
@@ -355,11 +379,52 @@ amg_status amg_update_values(amg_handle h, const double* d_val, hipStream_t stre
     if (!h || !d_val) return AMG_ERR_INVALID_ARG;
     auto t0 = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lock(g_mu);
-    h->H->gr.reset();
-    refresh_hierarchy(*h->H, d_val, stream);
-    ++h->H->val_version;
-    h->H->cache_event = AMG_CACHE_REFRESH;
-    h->H->setup_ms = ms_since(t0);
+    Hierarchy* H = h->H;
+    if (H->refs - (H->in_cache ? 1 : 0) > 1) {
+      // Another caller's handle shares this hierarchy: this handle gets a
+      // hierarchy of its own for the new values (copy on write, not cached);
+      // the shared one keeps its values.
+      std::unique_ptr<Hierarchy> N(new Hierarchy);
+      N->prm = H->prm;
+      N->S = H->S;
+      N->n = H->n;
+      N->nnz = H->nnz;
+      N->lv.reserve(AMG_MAX_LEVELS + 1);
+      N->flags.alloc(16);
+      AMG_HIP(hipHostMalloc((void**)&N->h_flags, 64, hipHostMallocDefault));
+      try {
+        build_hierarchy(*N, H->lv[0].rp.p, H->lv[0].ci.p, d_val, stream);
+      } catch (...) {
+        (void)hipStreamSynchronize(stream);
+        throw;
+      }
+      N->cache_event = AMG_CACHE_COLD;
+      N->setup_ms = ms_since(t0);
+      N->refs = 1;
+      release(H);
+      h->H = N.release();
+      return AMG_OK;
+    }
+    H->gr.reset();
+    try {
+      refresh_hierarchy(*H, d_val, stream);
+    } catch (const Error& e) {
+      // part-way refreshed: out of the cache, and refused by solves until a
+      // later refresh succeeds
+      (void)hipStreamSynchronize(stream);
+      H->broken = e.status;
+      if (H->in_cache) uncache(H);
+      throw;
+    } catch (...) {
+      (void)hipStreamSynchronize(stream);
+      H->broken = AMG_ERR_HIP;
+      if (H->in_cache) uncache(H);
+      throw;
+    }
+    H->broken = AMG_OK;
+    ++H->val_version;
+    H->cache_event = AMG_CACHE_REFRESH;
+    H->setup_ms = ms_since(t0);
     return AMG_OK;
   });
 }
@@ -369,6 +434,7 @@ amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, i
   return guarded([&]() -> amg_status {
     if (!h || !d_b || !d_x || nrhs < 1 || nrhs > kMaxWidth || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
     Hierarchy& H = *h->H;
+    if (H.broken != AMG_OK) return H.broken;
     if (H.S > 1 && nrhs != H.S) return AMG_ERR_INVALID_ARG;
     if (H.prm.solver == AMG_SOLVER_BICGSTAB) {
       if (nrhs == 1) return bicgstab_solve(H, h->opts, d_b, d_x, tol, info, stream);
@@ -387,6 +453,7 @@ amg_status amg_solve_adjoint(amg_handle h, const double* d_g, double* d_lambda, 
   return guarded([&]() -> amg_status {
     if (!d_g || !d_lambda || nrhs < 1 || nrhs > kMaxWidth || !(tol >= 0.0)) return AMG_ERR_INVALID_ARG;
     Hierarchy& H = *h->H;
+    if (H.broken != AMG_OK) return H.broken;
     Hierarchy* T;
     {
       // the lock covers building or refreshing A^T's hierarchy (shared state
@@ -442,6 +509,7 @@ amg_status amg_solve_columns(amg_handle h, int32_t ncols, int* iters, double* re
 amg_status amg_apply_vcycle(amg_handle h, const double* d_r, double* d_z, hipStream_t stream) {
   return guarded([&]() -> amg_status {
     if (!h || !d_r || !d_z) return AMG_ERR_INVALID_ARG;
+    if (h->H->broken != AMG_OK) return h->H->broken;
     apply_vcycle(*h->H, d_r, d_z, stream);
     return AMG_OK;
   });
@@ -554,6 +622,8 @@ static amg_status field_ptr(const Hierarchy& H, int level, int field, const void
     case AMG_FIELD_G_COL: if (coarsest) return AMG_ERR_INVALID_ARG; *p = L.gci.p; *count = L.gnnz; *eb = 4; break;
     case AMG_FIELD_COARSE_FACTOR: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.L.p; *count = (int64_t)H.co.m * H.co.m * S; *eb = 8; break;
     case AMG_FIELD_COARSE_INV: if (!coarsest) return AMG_ERR_INVALID_ARG; *p = H.co.inv.p; *count = (int64_t)H.co.m * H.co.m * S; *eb = 8; break;
+    case AMG_FIELD_SW: *p = L.sw.p; *count = L.n * S; *eb = 8; break;
+    case AMG_FIELD_COARSE_INV32: if (!coarsest || !H.fp32()) return AMG_ERR_INVALID_ARG; *p = H.co.inv32.p; *count = (int64_t)H.co.m * H.co.m * S; *eb = 4; break;
     case AMG_FIELD_COARSE_PIVOTS: if (!coarsest || H.prm.symmetric) return AMG_ERR_INVALID_ARG; *p = H.co.piv.p; *count = (int64_t)H.co.m * S; *eb = 4; break;
     default: return AMG_ERR_INVALID_ARG;
   }
@@ -643,6 +713,14 @@ amg_status amg_kernel_bytes(amg_handle h, int kernel, int level, int flexible, d
   if (kernel < 0 || kernel >= KID_COUNT || level < 0 || level >= (int)H.lv.size()) return AMG_ERR_INVALID_ARG;
   *bytes = kernel_bytes(H, kernel, level, flexible);
   return AMG_OK;
+}
+
+amg_status amg_convert_bf16(const float* d_in, uint16_t* d_out, int64_t n, hipStream_t stream) {
+  return guarded([&]() -> amg_status {
+    if (n < 0 || (n > 0 && (!d_in || !d_out))) return AMG_ERR_INVALID_ARG;
+    if (n > 0) convert_bf16(d_in, d_out, n, stream);
+    return AMG_OK;
+  });
 }
 
 const char* amg_status_string(amg_status s) {

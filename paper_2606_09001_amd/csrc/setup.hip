@@ -755,6 +755,11 @@ __global__ void k_to_bf16(int64_t m, const double* __restrict__ a, uint16_t* __r
   if (t < m) b[t] = f32_to_bf16((float)a[t]);
 }
 
+__global__ void k_f32_to_bf16(int64_t m, const float* __restrict__ a, uint16_t* __restrict__ b) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m; t += stride) b[t] = f32_to_bf16(a[t]);
+}
+
 // ------------------------------------------------------ sliced copy of A
 
 // Entries per slice of 64 rows: 64 times the slice's longest row.
@@ -1428,6 +1433,12 @@ void transpose_csr_pattern(int n, int64_t nnz, const int* rp, const int* ci, DBu
   AMG_HIP(hipStreamSynchronize(s));
 }
 
+void convert_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s) {
+  const int grid = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 16384);
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid), dim3(kBlock), 0, s, n, in, out);
+  AMG_HIP(hipGetLastError());
+}
+
 // A^T of the level-0 matrix (pattern, entry map, values) for the adjoint of
 // a nonsymmetric A.
 void transpose_pattern(Hierarchy& H, hipStream_t s) {
@@ -1447,6 +1458,20 @@ void transpose_values(Hierarchy& H, hipStream_t s) {
 }
 
 void refresh_hierarchy(Hierarchy& H, const double* d_val, hipStream_t s) {
+  if (H.prm.theta > 0.0) {
+    // With a strength threshold the strength graph, hence the aggregates and
+    // every coarse pattern, depend on the values: the hierarchy is set up
+    // again from the stored pattern, so it never depends on the values it was
+    // first built with.
+    DBuf<int> rp, ci;
+    rp.alloc(H.n + 1);
+    ci.alloc(H.nnz);
+    AMG_HIP(hipMemcpyAsync(rp.p, H.lv[0].rp.p, rp.bytes(), hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipMemcpyAsync(ci.p, H.lv[0].ci.p, ci.bytes(), hipMemcpyDeviceToDevice, s));
+    H.bt.W = 0;  // batched workspaces follow the (possibly different) levels
+    build_hierarchy(H, rp.p, ci.p, d_val, s);
+    return;
+  }
   Level& L0 = H.lv[0];
   AMG_HIP(hipMemcpyAsync(L0.v.p, d_val, L0.v.bytes(), hipMemcpyDeviceToDevice, s));
   for (size_t l = 0; l < H.lv.size(); ++l) {

@@ -1708,7 +1708,9 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
   Level& L0 = H.lv[0];
   const int n = H.n;
   const bool multi = H.lv.size() > 1;
-  const int flexible = o.flexible < 0 ? (H.fp32() ? 1 : 0) : o.flexible;
+  // automatic: flexible whenever the preconditioner is not a fixed symmetric
+  // operator (FP32 cycle, or unequal pre/post sweep counts)
+  const int flexible = o.flexible < 0 ? ((H.fp32() || H.prm.nu_pre != H.prm.nu_post) ? 1 : 0) : o.flexible;
   const bool graphs = o.use_graphs && H.inst.kernel < 0;
   hipStream_t s = caller;
   if (graphs) {

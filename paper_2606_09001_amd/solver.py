@@ -201,7 +201,7 @@ class AmgHierarchy:
         eb = C.c_int(0)
         _lib.check(self._L.amg_field_info(self._h, level, fid, C.byref(count), C.byref(eb)), "amg_field_info")
         dtype = {(4, False): torch.int32, (8, False): torch.float64, (2, False): torch.int16}[(eb.value, False)]
-        if field in ("A_v32", "sw32"):
+        if field in ("A_v32", "sw32", "coarse_inv32"):
             dtype = torch.float32
         t = torch.empty(max(count.value, 1), dtype=dtype, device="cuda")
         _lib.check(self._L.amg_export_field(self._h, level, fid, t.data_ptr(), t.numel() * t.element_size(),

@@ -126,11 +126,12 @@ def test_detect_pattern_by_one_hot_probing():
 
 
 def _tridiag_operator(d):
-    """Section 3.3's Toeplitz tridiagonal operator (d a torch scalar)."""
+    """tridiag(-1, d, -1) with Dirichlet ends as a callable (the operator of
+    Section 3.3; d a torch scalar): y_i = d x_i - x_{i-1} - x_{i+1}, with
+    x_{-1} = x_n = 0."""
     def matvec(x):
-        y = -torch.roll(x, 1) + d * x - torch.roll(x, -1)
-        y = torch.cat([(d * x[0] - x[1]).reshape(1), y[1:-1], (-x[-2] + d * x[-1]).reshape(1)])
-        return y
+        xp = torch.nn.functional.pad(x, (1, 1))
+        return d * x - xp[:-2] - xp[2:]
     return matvec
 
 

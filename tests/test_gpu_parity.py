@@ -74,9 +74,12 @@ def _solve_parity(rp, ci, v, b, tol, **kw):
     z = host(H.apply_vcycle(dev(b)))
     zo = O.vcycle(b)
     assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+    # the GPU's automatic beta is flexible for a cycle that is not a fixed
+    # symmetric operator (unequal sweep counts)
+    flex = kw.get("nu_pre", 1) != kw.get("nu_post", 1)
     # converged solve: counts within one, both meet the tolerance (true FP64 residual)
     x, info = H.solve(dev(b), tol)
-    xo, io = O.pcg(b, tol=tol)
+    xo, io = O.pcg(b, tol=tol, flexible=flex)
     assert info["status"] == 0 and io["status"] == 0
     assert abs(info["iters"] - io["iters"]) <= 1, (info["iters"], io["iters"])
     xg = host(x)
@@ -86,7 +89,7 @@ def _solve_parity(rp, ci, v, b, tol, **kw):
     k = io["iters"]
     Hk, _ = pair(rp, ci, v, maxiter=k, **kw)
     xk, ik = Hk.solve(dev(b), 0.0)
-    xok, iok = O.pcg(b, tol=0.0, maxiter=k)
+    xok, iok = O.pcg(b, tol=0.0, maxiter=k, flexible=flex)
     assert ik["iters"] == k and iok["iters"] == k
     err = np.linalg.norm(host(xk) - xok) / np.linalg.norm(xok)
     assert err <= 1e-9, err
@@ -108,7 +111,9 @@ def test_solve_parity(case):
 def test_solve_parity_deep_and_options():
     rp, ci, v = M.diffusion(np.exp(M.grf(20, 3, seed=6)))
     b = M.rhs_normal(len(rp) - 1, 9)
-    for kw in (dict(max_coarse=10), dict(smoother="l1", max_coarse=10), dict(nu_pre=2, nu_post=2)):
+    for kw in (dict(max_coarse=10), dict(smoother="l1", max_coarse=10), dict(nu_pre=2, nu_post=2),
+               dict(nu_pre=2, nu_post=3, max_coarse=10), dict(smoother="l1", nu_pre=3, nu_post=1),
+               dict(theta=0.08, max_coarse=10)):
         _solve_parity(rp, ci, v, b, 1e-10, **kw)
 
 
@@ -201,7 +206,10 @@ def test_refresh_bitexact_and_cache_events():
     H2 = AmgHierarchy(dev(rp), dev(ci), dev(v1), max_coarse=16)   # same values: hit
     _, info = H2.solve(b, 1e-8)
     assert info["cache_event"] == 1
-    H3 = AmgHierarchy(dev(rp), dev(ci), dev(v2), max_coarse=16)   # new values: in-place refresh
+    H.close()
+    H2.close()
+    # only the cache holds the hierarchy now: new values refresh it in place
+    H3 = AmgHierarchy(dev(rp), dev(ci), dev(v2), max_coarse=16)
     _, info = H3.solve(b, 1e-8)
     assert info["cache_event"] == 2
     O2 = oracle.OracleHierarchy(rp, ci, v2, max_coarse=16)

@@ -108,3 +108,12 @@ def test_matrix_free_entry_points_reject_bad_arguments_before_touching_a_device(
     assert L.amg_probe_scatter(4, 4, 1, 1, 1, 2, 1, None, None) == E           # null dY
     assert L.amg_probe_scatter(-1, 4, 1, 1, 1, 2, 1, 1, None) == E
     assert L.amg_solve_adjoint(None, 1, 1, 1e-8, 1, None, None) == E
+
+
+def test_convert_bf16_rejects_bad_arguments_before_touching_a_device():
+    from paper_2606_09001_amd import _lib
+    L = _lib.load()
+    assert L.amg_convert_bf16(1, 1, -1, None) == _lib.AMG_ERR_INVALID_ARG
+    assert L.amg_convert_bf16(None, 1, 4, None) == _lib.AMG_ERR_INVALID_ARG
+    assert L.amg_convert_bf16(1, None, 4, None) == _lib.AMG_ERR_INVALID_ARG
+    assert L.amg_convert_bf16(None, None, 0, None) == _lib.AMG_OK      # nothing to convert

@@ -118,12 +118,11 @@ def test_assembly_from_probes_is_exact(oracle_mod, name):
 
 
 def _tridiag_operator(d):
-    """Section 3.3's Toeplitz tridiagonal operator as a matrix-free callable."""
+    """tridiag(-1, d, -1) with Dirichlet ends as a callable (the operator of
+    Section 3.3): y_i = d x_i - x_{i-1} - x_{i+1}, with x_{-1} = x_n = 0."""
     def matvec(x):
-        y = -np.roll(x, 1) + d * x - np.roll(x, -1)
-        y[0] = d * x[0] - x[1]
-        y[-1] = -x[-2] + d * x[-1]
-        return y
+        xp = np.concatenate(([0.0], x, [0.0]))
+        return d * x - xp[:-2] - xp[2:]
     return matvec
 
 

@@ -162,7 +162,6 @@ def _random_mixed_sign(n, p, seed):
 
 
 def _theta_cases():
-    h = 1.0 / 17
     return {
         # |a_ij| = 1 = 0.25 sqrt(4 * 4) exactly: the tie keeps every edge
         "poisson_tie": (M.poisson(8, 2), 0.25, True),
@@ -309,15 +308,21 @@ def test_galerkin_poisson_zero_row_sums_interior(oracle_mod):
     assert checked > 0
 
 
-def test_refresh_equals_fresh_setup(oracle_mod):
+@pytest.mark.parametrize("theta", [0.0, 0.25])
+def test_refresh_equals_fresh_setup(oracle_mod, theta):
+    # theta > 0: the strength graphs of the two value sets differ, and the
+    # refreshed hierarchy is the fresh one of the new values (no trace of v1)
     N = 24
     k1 = np.exp(M.grf(N, 2, seed=1))
     k2 = np.exp(M.grf(N, 2, seed=2))
     rp, ci, v1 = M.diffusion(k1)
     _, _, v2 = M.diffusion(k2)
-    H = oracle_mod.OracleHierarchy(rp, ci, v1, max_coarse=16)
+    H = oracle_mod.OracleHierarchy(rp, ci, v1, max_coarse=16, theta=theta)
+    G1 = H.level(0)["G_ci"].copy()
     H.update_values(v2)
-    F = oracle_mod.OracleHierarchy(rp, ci, v2, max_coarse=16)
+    F = oracle_mod.OracleHierarchy(rp, ci, v2, max_coarse=16, theta=theta)
+    if theta > 0:
+        assert len(G1) != len(F.level(0)["G_ci"]) or not np.array_equal(G1, F.level(0)["G_ci"])
     assert H.num_levels == F.num_levels
     for l in range(H.num_levels):
         a, b = H.level(l), F.level(l)
