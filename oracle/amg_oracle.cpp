@@ -3,7 +3,10 @@
 // and the benchmark's CPU-baseline leg load this library; the product path
 // never does.  It shares no code, header or table with the HIP library.
 //
-// Plain, sequential, slow on purpose.  Every step follows the method as the
+// Plain and slow on purpose; the setup is sequential, and the solve loops
+// run on one thread unless or_set_threads asks for more (OpenMP over rows
+// and over fixed dot-product blocks, so results never depend on the thread
+// count).  Every step follows the method as the
 // paper fixes it where it speaks (adjoint, Eq. (1); matrix-value and RHS
 // gradients, Eq. (2); setup reuse on a fixed pattern, Section 2.1 "C++/CUDA
 // backend"; iteration count / final residual / status diagnostics, Section
@@ -121,8 +124,15 @@ double diag_of(const Csr& A, int i) {
   return 0.0;
 }
 
+// Threads of the solve loops (or_set_threads; default 1).  Only loops whose
+// results do not depend on how rows are shared out run in parallel: row-wise
+// products and element-wise updates, and dot products over fixed blocks.
+int g_threads = 1;
+constexpr int kParMin = 16384;  // shorter loops stay on one thread
+
 // y = A x, each row summed in stored order from +0.0.
 void spmv(const Csr& A, const double* x, double* y) {
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (A.nrows >= kParMin)
   for (int i = 0; i < A.nrows; ++i) {
     double s = 0.0;
     for (int k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * x[A.ci[k]];
@@ -130,9 +140,24 @@ void spmv(const Csr& A, const double* x, double* y) {
   }
 }
 
+// <a, b> over fixed blocks of kDotBlock elements: each block summed in index
+// order from +0.0, then the block sums in block order.  The blocks do not
+// depend on the thread count, so neither does the result; a vector of at
+// most kDotBlock elements is one block (the plain sequential sum).
+constexpr int kDotBlock = 8192;
 double dot(const std::vector<double>& a, const std::vector<double>& b) {
+  const int64_t n = (int64_t)a.size();
+  const int64_t nb = (n + kDotBlock - 1) / kDotBlock;
+  std::vector<double> part(std::max<int64_t>(nb, 1), 0.0);
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
+  for (int64_t k = 0; k < nb; ++k) {
+    double s = 0.0;
+    const int64_t e = std::min(n, (k + 1) * kDotBlock);
+    for (int64_t i = k * kDotBlock; i < e; ++i) s += a[i] * b[i];
+    part[k] = s;
+  }
   double s = 0.0;
-  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  for (int64_t k = 0; k < nb; ++k) s += part[k];
   return s;
 }
 
@@ -482,21 +507,27 @@ void vcycle(const Hier& H, size_t l, const double* b, double* x) {
   const Level& L = H.lv[l];
   int n = L.A.nrows;
   std::vector<double> Ax(n), r(n);
+  const bool par = n >= kParMin;
+  (void)par;
   for (int i = 0; i < n; ++i) x[i] = 0.0;
   for (int s = 0; s < H.prm.nu_pre; ++s) {
     spmv(L.A, x, Ax.data());
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (par)
     for (int i = 0; i < n; ++i) x[i] = x[i] + L.sw[i] * (b[i] - Ax[i]);
   }
   spmv(L.A, x, Ax.data());
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (par)
   for (int i = 0; i < n; ++i) r[i] = b[i] - Ax[i];
   int nc = L.nagg;
   std::vector<double> bc(nc), xc(nc), Pxc(n);
   spmv(L.R, r.data(), bc.data());
   vcycle(H, l + 1, bc.data(), xc.data());
   spmv(L.P, xc.data(), Pxc.data());
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (par)
   for (int i = 0; i < n; ++i) x[i] = x[i] + Pxc[i];
   for (int s = 0; s < H.prm.nu_post; ++s) {
     spmv(L.A, x, Ax.data());
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (par)
     for (int i = 0; i < n; ++i) x[i] = x[i] + L.sw[i] * (b[i] - Ax[i]);
   }
 }
@@ -548,6 +579,7 @@ int pcg(const Hier& H, const double* bptr, double* xptr, double tol, int maxiter
       if (!(pq > 0.0)) { breakdown = true; break; }
       double alpha = rz / pq;
       if (flexible) rold = r;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
       for (int i = 0; i < n; ++i) {
         x[i] = x[i] + alpha * p[i];
         r[i] = r[i] - alpha * q[i];
@@ -568,6 +600,7 @@ int pcg(const Hier& H, const double* bptr, double* xptr, double tol, int maxiter
         beta = rzn / rz;
       }
       rz = rzn;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
       for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
       if (conj) conj[iters - 1] = dot(p, q) / std::sqrt(dot(p, p) * dot(q, q));
     }
@@ -575,19 +608,18 @@ int pcg(const Hier& H, const double* bptr, double* xptr, double tol, int maxiter
     if (!conv) break;  // iteration limit
     std::vector<double> Ax(n);
     spmv(A, x.data(), Ax.data());
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
     for (int i = 0; i < n; ++i) r[i] = b[i] - Ax[i];
     double trr = dot(r, r);
     if (trr <= thresh) { status = OR_OK; break; }
     if (replacements >= 5 || iters >= maxiter) break;
     ++replacements;
   }
-  std::vector<double> Ax(n);
+  std::vector<double> Ax(n), d(n);
   spmv(A, x.data(), Ax.data());
-  double trr = 0.0;
-  for (int i = 0; i < n; ++i) {
-    double d = b[i] - Ax[i];
-    trr += d * d;
-  }
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
+  for (int i = 0; i < n; ++i) d[i] = b[i] - Ax[i];
+  const double trr = dot(d, d);
   *relres_out = std::sqrt(trr / bb);
   *iters_out = iters;
   std::copy(x.begin(), x.end(), xptr);
@@ -639,6 +671,7 @@ int bicgstab(const Hier& H, const double* bptr, double* xptr, double tol, int ma
         first = false;
       } else {
         double beta = (rho / rho_old) * (alpha / omega);
+        #pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
         for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
       }
       apply_prec(H, use_prec, p, y, iters);
@@ -646,6 +679,7 @@ int bicgstab(const Hier& H, const double* bptr, double* xptr, double tol, int ma
       double rv = dot(rh, v);
       if (!(rv != 0.0) || !(rv == rv)) { breakdown = true; break; }
       alpha = rho / rv;
+      #pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
       for (int i = 0; i < n; ++i) {
         x[i] = x[i] + alpha * y[i];
         s[i] = r[i] - alpha * v[i];
@@ -664,6 +698,7 @@ int bicgstab(const Hier& H, const double* bptr, double* xptr, double tol, int ma
       if (!(tt > 0.0)) { breakdown = true; break; }
       omega = ts / tt;
       if (!(omega != 0.0) || !(omega == omega)) { breakdown = true; break; }
+      #pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
       for (int i = 0; i < n; ++i) {
         x[i] = x[i] + omega * z[i];
         r[i] = s[i] - omega * t[i];
@@ -677,19 +712,18 @@ int bicgstab(const Hier& H, const double* bptr, double* xptr, double tol, int ma
     if (breakdown || !conv) break;
     std::vector<double> Ax(n);
     spmv(A, x.data(), Ax.data());
+    #pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
     for (int i = 0; i < n; ++i) r[i] = b[i] - Ax[i];
     double trr = dot(r, r);
     if (trr <= thresh) { status = OR_OK; break; }
     if (replacements >= 5 || iters >= maxiter) break;
     ++replacements;
   }
-  std::vector<double> Ax(n);
+  std::vector<double> Ax(n), d(n);
   spmv(A, x.data(), Ax.data());
-  double trr = 0.0;
-  for (int i = 0; i < n; ++i) {
-    double d = b[i] - Ax[i];
-    trr += d * d;
-  }
+  #pragma omp parallel for schedule(static) num_threads(g_threads) if (n >= kParMin)
+  for (int i = 0; i < n; ++i) d[i] = b[i] - Ax[i];
+  const double trr = dot(d, d);
   *relres_out = std::sqrt(trr / bb);
   *iters_out = iters;
   std::copy(x.begin(), x.end(), xptr);
@@ -701,6 +735,11 @@ int bicgstab(const Hier& H, const double* bptr, double* xptr, double tol, int ma
 
 // ================================================================ C API
 extern "C" {
+
+// Threads of the solve loops (spmv, element-wise updates, fixed-block dot
+// products); the results do not depend on it.  k < 1 is taken as 1.
+void or_set_threads(int k) { g_threads = k < 1 ? 1 : k; }
+int or_get_threads(void) { return g_threads; }
 
 void* or_setup(int n, const int* rp, const int* ci, const double* v, double theta, int max_coarse, int max_levels,
                int smoother, double omega, int nu_pre, int nu_post, int symmetric, int* status) {

@@ -1,7 +1,8 @@
 """Compile the C++ oracle into oracle/liboracle.so (test infrastructure).
 
 g++ -O2 -std=c++17 -ffp-contract=off: no FMA contraction, IEEE division and
-square root, so every product and sum is rounded on its own.
+square root, so every product and sum is rounded on its own.  -fopenmp for
+the optional multi-threaded solve loops (or_set_threads).
 """
 import os
 import subprocess
@@ -14,7 +15,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
            "-o", tmp, SRC]
     if verbose:
         print(" ".join(cmd), flush=True)

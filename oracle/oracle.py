@@ -13,7 +13,8 @@ import numpy as np
 __all__ = ["OracleHierarchy", "spmv", "pattern_grad", "rel_residual", "node_key", "validate", "transpose",
            "color_columns", "probe_vectors", "probe_assemble", "probe_scatter",
            "diffusion_theta_grad", "OR_OK", "OR_NOT_CONVERGED", "OR_ERR_INVALID_ARG", "OR_ERR_ZERO_DIAG",
-           "OR_ERR_PATTERN_MISMATCH", "OR_ERR_BREAKDOWN", "OR_ERR_COARSE_TOO_LARGE", "load"]
+           "OR_ERR_PATTERN_MISMATCH", "OR_ERR_BREAKDOWN", "OR_ERR_COARSE_TOO_LARGE", "load",
+           "set_threads", "get_threads", "host_cores"]
 
 OR_OK = 0
 OR_NOT_CONVERGED = 1
@@ -81,8 +82,30 @@ def load():
     L.or_node_key.argtypes = [C.c_int]
     L.or_validate.restype = C.c_int
     L.or_validate.argtypes = [C.c_int, _ip, _ip]
+    L.or_set_threads.argtypes = [C.c_int]
+    L.or_get_threads.restype = C.c_int
     _LIB = L
     return L
+
+
+def set_threads(k: int):
+    """Threads of the oracle's solve loops (default 1).  Results do not depend
+    on it: rows and fixed dot-product blocks are shared out, never split."""
+    load().or_set_threads(int(k))
+
+
+def get_threads() -> int:
+    return load().or_get_threads()
+
+
+def host_cores() -> int:
+    """Cores this process may run on (its affinity mask, capped at 16, the
+    CPU share of one GPU on the box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def _i32(a):

@@ -390,3 +390,42 @@ def test_tridiagonal_inverse_problem_section_3_2(oracle_mod):
             break
     assert first_close is not None and first_close < gold["paper_claim_steps_below"]
     assert steps is not None and abs(d - d_true) < 1e-3
+
+
+def test_threads_do_not_change_results(oracle_mod):
+    """The oracle's optional multi-threaded solve loops share out whole rows and
+    fixed dot-product blocks, so every thread count gives the same bits; and a
+    dot product over several blocks is the block sums added in block order
+    (one block = the plain sequential sum)."""
+    rp, ci, v = M.diffusion(np.exp(M.grf(40, 3, seed=9)))        # 64,000 unknowns: several blocks
+    n = len(rp) - 1
+    b = M.rhs_normal(n, 5)
+    H = oracle_mod.OracleHierarchy(rp, ci, v)
+    runs = []
+    try:
+        for t in (1, 3, 8):
+            oracle_mod.set_threads(t)
+            assert oracle_mod.get_threads() == t
+            x, info = H.pcg(b, tol=1e-9)
+            xb, _ = H.bicgstab(b, tol=1e-9)
+            runs.append((x, xb, info["iters"], info["rel_resid"]))
+    finally:
+        oracle_mod.set_threads(1)
+    for x, xb, it, rr in runs[1:]:
+        assert np.array_equal(x.view(np.int64), runs[0][0].view(np.int64))
+        assert np.array_equal(xb.view(np.int64), runs[0][1].view(np.int64))
+        assert it == runs[0][2] and rr == runs[0][3]
+    # the reported true residual is the fixed-block dot of b - A x: 8192-element
+    # blocks each summed in index order, then the block sums in block order
+    d = b - _A(rp, ci, v) @ runs[0][0]
+    assert runs[0][3] == np.sqrt(_blocked_sq(d) / _blocked_sq(b))
+
+
+def _blocked_sq(b):
+    tot = 0.0
+    for k in range(0, len(b), 8192):
+        s = 0.0
+        for t in b[k:k + 8192]:
+            s += float(t) * float(t)
+        tot += s
+    return tot
