@@ -108,6 +108,20 @@ def test_multi_system(prec):
         assert cols["status"][s] == 0 and rr <= 1e-9
         if prec == "fp64":
             assert abs(cols["iters"][s] - io["iters"]) <= 1
+    if prec == "fp64":
+        # iterate parity at a fixed iteration count, every system against the
+        # oracle run on that system alone
+        kk = 9
+        Hk = AmgHierarchy(dev(rp), dev(ci), dev(V), max_coarse=32, maxiter=kk)
+        Xk, ik = Hk.solve(dev(B), 0.0)
+        Xkh = host(Xk)
+        assert ik["iters"] == kk
+        for s in range(S):
+            O = _oracle(rp, ci, vals[s], max_coarse=32)
+            xo, _ = O.pcg(B[:, s].copy(), tol=0.0, maxiter=kk)
+            err = np.linalg.norm(Xkh[:, s] - xo) / np.linalg.norm(xo)
+            print(f"[iterate parity] system {s} k={kk} err={err:.2e}", flush=True)
+            assert err <= 1e-9, (s, err)
 
 
 def test_batched_pattern_grads():

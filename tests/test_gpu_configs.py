@@ -52,6 +52,8 @@ def test_poisson_128_full():
 
 def test_lognormal_diffusion_192_cached_setup():
     import oracle
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    oracle.set_threads(oracle.host_cores())
     N = 192
     k = np.exp(M.grf(N, 3, seed=2))
     rp, ci, v = M.diffusion(k)
@@ -71,6 +73,16 @@ def test_lognormal_diffusion_192_cached_setup():
             print(f"[c3] gpu iters={info['iters']} fp32 iters={info32['iters']} oracle iters={io['iters']}",
                   flush=True)
             assert abs(info["iters"] - io["iters"]) <= 1
+            # iterate parity at the oracle's iteration count (the cached
+            # hierarchy, another handle with that iteration limit)
+            k = io["iters"]
+            Hk = AmgHierarchy(dev(rp), dev(ci), dev(v), maxiter=k)
+            xk, ik = Hk.solve(dev(b), 0.0)
+            xok, _ = O.pcg(b, tol=0.0, maxiter=k)
+            err = np.linalg.norm(host(xk) - xok) / np.linalg.norm(xok)
+            print(f"[c3 iterate parity] k={k} err={err:.3e}", flush=True)
+            assert ik["iters"] == k and ik["cache_event"] in (0, 1) and err <= 1e-9
+            Hk.close()
 
 
 def _c4_problem(N):
@@ -169,6 +181,7 @@ def test_batched_64_systems_96_full():
     oracle's."""
     import oracle
     from paper_2606_09001_amd.solver import AmgHierarchy, finalize
+    oracle.set_threads(oracle.host_cores())
     N, S = 96, 64
     vals = []
     for s in range(S):
@@ -189,7 +202,8 @@ def test_batched_64_systems_96_full():
             assert cols["status"][s] == 0 and rr <= 1e-8, (prec, s, rr)
         if prec == "fp64":
             st = H.stats()
-            for s in (0, 37, 63):
+            sampled = {}
+            for s in (0, 31, 63):
                 O = oracle.OracleHierarchy(rp, ci, vals[s])
                 assert O.num_levels == st["num_levels"]
                 for l in range(O.num_levels - 1):
@@ -201,6 +215,21 @@ def test_batched_64_systems_96_full():
                 xo, io = O.pcg(B[:, s].copy(), tol=1e-8)
                 print(f"[c5a] system {s}: gpu iters {cols['iters'][s]} oracle {io['iters']}", flush=True)
                 assert abs(cols["iters"][s] - io["iters"]) <= 1
+                sampled[s] = (O, io["iters"])
+            # iterate parity at a fixed count (the smallest sampled oracle count):
+            # the batched launch against the oracle run on each system alone
+            kk = min(k for _, k in sampled.values())
+            Hk = AmgHierarchy(d_rp, d_ci, d_V, autotune=1, maxiter=kk)
+            Xk, ik = Hk.solve(d_B, 0.0)
+            Xkh = host(Xk)
+            assert ik["iters"] == kk
+            for s, (O, _) in sampled.items():
+                xo, _ = O.pcg(B[:, s].copy(), tol=0.0, maxiter=kk)
+                err = np.linalg.norm(Xkh[:, s] - xo) / np.linalg.norm(xo)
+                print(f"[c5a iterate parity] system {s} k={kk} err={err:.3e}", flush=True)
+                assert err <= 1e-9, (s, err)
+            Hk.close()
+            del sampled
         H.close()
         finalize()
 
@@ -209,10 +238,12 @@ def test_batched_32_rhs_poisson_256_full():
     """32 right-hand sides on the 256^3 Poisson system (16.7M unknowns),
     autotuned, FP64 and FP32 cycle: every column's true residual (oracle
     SpMV) within the tolerance, the FP64 and mixed columns converge in the
-    same iteration window, and column 0 matches a single-RHS solve of the
-    same vector in iteration count."""
+    same iteration window; sampled FP64 columns against the oracle solving
+    them alone: iteration counts within one, and iterate parity at a fixed
+    count."""
     import oracle
     from paper_2606_09001_amd.solver import AmgHierarchy, finalize
+    oracle.set_threads(oracle.host_cores())
     N, k = 256, 32
     rp, ci, v = M.poisson(N, 3)
     n = len(rp) - 1
@@ -233,9 +264,27 @@ def test_batched_32_rhs_poisson_256_full():
             assert cols["status"][c] == 0 and rr <= 1e-8, (prec, c, rr)
             assert abs(cols["rel_resid"][c] - rr) <= 1e-6 * rr + 1e-15
         if prec == "fp64":
-            x1, i1 = H.solve(d_B[:, 0].contiguous(), 1e-8)
-            print(f"[c5b] column 0: batched iters {cols['iters'][0]} single {i1['iters']}", flush=True)
-            assert abs(cols["iters"][0] - i1["iters"]) <= 1
+            del X
+            print("[c5b] oracle setup 256^3", flush=True)
+            O = oracle.OracleHierarchy(rp, ci, v)
+            sampled = (0, 15, 31)
+            counts = {}
+            for c in sampled:
+                xo, io = O.pcg(B[:, c].copy(), tol=1e-8)
+                print(f"[c5b] column {c}: batched iters {cols['iters'][c]} oracle {io['iters']}", flush=True)
+                assert io["status"] == 0 and abs(cols["iters"][c] - io["iters"]) <= 1
+                counts[c] = io["iters"]
+            kk = min(counts.values())
+            Hk = AmgHierarchy(d_rp, d_ci, d_v, autotune=1, maxiter=kk)
+            X, ik = Hk.solve(d_B, 0.0)
+            assert ik["iters"] == kk
+            for c in sampled:
+                xo, _ = O.pcg(B[:, c].copy(), tol=0.0, maxiter=kk)
+                err = np.linalg.norm(host(X[:, c].contiguous()) - xo) / np.linalg.norm(xo)
+                print(f"[c5b iterate parity] column {c} k={kk} err={err:.3e}", flush=True)
+                assert err <= 1e-9, (c, err)
+            Hk.close()
+            del O
         H.close()
         finalize()
         del X
