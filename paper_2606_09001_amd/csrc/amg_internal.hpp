@@ -168,7 +168,6 @@ struct Ctl {
   int state;              // 0 running, 1 converged (recursive), 2 iteration limit, -1 breakdown
   int flexible;
   int pad_;
-  unsigned int ticket[8];
 };
 
 // Kernels that can be timed inside real solves (event pairs around every
@@ -451,41 +450,6 @@ __device__ inline void block_sum(double (&v)[NV]) {
   __syncthreads();
 }
 
-// Deterministic grid reduction: every block publishes its NV block sums to
-// partials[m*gridDim.x + blockIdx.x]; the last block to arrive (ticket)
-// reduces them in a fixed order.  Returns true in the last block only, with
-// the totals valid in its thread 0.  The ticket is reset for the next use.
-template <int NV>
-__device__ inline bool grid_sum(double (&v)[NV], double* partials, unsigned int* ticket) {
-  __shared__ bool s_last;
-  block_sum<NV>(v);
-  const int G = gridDim.x;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int m = 0; m < NV; ++m) partials[m * G + blockIdx.x] = v[m];
-    __threadfence();
-    unsigned int t = atomicAdd(ticket, 1u);
-    s_last = (t == (unsigned)G - 1);
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  double acc[NV];
-#pragma unroll
-  for (int m = 0; m < NV; ++m) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < G; b += kBlock)
-      s += __hip_atomic_load(partials + m * G + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    acc[m] = s;
-  }
-  block_sum<NV>(acc);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int m = 0; m < NV; ++m) v[m] = acc[m];
-    *ticket = 0u;
-  }
-  return true;
-}
 #endif  // __HIPCC__
 
 }  // namespace amg

@@ -377,11 +377,6 @@ __global__ void __launch_bounds__(kBlock) k_vec(int n, const int* __restrict__ r
   publish_partials<Op::NRED>(d, partials);
 }
 
-// Loads of the operator's entry stream (read once per sweep).
-#ifndef AMG_STREAM_LOAD
-#define AMG_STREAM_LOAD(ptr) (*(ptr))
-#endif
-
 // Sliced sweep: thread per row, the wave's 64 rows form one slice whose
 // entries are stored column-major, so entry j of all 64 rows is one
 // coalesced load.  The slice width is uniform across the wave; padding
@@ -405,8 +400,8 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, const int* __restrict__ 
 #pragma unroll
   for (int j = 0; j < kSellMaxW; ++j) {
     const int p = off + min(j, w - 1) * 64 + lane;
-    col[j] = AMG_STREAM_LOAD(sci + p);
-    val[j] = AMG_STREAM_LOAD(op.v + p);
+    col[j] = sci[p];
+    val[j] = op.v[p];
   }
   PT pv[kSellMaxW];
 #pragma unroll
@@ -437,7 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_sello(int n, const int* __restrict__
   const int sb = off >> 6;
   typename std::remove_const<typename std::remove_pointer<decltype(op.v)>::type>::type val[kSellMaxW];
 #pragma unroll
-  for (int j = 0; j < kSellMaxW; ++j) val[j] = AMG_STREAM_LOAD(op.v + off + min(j, w - 1) * 64 + lane);
+  for (int j = 0; j < kSellMaxW; ++j) val[j] = op.v[off + min(j, w - 1) * 64 + lane];
   // the slice's kSellMaxW records as one block (the array is padded so the
   // last slice's block stays in bounds)
   int4 rec[kSellMaxW];
