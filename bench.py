@@ -226,22 +226,30 @@ def run_batched(args, dev):
     d_B = torch.from_numpy(B).to(dev)
     del B
     X = torch.empty_like(d_B)
-    res = {}
+    res = {"workload": f"3D Poisson {N}^3 ({n} unknowns, {len(ci)} nnz), {k} right-hand sides ~ N(0,1) seeds "
+                       f"3000-{3000 + k - 1}, row-major [n][{k}], one batched PCG launch sequence, tol {args.tol:g}"}
+    sample = [c for c in (0, k - 1) if c < k]
+    xs = {}
     for prec in ("fp64", "fp32"):
         H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec, autotune=1)
         ms, cols, info = time_solves(H, d_B, X, args.tol, args.batched_steps, 1)
-        res[prec] = dict(ms_per_batch=round(ms, 3), rhs_per_s=round(k * 1e3 / ms, 2), iters_max=max(cols["iters"]),
-                         rel_resid_max=max(cols["rel_resid"]), all_converged=all(s_ == 0 for s_ in cols["status"]))
+        res[prec] = batched_entry(H, ms, cols, k, prec, "rhs_per_s")
+        if not args.no_kernel_table:
+            res[prec]["kernels_L0"] = batched_kernel_table(H, d_B, X, args.tol, k, prec)
+        xs[prec] = {c: X[:, c].cpu().numpy().copy() for c in sample}
         log(f"batched {k} RHS on {N}^3 {prec}: {ms:.1f} ms/batch, {k * 1e3 / ms:.1f} RHS/s, "
-            f"iters {min(cols['iters'])}..{max(cols['iters'])}")
+            f"iters {min(cols['iters'])}..{max(cols['iters'])}, {res[prec]['solve_hbm_gbs']:.0f} GB/s")
         H.close()
         del H
         finalize()
         torch.cuda.synchronize()
     res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms_per_batch"] / res["fp32"]["ms_per_batch"], 4)
-    out[f"poisson3d_{N}_x{k}rhs"] = res
     del d_B, X, d_rp, d_ci, d_v
     torch.cuda.empty_cache()
+    if not args.no_oracle_errors:
+        res["vs_oracle"] = oracle_errors(rp, ci, v, {c: M.rhs_normal(n, 3000 + c) for c in sample}, args.tol, xs,
+                                         "column")
+    out[f"poisson3d_{N}_x{k}rhs"] = res
     # (2) S same-pattern lognormal diffusion systems on a 96^3 grid
     N, S = args.batched_sys_grid, 64
     vals = []
@@ -255,26 +263,99 @@ def run_batched(args, dev):
     d_rp, d_ci, d_V, d_B = (torch.from_numpy(a).to(dev) for a in (rp, ci, V, B))
     del V, B
     X = torch.empty_like(d_B)
-    res = {}
+    res = {"workload": f"{S} lognormal diffusion systems on {N}^3 ({n} unknowns, {len(ci)} nnz each) sharing the "
+                       f"7-point pattern, k = exp(GRF seeds 1000-{1000 + S - 1}), b seeds 2000-{2000 + S - 1}, "
+                       f"values [nnz][{S}], one batched PCG launch sequence, tol {args.tol:g}"}
+    sample = [s_ for s_ in (0, 31, 63) if s_ < S]
+    xs = {}
     for prec in ("fp64", "fp32"):
         t0 = time.time()
         H = AmgHierarchy(d_rp, d_ci, d_V, vcycle_prec=prec, autotune=1)
         torch.cuda.synchronize()
         setup_ms = (time.time() - t0) * 1e3
         ms, cols, info = time_solves(H, d_B, X, args.tol, args.batched_steps, 1)
-        res[prec] = dict(ms_per_batch=round(ms, 3), systems_per_s=round(S * 1e3 / ms, 2),
-                         iters_max=max(cols["iters"]), rel_resid_max=max(cols["rel_resid"]),
-                         all_converged=all(s_ == 0 for s_ in cols["status"]), setup_ms=round(setup_ms, 1))
+        res[prec] = batched_entry(H, ms, cols, S, prec, "systems_per_s")
+        res[prec]["setup_ms"] = round(setup_ms, 1)
+        if not args.no_kernel_table:
+            res[prec]["kernels_L0"] = batched_kernel_table(H, d_B, X, args.tol, S, prec)
+        xs[prec] = {c: X[:, c].cpu().numpy().copy() for c in sample}
         log(f"batched {S} systems {N}^3 {prec}: setup {setup_ms:.0f} ms, {ms:.1f} ms/batch, "
-            f"{S * 1e3 / ms:.1f} systems/s, iters {min(cols['iters'])}..{max(cols['iters'])}")
+            f"{S * 1e3 / ms:.1f} systems/s, iters {min(cols['iters'])}..{max(cols['iters'])}, "
+            f"{res[prec]['solve_hbm_gbs']:.0f} GB/s")
         H.close()
         del H
         finalize()
         torch.cuda.synchronize()
     res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms_per_batch"] / res["fp32"]["ms_per_batch"], 4)
-    out[f"diffusion3d_{N}_x{S}systems"] = res
     del d_B, X, d_V
     torch.cuda.empty_cache()
+    if not args.no_oracle_errors:
+        errs = {}
+        for s_ in sample:
+            _, _, vv = M.diffusion(np.exp(M.grf(N, 3, seed=1000 + s_)))
+            e = oracle_errors(rp, ci, vv, {s_: M.rhs_normal(n, 2000 + s_)}, args.tol,
+                              {p_: {s_: xs[p_][s_]} for p_ in xs}, "system")
+            errs.update(e["per"])
+        res["vs_oracle"] = {"kind": "system", "per": errs,
+                            "max_err_fp64": max(d_["err_fp64"] for d_ in errs.values()),
+                            "max_err_fp32": max(d_["err_fp32"] for d_ in errs.values())}
+    out[f"diffusion3d_{N}_x{S}systems"] = res
+    return out
+
+
+def batched_entry(H, ms, cols, width, prec, rate_key):
+    """Throughput of one timed batched solve: columns per second, and the
+    algorithmic HBM rate of the launches (every batched sweep processes all
+    columns until the last one finishes: iterations = the largest column
+    count, bytes from amg_kernel_bytes_batched)."""
+    it_bytes = H.kernel_bytes_batched(None, 0, flexible=(prec == "fp32"), width=width)
+    gbs = max(cols["iters"]) * it_bytes / (ms * 1e-3) / 1e9
+    return dict(ms_per_batch=round(ms, 3), **{rate_key: round(width * 1e3 / ms, 2)},
+                iters_max=max(cols["iters"]), iters_min=min(cols["iters"]), rel_resid_max=max(cols["rel_resid"]),
+                all_converged=all(s_ == 0 for s_ in cols["status"]), bytes_per_iter=it_bytes,
+                ms_per_iter=round(ms / max(cols["iters"]), 4), solve_hbm_gbs=round(gbs, 1),
+                solve_hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+
+
+def batched_kernel_table(H, B, X, tol, width, prec):
+    """Level-0 batched sweeps timed in-solve (HIP event pairs around every
+    launch of one kernel on the solve stream, one solve per kernel) against
+    their algorithmic bytes."""
+    kt = {}
+    for name in ("spmv_dot", "pre", "post", "restrict", "prolong", "cg_update"):
+        H.instrument(name, 0)
+        H.solve(B, tol, out=X)
+        r = H.instrument_read()
+        H.instrument(None)
+        if r["launches"] == 0:
+            continue
+        nbytes = H.kernel_bytes_batched(name, 0, flexible=(prec == "fp32"), width=width)
+        g = nbytes / (r["avg_ms"] * 1e-3) / 1e9
+        kt[name] = dict(avg_us=round(r["avg_ms"] * 1e3, 2), bytes_per_launch=nbytes, gbs=round(g, 1),
+                        frac=round(g / HBM_PEAK_GBS, 4), launches=r["launches"])
+    return kt
+
+
+def oracle_errors(rp, ci, v, rhs, tol, xs, kind):
+    """Error of GPU solutions against the FP64 oracle solving the same
+    right-hand side to the same tolerance (all host cores): per sampled
+    column, ||x_gpu - x_oracle|| / ||x_oracle|| for the FP64 and the FP32
+    cycle, and the oracle's iteration count."""
+    import numpy as np
+    import oracle
+    oracle.set_threads(oracle.host_cores())
+    O = oracle.OracleHierarchy(rp, ci, v)
+    per = {}
+    for c, b in rhs.items():
+        xo, io = O.pcg(b, tol=tol)
+        nx = np.linalg.norm(xo)
+        per[c] = {"oracle_iters": io["iters"],
+                  **{f"err_{p}": float(np.linalg.norm(xs[p][c] - xo) / nx) for p in xs}}
+    del O
+    out = {"kind": kind, "per": per}
+    for p in xs:
+        out[f"max_err_{p}"] = max(d[f"err_{p}"] for d in per.values())
+    log(f"vs oracle ({kind}s {list(rhs)}): " + ", ".join(f"{p} {out[f'max_err_{p}']:.2e}" for p in xs))
     return out
 
 
@@ -294,6 +375,7 @@ def run_diffusion(args, dev):
     x = torch.empty(n, dtype=torch.float64, device=dev)
     out = {"workload": f"3D lognormal diffusion {N}^3 ({n} unknowns, {len(ci)} nnz), k = exp(GRF seed 2, sigma 1, "
                        f"correlation 0.1), 10 right-hand sides with the setup cached, tol {args.tol:g}"}
+    xs_d = {}
     for prec in ("fp64", "fp32"):
         t0 = time.time()
         H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec)
@@ -316,6 +398,8 @@ def run_diffusion(args, dev):
         H.update_values(d_v)     # warm resetup: numeric refresh of the whole hierarchy, same pattern
         torch.cuda.synchronize()
         refresh_ms = (time.time() - t0) * 1e3
+        H.solve(Bs[0], args.tol, out=x)
+        xs_d[prec] = {100: x.cpu().numpy().copy()}
         out[prec] = dict(ms_per_solve=round(ms, 3), solves_per_s=round(1e3 / ms, 2), iters_mean=float(np.mean(iters)),
                          rel_resid_max=max(rr), setup_ms=round(setup_ms, 1), refresh_ms=round(refresh_ms, 1),
                          solve_hbm_gbs=round(gbs, 1), solve_hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
@@ -342,6 +426,8 @@ def run_diffusion(args, dev):
         H.close()
         finalize()
     out["speedup_mixed_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["fp32"]["ms_per_solve"], 4)
+    if not args.no_oracle_errors:
+        out["vs_oracle"] = oracle_errors(rp, ci, v, {100: M.rhs_normal(n, 100)}, args.tol, xs_d, "rhs seed")
     return out
 
 
@@ -623,8 +709,15 @@ def run_adjoint(args, dev):
     Ht.close()
     out = {"workload": f"2D diffusion {N}^2 ({N * N} unknowns), theta = GRF seed 41, u_obs from theta = GRF seed 42, "
                        f"loss 0.5||u - u_obs||^2, forward and adjoint solves to 1e-10, one gradient step per iteration"}
+    grads = {}
     for prec in ("fp64", "fp32"):
         th = torch.tensor(theta0, device=dev, requires_grad=True)
+        # the gradient at theta0 (compared with the oracle's below)
+        val0 = M.diffusion_values_torch(torch.exp(th))
+        x0_ = amg_solve(d_rp, d_ci, val0, b, 1e-10, vcycle_prec=prec)
+        (0.5 * torch.sum((x0_ - u_obs) ** 2)).backward()
+        grads[prec] = th.grad.cpu().numpy().copy()
+        th.grad = None
 
         def step():
             val = M.diffusion_values_torch(torch.exp(th))
@@ -649,6 +742,23 @@ def run_adjoint(args, dev):
         out[prec] = dict(ms_per_step=round(ms, 3), steps_per_s=round(1e3 / ms, 2), loss_last=float(loss.detach()))
         log(f"adjoint {N}^2 {prec}: {ms:.2f} ms per gradient step (refresh + forward + adjoint + pattern grad)")
         finalize()
+    if not args.no_oracle_errors:
+        # dL/dtheta at theta0 from the oracle: forward and adjoint solves to 1e-10,
+        # pattern gradient, chain rule through the harmonic face coefficients
+        import oracle
+        oracle.set_threads(oracle.host_cores())
+        k0 = np.exp(theta0)
+        _, _, v0 = M.diffusion(k0)
+        uo = u_obs.cpu().numpy()
+        O = oracle.OracleHierarchy(rp, ci, v0)
+        xo, _ = O.pcg(np.ones(N * N), tol=1e-10)
+        lo, _ = O.solve_adjoint(xo - uo, tol=1e-10)
+        go = oracle.diffusion_theta_grad(k0, rp, ci, O.pattern_grad(lo, xo))
+        ng = np.linalg.norm(go)
+        out["vs_oracle"] = {"kind": "dL/dtheta at theta0", **{f"grad_rel_err_{p}": float(np.linalg.norm(grads[p] - go) / ng)
+                                                            for p in grads}}
+        log(f"adjoint {N}^2 gradient vs oracle: " + ", ".join(f"{p} {out['vs_oracle'][f'grad_rel_err_{p}']:.2e}"
+                                                            for p in grads))
     return out
 
 
@@ -660,6 +770,9 @@ def main():
     ap.add_argument("--grid", type=int, default=128, help="interior grid points per axis (default 128)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-errors", action="store_true",
+                    help="skip the oracle solves that report each workload's error against the FP64 oracle")
+    ap.add_argument("--batched-only", action="store_true", help="only the batched workloads; for profiling")
     ap.add_argument("--calib-copy-mib", type=int, default=512,
                     help="size of a plain device copy run once (PMC calibration of FETCH/WRITE_SIZE)")
     ap.add_argument("--no-kernel-table", action="store_true",
@@ -772,6 +885,9 @@ def main():
     if args.diffusion_only:
         print(json.dumps({"diffusion": run_diffusion(args, dev)}), flush=True)
         return
+    if args.batched_only:
+        print(json.dumps({"batched": run_batched(args, dev)}), flush=True)
+        return
 
     res = {}
     hier = {}
@@ -863,25 +979,39 @@ def main():
         t0 = time.time()
         O = oracle.OracleHierarchy(rp, ci, v)
         osetup = time.time() - t0
-        # a bounded sample: complete solves of the same system, repeated until
-        # at least 10 s of host time have been spent
-        t0 = time.time()
-        nsolves = 0
-        while True:
-            xo, io = O.pcg(b, tol=args.tol)
-            nsolves += 1
-            if time.time() - t0 >= 10.0:
-                break
-        osolve = (time.time() - t0) / nsolves
+        nproc = os.cpu_count()
+        cores = oracle.host_cores()
+
+        def sample(threads, budget):
+            # a bounded sample: complete solves of the same system, repeated
+            # until `budget` seconds of host time have been spent
+            oracle.set_threads(threads)
+            t0 = time.time()
+            k = 0
+            while True:
+                xo, io = O.pcg(b, tol=args.tol)
+                k += 1
+                if time.time() - t0 >= budget:
+                    break
+            return (time.time() - t0) / k, k, xo, io
+
+        osolve, nsolves, xo, io = sample(cores, 10.0)
+        osolve1, nsolves1, _, _ = sample(1, 10.0)
+        oracle.set_threads(1)
         err = float(np.linalg.norm(sols["fp64"] - xo) / np.linalg.norm(xo))
         err32 = float(np.linalg.norm(sols["fp32"] - xo) / np.linalg.norm(xo))
-        cpu = {"value": round(1.0 / osolve, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": round(1.0 / osolve, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
                "sample": f"{nsolves} complete FP64 AMG-PCG solves of the {N}^3 Poisson system to {args.tol:g} "
                          f"({io['iters']} iterations each, {osolve:.2f} s per solve, {nsolves * osolve:.1f} s in "
-                         f"all; setup {osetup:.2f} s not included), single-threaded C++ oracle on the host",
+                         f"all; setup {osetup:.2f} s not included), C++ oracle with {cores} OpenMP threads in its "
+                         f"solve loops (host: {nproc} logical CPUs, affinity {cores})",
+               "host_nproc": nproc,
+               "single_thread": {"value": round(1.0 / osolve1, 4), "cores": 1, "solves": nsolves1,
+                                 "s_per_solve": round(osolve1, 3)},
                "oracle_iters": io["iters"], "gpu_vs_oracle_rel_err": err, "mixed_vs_oracle_rel_err": err32}
-        log(f"oracle: setup {osetup:.2f}s solve {osolve:.2f}s iters {io['iters']}; |x_gpu-x_oracle|/|x|={err:.2e} "
-            f"(mixed {err32:.2e})")
+        log(f"oracle: setup {osetup:.2f}s; solve {osolve:.2f}s on {cores} threads, {osolve1:.2f}s on 1; "
+            f"iters {io['iters']}; |x_gpu-x_oracle|/|x|={err:.2e} (mixed {err32:.2e})")
+        del O
 
     batched = None
     if not args.no_batched:

@@ -320,6 +320,18 @@ amg_status amg_instrument_read(amg_handle h, int* launches, double* total_ms, do
  * the flexible beta (adds the read of q to the level-0 post-smoother). */
 amg_status amg_kernel_bytes(amg_handle h, int kernel, int level, int flexible, double* bytes);
 
+/* Algorithmic bytes of one launch of a batched sweep with `width` columns
+ * (amg_solve with nrhs = width; with n_systems S > 1, width must be S): the
+ * batched kernels stream every operator as CSR (int32 columns and row
+ * pointers, once per launch); values, smoother weights and coarse inverses
+ * are read once per launch for right-hand sides of one matrix and once per
+ * column for S systems sharing a pattern; every vector operand is width
+ * columns wide.  kernel -1: one whole batched PCG iteration with every column
+ * active.  amg_instrument times the batched solve's launches the same way
+ * (the done test is then "every column finished"). */
+amg_status amg_kernel_bytes_batched(amg_handle h, int kernel, int level, int flexible, int32_t width,
+                                    double* bytes);
+
 /* Releases the caller's reference; the hierarchy is freed when neither a
  * caller nor the cache holds it. */
 amg_status amg_destroy(amg_handle h);

@@ -41,6 +41,7 @@ EXPORTS = [
     "amg_cache_size", "amg_set_cache_capacity", "amg_status_string", "amg_instrument", "amg_instrument_read",
     "amg_kernel_bytes", "amg_pattern_grad_batched", "amg_solve_columns", "amg_color_columns",
     "amg_probe_vectors", "amg_probe_assemble", "amg_probe_scatter", "amg_convert_bf16",
+    "amg_kernel_bytes_batched",
 ]
 
 KERNELS = {"spmv_dot": 0, "pre": 1, "post": 2, "restrict": 3, "prolong": 4, "cg_update": 5, "xpay": 6, "coarse": 7}
@@ -119,6 +120,7 @@ def load():
     L.amg_instrument.argtypes = [vp, C.c_int, C.c_int]
     L.amg_instrument_read.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)]
     L.amg_kernel_bytes.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(dbl)]
+    L.amg_kernel_bytes_batched.argtypes = [vp, C.c_int, C.c_int, C.c_int, i32, C.POINTER(dbl)]
     L.amg_pattern_grad_batched.argtypes = [vp, vp, vp, i32, vp, vp]
     L.amg_solve_columns.argtypes = [vp, i32, vp, vp, vp]
     L.amg_color_columns.argtypes = [i32, i64, vp, vp, vp, C.POINTER(i32), vp]

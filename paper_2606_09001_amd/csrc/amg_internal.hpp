@@ -327,6 +327,8 @@ void capture_graph(hipStream_t s, hipGraphExec_t& ex, const std::function<void()
 // batch.hip
 amg_status pcg_solve_wide(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int W,
                           amg_info* info, hipStream_t s);
+double wide_kernel_bytes(const Hierarchy& H, int kid, int level, int flexible, int W);
+double wide_iteration_bytes(const Hierarchy& H, int flexible, int W);
 void pattern_grad_wide(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, int W, hipStream_t s);
 void choose_shapes(Hierarchy& H, hipStream_t s);
 double kernel_bytes(const Hierarchy& H, int kid, int level, int flexible);

@@ -328,6 +328,36 @@ __global__ void __launch_bounds__(kBlock) k_wide(int n, int W, int spx, const in
   publish_w<LW, Op::NRED>(d, W, partials);
 }
 
+// Instrumented launches (amg_instrument) of the batched solve: the done
+// state of the batch (every column finished) is copied into the record
+// before the event pair, so launches that return at once are left out.
+__global__ void k_wsnap_done(const BatchHead* head, int* dst) {
+  if (threadIdx.x == 0) dst[0] = head->ndone >= head->W ? 1 : 0;
+}
+
+struct WInstScope {
+  Hierarchy& H;
+  hipStream_t s;
+  bool on;
+  WInstScope(Hierarchy& h, int kid, int level, hipStream_t st) : H(h), s(st) {
+    on = H.inst.kernel == kid && (H.inst.level == level || H.inst.level < 0) &&
+         2 * (H.inst.used + 1) <= (int)H.inst.ev.size();
+    if (on) {
+      hipLaunchKernelGGL(k_wsnap_done, dim3(1), dim3(64), 0, s, H.bt.head.p, H.inst.was_done.p + H.inst.used);
+      AMG_HIP(hipEventRecord(H.inst.ev[2 * H.inst.used], s));
+    }
+  }
+  // closes the timed range (at most once)
+  void end() {
+    if (on) {
+      (void)hipEventRecord(H.inst.ev[2 * H.inst.used + 1], s);
+      ++H.inst.used;
+      on = false;
+    }
+  }
+  ~WInstScope() { end(); }
+};
+
 // ------------------------------------------------- elementwise (FP64 CG)
 
 // r = b, x = 0, <b, b> per column
@@ -805,19 +835,24 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
   for (int l = 0; l < nl - 1; ++l) {
     Level& L = H.lv[l];
     BatchLevel& BL = B.lv[l];
-    if (l == 0)
-      wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, double>{WB<T>::v(L), r0, WB<T>::x(BL), WB<T>::r(BL), W}, hd,
-             nullptr, s);
-    else
-      wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W},
-             hd, nullptr, s);
+    {
+      WInstScope is(H, KID_PRE, l, s);
+      if (l == 0)
+        wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
+               WResid<SYS, T, double>{WB<T>::v(L), r0, WB<T>::x(BL), WB<T>::r(BL), W}, hd, nullptr, s);
+      else
+        wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
+               WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W}, hd, nullptr, s);
+    }
     Level& Ln = H.lv[l + 1];
     BatchLevel& BN = B.lv[l + 1];
     const bool coarsest = (l + 1 == nl - 1);
+    WInstScope is(H, KID_RESTRICT, l, s);
     w_restrict<SYS, T>(H, L, LWv, BL.spxR, BL.brR, W, WB<T>::r(BL), WB<T>::b(BN), coarsest ? nullptr : WB<T>::sw(Ln),
                        coarsest ? nullptr : WB<T>::x(BN), s);
   }
   {
+    WInstScope is(H, KID_COARSE, nl - 1, s);
     BatchLevel& BC = B.lv[nl - 1];
     const int64_t nt = (int64_t)C.n * W;
     hipLaunchKernelGGL((k_wcoarse<SYS, T>), dim3((int)((nt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, C.n, C.m,
@@ -827,9 +862,13 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = H.lv[l];
     BatchLevel& BL = B.lv[l];
-    w_prolong<SYS, T>(H, L, LWv, BL.spxP, BL.brP, W, res, WB<T>::x(BL), s);
+    {
+      WInstScope is(H, KID_PROLONG, l, s);
+      w_prolong<SYS, T>(H, L, LWv, BL.spxP, BL.brP, W, res, WB<T>::x(BL), s);
+    }
     const T* vv = WB<T>::v(L);
     const T* sw = WB<T>::sw(L);
+    WInstScope is(H, KID_POST, l, s);
     if (l == 0) {
       int np = 0;
       if (red == 2)
@@ -841,6 +880,7 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
       else
         wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 0>{vv, sw, r0, WB<T>::x(BL), z0, q, W}, hd,
                nullptr, s);
+      is.end();
       if (red == 2)
         hipLaunchKernelGGL(k_wfin_beta<2>, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, np);
       else if (red == 1)
@@ -1036,7 +1076,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
   const bool multi = H.lv.size() > 1;
   const int flexible = o.flexible < 0 ? ((H.fp32() || H.prm.nu_pre != H.prm.nu_post) ? 1 : 0) : o.flexible;
   if (!multi) throw Error(AMG_ERR_INVALID_ARG, "batched solves need at least two levels");
-  const bool graphs = o.use_graphs != 0;
+  const bool graphs = o.use_graphs != 0 && H.inst.kernel < 0;
   hipStream_t s = caller;
   if (graphs) {
     graph_stream(H);
@@ -1063,11 +1103,18 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
   T* x0 = WB<T>::x(B.lv[0]);
   // one batched iteration (columns flagged `first` take p = z on device)
   auto iteration = [&](int c, hipStream_t stq) {
-    const int np = wsweep(LWv, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p, WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W},
-                          B.head.p, part, stq);
+    int np;
+    {
+      WInstScope is(H, KID_SPMV_DOT, 0, stq);
+      np = wsweep(LWv, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p,
+                  WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W}, B.head.p, part, stq);
+    }
     hipLaunchKernelGGL(k_wfin_alpha, dim3(W), dim3(kWFin), 0, stq, B.ctl.p, B.head.p, part, W, np);
-    AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wupdate<LW, SYS, T>), dim3(gw), dim3(kBlock), 0, stq, n, W, d_x,
-                                            B.r.p, pb[c ^ 1], B.q.p, WB<T>::sw(L0), x0, B.ctl.p, B.head.p, part));
+    {
+      WInstScope is(H, KID_CG_UPDATE, 0, stq);
+      AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wupdate<LW, SYS, T>), dim3(gw), dim3(kBlock), 0, stq, n, W, d_x,
+                                              B.r.p, pb[c ^ 1], B.q.p, WB<T>::sw(L0), x0, B.ctl.p, B.head.p, part));
+    }
     hipLaunchKernelGGL(k_wfin_update, dim3(W), dim3(kWFin), 0, stq, B.ctl.p, B.head.p, part, W, gw);
     wvcycle<SYS, T>(H, W, B.r.p, B.z.p, B.q.p, flexible ? 2 : 1, stq);
   };
@@ -1175,6 +1222,61 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
 }
 
 }  // namespace
+
+// Algorithmic bytes of one launch of a batched sweep with W columns (every
+// matrix array streamed once, every vector operand read once, every output
+// written once).  The wide kernels sweep CSR; with S = W systems sharing the
+// pattern the values, smoother weights and coarse inverses are per column
+// ([entry][S]), with W right-hand sides of one matrix they are read once.
+// Vectors are W columns wide.
+double wide_kernel_bytes(const Hierarchy& H, int kid, int level, int flexible, int W) {
+  const int nl = (int)H.lv.size();
+  if (level < 0 || level >= nl || W < 1) return 0.0;
+  const Level& L = H.lv[level];
+  const double sys = H.S > 1 ? (double)W : 1.0;             // value streams per entry
+  const double w = W;
+  const double v = H.fp32() ? 4.0 : 8.0;                     // cycle values and vectors
+  const double pw = H.fp32() ? (H.bf16() ? 2.0 : 4.0) : 8.0; // transfer values
+  const double n = L.n, nc = L.nagg;
+  auto M = [&](double nz, double rows, double vb) { return 4.0 * nz + 4.0 * (rows + 1.0) + vb * nz * sys; };
+  const double bw = level == 0 ? 8.0 : v;
+  const bool has_next = level + 1 < nl;
+  const bool next_coarsest = level + 2 == nl;
+  switch (kid) {
+    // p' = z + beta p gathered (z and p), p' and q = A p' written
+    case KID_SPMV_DOT: return M((double)L.nnz, n, 8.0) + 32.0 * n * w;
+    case KID_PRE: return M((double)L.nnz, n, v) + (bw + 2.0 * v) * n * w;
+    case KID_POST: {
+      const double ow = level == 0 ? 8.0 : v;
+      return M((double)L.nnz, n, v) + (bw + v + ow) * n * w + v * n * sys + (level == 0 && flexible ? 8.0 * n * w : 0.0);
+    }
+    case KID_RESTRICT:
+      if (!has_next) return 0.0;
+      return M((double)L.pnnz, nc, pw) + v * n * w + v * nc * w + (next_coarsest ? 0.0 : v * nc * sys + v * nc * w);
+    case KID_PROLONG:
+      if (!has_next) return 0.0;
+      return M((double)L.pnnz, n, pw) + v * nc * w + 2.0 * v * n * w;
+    // x, r read and written, p and q read; sw read and x0 = sw o r written
+    case KID_CG_UPDATE: return 48.0 * n * w + v * n * sys + v * n * w;
+    case KID_XPAY: return 0.0;
+    case KID_COARSE: {
+      const double m = H.co.n;
+      return m * m * v * sys + 2.0 * m * v * w;
+    }
+  }
+  return 0.0;
+}
+
+// Bytes of one batched PCG iteration with every one of the W columns active.
+double wide_iteration_bytes(const Hierarchy& H, int flexible, int W) {
+  const int nl = (int)H.lv.size();
+  double b = wide_kernel_bytes(H, KID_SPMV_DOT, 0, flexible, W) + wide_kernel_bytes(H, KID_CG_UPDATE, 0, flexible, W) +
+             wide_kernel_bytes(H, KID_COARSE, nl - 1, flexible, W);
+  for (int l = 0; l < nl - 1; ++l)
+    b += wide_kernel_bytes(H, KID_PRE, l, flexible, W) + wide_kernel_bytes(H, KID_RESTRICT, l, flexible, W) +
+         wide_kernel_bytes(H, KID_PROLONG, l, flexible, W) + wide_kernel_bytes(H, KID_POST, l, flexible, W);
+  return b;
+}
 
 amg_status pcg_solve_wide(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int W,
                           amg_info* info, hipStream_t s) {

@@ -715,6 +715,20 @@ amg_status amg_kernel_bytes(amg_handle h, int kernel, int level, int flexible, d
   return AMG_OK;
 }
 
+amg_status amg_kernel_bytes_batched(amg_handle h, int kernel, int level, int flexible, int32_t width,
+                                    double* bytes) {
+  if (!h || !bytes || width < 1 || width > kMaxWidth) return AMG_ERR_INVALID_ARG;
+  const Hierarchy& H = *h->H;
+  if (H.S > 1 && width != H.S) return AMG_ERR_INVALID_ARG;
+  if (kernel == -1) {
+    *bytes = wide_iteration_bytes(H, flexible, width);
+    return AMG_OK;
+  }
+  if (kernel < 0 || kernel >= KID_COUNT || level < 0 || level >= (int)H.lv.size()) return AMG_ERR_INVALID_ARG;
+  *bytes = wide_kernel_bytes(H, kernel, level, flexible, width);
+  return AMG_OK;
+}
+
 amg_status amg_convert_bf16(const float* d_in, uint16_t* d_out, int64_t n, hipStream_t stream) {
   return guarded([&]() -> amg_status {
     if (n < 0 || (n > 0 && (!d_in || !d_out))) return AMG_ERR_INVALID_ARG;

@@ -189,6 +189,18 @@ class AmgHierarchy:
         _lib.check(self._L.amg_kernel_bytes(self._h, kid, level, int(flexible), C.byref(b)), "amg_kernel_bytes")
         return b.value
 
+    def kernel_bytes_batched(self, kernel: str | None, level: int = 0, flexible: bool = False,
+                             width: int | None = None) -> float:
+        """Algorithmic bytes of one launch of a batched sweep with `width`
+        columns (default: the number of systems); kernel None: one batched
+        PCG iteration with every column active."""
+        kid = -1 if kernel is None else _lib.KERNELS[kernel]
+        w = self.n_systems if width is None else int(width)
+        b = C.c_double(0)
+        _lib.check(self._L.amg_kernel_bytes_batched(self._h, kid, level, int(flexible), w, C.byref(b)),
+                   "amg_kernel_bytes_batched")
+        return b.value
+
     def stats(self) -> dict:
         s = _lib.amg_hier_stats()
         _lib.check(self._L.amg_hierarchy_stats(self._h, C.byref(s)), "amg_hierarchy_stats")
