@@ -57,7 +57,8 @@ typedef enum {
                                        non-SPD (symmetric) / singular (nonsymmetric) coarse matrix */
   AMG_ERR_OOM = -5,                 /* device allocation failed */
   AMG_ERR_HIP = -6,                 /* a HIP runtime call failed */
-  AMG_ERR_COARSE_TOO_LARGE = -7     /* coarsening stalled above the dense coarse-solve limit */
+  AMG_ERR_COARSE_TOO_LARGE = -7,    /* coarsening stalled above the dense coarse-solve limit */
+  AMG_ERR_SCRATCH_LIMIT = -8        /* the system exceeds the static workspace of amg_solve_noalloc */
 } amg_status;
 
 enum { AMG_PREC_FP64 = 0, AMG_PREC_FP32 = 1 };
@@ -244,6 +245,34 @@ amg_status amg_pattern_grad_batched(amg_handle h, const double* d_lambda, const 
 /* One V-cycle z = M^-1 r on the fine level (FP64 in and out, the handle's
  * cycle precision inside): the preconditioner as an operator. */
 amg_status amg_apply_vcycle(amg_handle h, const double* d_r, double* d_z, hipStream_t stream);
+
+/* Allocation-free PCG solve, for callers that cannot allocate device memory
+ * (code recorded under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  It computes what amg_solve(h, d_b, d_x, tol, 1, info,
+ * stream) computes with use_graphs = 0 -- the same kernels in the same order,
+ * so the same x bit for bit -- but its Krylov workspace (residual r,
+ * preconditioned residual z, the two direction buffers, q = A p, the
+ * per-workgroup partial sums and the device control block) lives in one
+ * static device array of AMG_NOALLOC_SCRATCH_BYTES per GPU instead of the
+ * handle's buffers.  That array is part of the library's code object: each
+ * GPU the library runs on holds it from the library's load until the
+ * process ends.  The call makes no hipMalloc, hipFree, graph or other
+ * allocating call; it synchronises the stream between iteration chunks like
+ * amg_solve.  Each call clears the part of the array that must start at
+ * zero; contents otherwise persist from the previous call.
+ * Limits: a PCG handle (solver = AMG_SOLVER_PCG) of one system, one
+ * right-hand side, n <= AMG_NOALLOC_MAX_N rows and at most
+ * AMG_NOALLOC_MAX_PARTIALS partial-sum slots (level-0 sweep grids of a few
+ * hundred thousand workgroups); a larger system returns
+ * AMG_ERR_SCRATCH_LIMIT before anything is launched, another solver or width
+ * AMG_ERR_INVALID_ARG.  Every call on a GPU uses that GPU's one array: calls
+ * that overlap on one GPU (any handles, any streams, any threads) race and
+ * must be serialised by the caller. */
+#define AMG_NOALLOC_MAX_N 2097152
+#define AMG_NOALLOC_MAX_PARTIALS 1048576
+#define AMG_NOALLOC_SCRATCH_BYTES (256 + 8 * (size_t)AMG_NOALLOC_MAX_PARTIALS + 5 * 8 * (size_t)AMG_NOALLOC_MAX_N)
+amg_status amg_solve_noalloc(amg_handle h, const double* d_b, double* d_x, double tol, amg_info* info,
+                             hipStream_t stream);
 
 /* ---- matrix-free operators (Section 2.1, "Matrix-free operator support") ----
  * An operator given as a callable x -> A x with a known CSR pattern is

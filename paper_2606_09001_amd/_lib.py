@@ -20,6 +20,8 @@ AMG_ERR_BREAKDOWN = -4
 AMG_ERR_OOM = -5
 AMG_ERR_HIP = -6
 AMG_ERR_COARSE_TOO_LARGE = -7
+AMG_ERR_SCRATCH_LIMIT = -8
+AMG_NOALLOC_MAX_N = 2097152
 
 AMG_PREC_FP64 = 0
 AMG_PREC_FP32 = 1
@@ -40,7 +42,7 @@ EXPORTS = [
     "amg_apply_vcycle", "amg_hierarchy_stats", "amg_field_info", "amg_export_field", "amg_destroy", "amg_finalize",
     "amg_cache_size", "amg_set_cache_capacity", "amg_status_string", "amg_instrument", "amg_instrument_read",
     "amg_kernel_bytes", "amg_pattern_grad_batched", "amg_solve_columns", "amg_color_columns",
-    "amg_probe_vectors", "amg_probe_assemble", "amg_probe_scatter", "amg_convert_bf16",
+    "amg_probe_vectors", "amg_probe_assemble", "amg_probe_scatter", "amg_convert_bf16", "amg_solve_noalloc",
     "amg_kernel_bytes_batched",
 ]
 
@@ -106,6 +108,7 @@ def load():
     L.amg_setup.argtypes = [C.POINTER(amg_params), i32, i64, vp, vp, vp, i32, vp, C.POINTER(vp)]
     L.amg_update_values.argtypes = [vp, vp, vp]
     L.amg_solve.argtypes = [vp, vp, vp, dbl, i32, C.POINTER(amg_info), vp]
+    L.amg_solve_noalloc.argtypes = [vp, vp, vp, dbl, C.POINTER(amg_info), vp]
     L.amg_solve_adjoint.argtypes = [vp, vp, vp, dbl, i32, C.POINTER(amg_info), vp]
     L.amg_pattern_grad.argtypes = [vp, vp, vp, vp, vp]
     L.amg_apply_vcycle.argtypes = [vp, vp, vp, vp]

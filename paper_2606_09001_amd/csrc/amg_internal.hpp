@@ -274,6 +274,17 @@ struct Hierarchy {
   ~Hierarchy();
 };
 
+// Krylov workspace of one single-column PCG solve: the level-0 vectors, the
+// per-workgroup partial sums, the device control block and a host copy of
+// the control block.  Taken from the hierarchy's own buffers (solve_work) or
+// from the static array of the allocation-free solve.
+struct SolveWork {
+  double *r, *z, *p, *z2, *q, *partials;
+  Ctl* ctl;
+  Ctl* h_ctl;
+  bool graphs;  // hipGraph replay allowed (capture and instantiation allocate)
+};
+
 // Solve-time options carried by each handle.
 struct SolveOpts {
   int maxiter;
@@ -281,6 +292,17 @@ struct SolveOpts {
   int check_every;  // 0 auto
   int use_graphs;   // replay captured iterations
 };
+
+}  // namespace amg
+
+// A caller's reference on a (possibly shared) hierarchy, with its own
+// solve-time options.
+struct amg_handle_s {
+  amg::Hierarchy* H;
+  amg::SolveOpts opts;
+};
+
+namespace amg {
 
 // setup.hip
 void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const double* d_val, hipStream_t s);
@@ -311,13 +333,17 @@ void probe_scatter(int n, const int* rp, const int* ci, const int* color, int nc
 void coarse_setup(Hierarchy& H, hipStream_t s);
 // solve.hip
 void alloc_solve_workspace(Hierarchy& H);
+// Partial-sum slots a solve on H needs (the largest reducing grid, times the
+// reductions per sweep, plus slack).
+int64_t solve_partials_count(const Hierarchy& H);
+SolveWork solve_work(Hierarchy& H);
 // Persistent tuning cache (in memory and, when AMG_TUNE_CACHE names a file,
 // in a text file): lookup and record of a launch choice under a key.
 bool tune_lookup(const std::string& key, Shape* out);
 void tune_record(const std::string& key, const Shape& sh);
 
-amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int nrhs,
-                     amg_info* info, hipStream_t s);
+amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const SolveWork& w, const double* d_b, double* d_x,
+                     double tol, amg_info* info, hipStream_t s);
 amg_status bicgstab_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol,
                           amg_info* info, hipStream_t s);
 void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s);

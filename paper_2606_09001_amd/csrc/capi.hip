@@ -17,13 +17,6 @@
 
 #include "amg_internal.hpp"
 
-// A caller's reference on a (possibly shared) hierarchy, with its own
-// solve-time options.
-struct amg_handle_s {
-  amg::Hierarchy* H;
-  amg::SolveOpts opts;
-};
-
 namespace amg {
 
 void Graphs::reset() {
@@ -441,7 +434,7 @@ amg_status amg_solve(amg_handle h, const double* d_b, double* d_x, double tol, i
       return bicgstab_columns(H, h->opts, d_b, d_x, tol, nrhs, info, stream, H.bt);
     }
     if (nrhs > 1 || H.S > 1) return pcg_solve_wide(H, h->opts, d_b, d_x, tol, nrhs, info, stream);
-    return pcg_solve(H, h->opts, d_b, d_x, tol, nrhs, info, stream);
+    return pcg_solve(H, h->opts, solve_work(H), d_b, d_x, tol, info, stream);
   });
 }
 
@@ -748,6 +741,7 @@ const char* amg_status_string(amg_status s) {
     case AMG_ERR_OOM: return "AMG_ERR_OOM";
     case AMG_ERR_HIP: return "AMG_ERR_HIP";
     case AMG_ERR_COARSE_TOO_LARGE: return "AMG_ERR_COARSE_TOO_LARGE";
+    case AMG_ERR_SCRATCH_LIMIT: return "AMG_ERR_SCRATCH_LIMIT";
   }
   return "AMG_UNKNOWN_STATUS";
 }

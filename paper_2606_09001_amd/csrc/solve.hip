@@ -1508,6 +1508,16 @@ void choose_shapes(Hierarchy& H, hipStream_t s) {
   AMG_HIP(hipStreamSynchronize(s));
 }
 
+int64_t solve_partials_count(const Hierarchy& H) {
+  int64_t np = std::max<int64_t>(vec_grid(H.n), H.lv[0].shA.grid);
+  np = std::max<int64_t>(np, vec_grid(H.co.n));
+  return np * 4 + 64;
+}
+
+SolveWork solve_work(Hierarchy& H) {
+  return SolveWork{H.r.p, H.z.p, H.p.p, H.z2.p, H.q.p, H.partials.p, H.ctl.p, H.h_ctl, true};
+}
+
 void alloc_solve_workspace(Hierarchy& H) {
   const int n = H.n;
   H.r.alloc(n);
@@ -1515,9 +1525,7 @@ void alloc_solve_workspace(Hierarchy& H) {
   H.p.alloc(n);
   H.z2.alloc(n);
   H.q.alloc(n);
-  int64_t np = std::max<int64_t>(vec_grid(n), H.lv[0].shA.grid);
-  np = std::max<int64_t>(np, vec_grid(H.co.n));
-  H.partials.alloc(np * 4 + 64);
+  H.partials.alloc(solve_partials_count(H));
   if (!H.ctl.p) {
     H.ctl.alloc(1);
     AMG_HIP(hipMemset(H.ctl.p, 0, sizeof(Ctl)));
@@ -1648,17 +1656,22 @@ void pattern_grad(Hierarchy& H, const double* d_lam, const double* d_x, double* 
 }
 
 template <class T>
-void launch_cg_update(Hierarchy& H, int n, double* d_x, const double* p, Ctl* ctl, double* part, hipStream_t s) {
+void launch_cg_update(Hierarchy& H, const SolveWork& w, int n, double* d_x, const double* p, hipStream_t s) {
   Level& L0 = H.lv[0];
-  hipLaunchKernelGGL((k_cg_update<T>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, d_x, H.r.p, p, H.q.p,
-                     Bufs<T>::sw(L0), Bufs<T>::x(L0), ctl, part);
+  hipLaunchKernelGGL((k_cg_update<T>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, d_x, w.r, p, w.q,
+                     Bufs<T>::sw(L0), Bufs<T>::x(L0), w.ctl, w.partials);
 }
 
 template <class T>
-void launch_sw_mul(Hierarchy& H, int n, const Ctl* ctl, hipStream_t s) {
+void launch_sw_mul(Hierarchy& H, const SolveWork& w, int n, hipStream_t s) {
   Level& L0 = H.lv[0];
-  hipLaunchKernelGGL((k_sw_mul<T>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, Bufs<T>::sw(L0), H.r.p,
-                     Bufs<T>::x(L0), ctl);
+  hipLaunchKernelGGL((k_sw_mul<T>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, Bufs<T>::sw(L0), w.r,
+                     Bufs<T>::x(L0), w.ctl);
+}
+
+void read_ctl(const SolveWork& w, hipStream_t s) {
+  AMG_HIP(hipMemcpyAsync(w.h_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
 }
 
 // Captures the launches made by `body` on stream s into an executable graph;
@@ -1696,9 +1709,8 @@ void graph_stream(Hierarchy& H) {
   }
 }
 
-amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int nrhs,
-                     amg_info* info, hipStream_t caller) {
-  if (nrhs != 1) throw Error(AMG_ERR_INVALID_ARG, "this entry point takes one right-hand side");
+amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const SolveWork& w, const double* d_b, double* d_x,
+                     double tol, amg_info* info, hipStream_t caller) {
   auto t0 = std::chrono::steady_clock::now();
   Level& L0 = H.lv[0];
   const int n = H.n;
@@ -1706,7 +1718,7 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
   // automatic: flexible whenever the preconditioner is not a fixed symmetric
   // operator (FP32 cycle, or unequal pre/post sweep counts)
   const int flexible = o.flexible < 0 ? ((H.fp32() || H.prm.nu_pre != H.prm.nu_post) ? 1 : 0) : o.flexible;
-  const bool graphs = o.use_graphs && H.inst.kernel < 0;
+  const bool graphs = w.graphs && o.use_graphs && H.inst.kernel < 0;
   hipStream_t s = caller;
   if (graphs) {
     graph_stream(H);
@@ -1720,32 +1732,32 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
       H.gr.key_w = 1;
     }
   }
-  Ctl* ctl = H.ctl.p;
-  double* part = H.partials.p;
+  Ctl* ctl = w.ctl;
+  double* part = w.partials;
   const int gv = vec_grid(n);
-  hipLaunchKernelGGL(k_cg_init, dim3(gv), dim3(kBlock), 0, s, n, d_b, H.r.p, d_x, part);
+  hipLaunchKernelGGL(k_cg_init, dim3(gv), dim3(kBlock), 0, s, n, d_b, w.r, d_x, part);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, s, ctl, part, gv, tol, o.maxiter, flexible);
   AMG_HIP(hipGetLastError());
   // search directions alternate between two buffers (the fused direction
   // update writes the new p while neighbours still gather the old one)
-  double* pb[2] = {H.p.p, H.z2.p};
+  double* pb[2] = {w.p, w.z2};
   int cur = 0;
   // one PCG iteration: p = z + beta p and q = A p; alpha; x, r update; z = M^-1 r, beta
   auto iteration = [&](int first, int c, hipStream_t st) {
     int np;
     {
       InstScope is(H, KID_SPMV_DOT, 0, st, ctl);
-      np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpSpmvXpayDev{L0.av(), H.z.p, pb[c], pb[c ^ 1], H.q.p, ctl, first},
+      np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpSpmvXpayDev{L0.av(), w.z, pb[c], pb[c ^ 1], w.q, ctl, first},
                  ctl, part, st);
     }
     hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinBlock), 0, st, ctl, part, np);
     {
       InstScope is(H, KID_CG_UPDATE, 0, st, ctl);
-      if (H.fp32()) launch_cg_update<float>(H, n, d_x, pb[c ^ 1], ctl, part, st);
-      else launch_cg_update<double>(H, n, d_x, pb[c ^ 1], ctl, part, st);
+      if (H.fp32()) launch_cg_update<float>(H, w, n, d_x, pb[c ^ 1], st);
+      else launch_cg_update<double>(H, w, n, d_x, pb[c ^ 1], st);
     }
     hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(kFinBlock), 0, st, ctl, part, gv);
-    CycleArgs a{H.r.p, H.z.p, H.q.p, ctl, part, flexible ? 2 : 1, 0, multi ? 1 : 0};
+    CycleArgs a{w.r, w.z, w.q, ctl, part, flexible ? 2 : 1, 0, multi ? 1 : 0};
     vcycle(H, a, st);
   };
   // two iterations captured once per direction-buffer parity and replayed
@@ -1762,10 +1774,10 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
   for (;;) {
     // (re)start: z = M^-1 r, rz = <r, z>; the first direction is p = z
     if (multi) {
-      if (H.fp32()) launch_sw_mul<float>(H, n, ctl, s);
-      else launch_sw_mul<double>(H, n, ctl, s);
+      if (H.fp32()) launch_sw_mul<float>(H, w, n, s);
+      else launch_sw_mul<double>(H, w, n, s);
     }
-    CycleArgs a0{H.r.p, H.z.p, H.q.p, ctl, part, 1, 1, multi ? 1 : 0};
+    CycleArgs a0{w.r, w.z, w.q, ctl, part, 1, 1, multi ? 1 : 0};
     vcycle(H, a0, s);
     int first = 1;
     // Iterations are queued in chunks; between chunks the host reads the
@@ -1790,10 +1802,10 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
         cur ^= 1;
       }
       AMG_HIP(hipGetLastError());
-      read_ctl(H, s);
-      if (H.h_ctl->done) break;
+      read_ctl(w, s);
+      if (w.h_ctl->done) break;
       if (o.check_every <= 0) {
-        const Ctl& c = *H.h_ctl;
+        const Ctl& c = *w.h_ctl;
         if (it_prev < 0) {  // decay measured from ||r_0||^2 = ||b||^2
           it_prev = 0;
           rr_prev = c.bb;
@@ -1811,17 +1823,17 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
         chunk = std::max(1, std::min(next, 32));
       }
     }
-    const int state = H.h_ctl->state;
+    const int state = w.h_ctl->state;
     if (state == 3) break;  // b = 0
     if (state < 0) {
       st = AMG_ERR_BREAKDOWN;
       break;
     }
     // true residual r = b - A x
-    const int np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpTrueResid{L0.av(), d_x, d_b, H.r.p}, nullptr, part, s);
+    const int np = sweep(L0.shA, n, L0.arp(), L0.aci(), OpTrueResid{L0.av(), d_x, d_b, w.r}, nullptr, part, s);
     hipLaunchKernelGGL(k_fin_trr, dim3(1), dim3(kFinBlock), 0, s, ctl, part, np);
-    read_ctl(H, s);
-    const Ctl& c = *H.h_ctl;
+    read_ctl(w, s);
+    const Ctl& c = *w.h_ctl;
     if (c.trr <= c.thresh) {
       st = AMG_OK;
       break;
@@ -1838,7 +1850,7 @@ amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const double* d_b, double
     AMG_HIP(hipEventRecord(H.gr.ev_out, s));
     AMG_HIP(hipStreamWaitEvent(caller, H.gr.ev_out, 0));
   }
-  const Ctl& c = *H.h_ctl;
+  const Ctl& c = *w.h_ctl;
   if (info) {
     info->iters = c.iters;
     info->status = st;
