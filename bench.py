@@ -48,7 +48,7 @@ def traffic_from_profiles(kernel_tag: str, src_hash: str):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("solve.hip", "amg_internal.hpp"):
+    for name in ("solve.hip", "batch.hip", "amg_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2606_09001_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -62,16 +62,34 @@ def kernel_source_hash():
 # scaled by what the same counter reads for the calibration kernel (a negation
 # of CALIB_MIB MiB: that many bytes read and written).
 
-FINE_KERNELS = {  # tag -> (regex on the demangled name); level 0 = the largest grid
-    "spmv_dot_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpSpmvXpayDev>",
-    "pre_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpResid<double, double> >",
-    "post_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpPost<double, double, double, 1> >",
+_SWEEP = r"k_(?:stream<\d+, |sell<|sello<)[^>]*"
+FINE_KERNELS = {  # tag -> (regex on the demangled name, grid rank: 0 = largest grid = level 0)
+    "spmv_dot_L0": (_SWEEP + r"OpSpmvXpayDev>", 0),
+    "pre_L0": (_SWEEP + r"OpResid<double, double> >", 0),
+    "post_L0": (_SWEEP + r"OpPost<double, double, double, 1> >", 0),
+    "restrict_L0": (_SWEEP + r"OpRestrict<double, double> >", 0),
+    "prolong_L0": (_SWEEP + r"OpProlong<double, double> >", 0),
+    "pre_L1": (_SWEEP + r"OpResid<double, double> >", 1),
+    "post_L1": (_SWEEP + r"OpPost<double, double, double, 0> >", 0),
+    "restrict_L1": (_SWEEP + r"OpRestrict<double, double> >", 1),
+    "prolong_L1": (_SWEEP + r"OpProlong<double, double> >", 1),
+}
+_WIDE = r"k_wide(?:_st)?<\d+, [^>]*"
+# level-0 sweeps of the batched solves (FP64 cycle).  Their grids are the
+# resident workgroup count on every level, so level 0 is told apart by size:
+# the dispatches within 60 % of the kernel's largest (duration or counter).
+WIDE_KERNELS = {
+    "wide_spmv_dot_L0": (_WIDE + r"WSpmvXpay<", "top"),
+    "wide_pre_L0": (_WIDE + r"WResid<(?:true|false), double, double> >", "top"),
+    "wide_post_L0": (_WIDE + r"WPost<(?:true|false), double, double, double, 1> >", "top"),
+    "wide_restrict_L0": (_WIDE + r"WRestrict<(?:true|false), double, double> >", "top"),
+    "wide_prolong_L0": (_WIDE + r"WProlong<(?:true|false), double, double> >", "top"),
 }
 BICG_KERNELS = {  # the BiCGSTAB solve's level-0 sweeps (FP64 cycle)
-    "A_y_dot_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpSpmvDots<1> >",
-    "A_z_dots_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpSpmvDots<2> >",
-    "pre_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpResid<double, double> >",
-    "post_L0": r"k_(?:stream<\d+, |sell<|sello<)[^>]*OpPost<double, double, double, 0> >",
+    "A_y_dot_L0": (_SWEEP + r"OpSpmvDots<1> >", 0),
+    "A_z_dots_L0": (_SWEEP + r"OpSpmvDots<2> >", 0),
+    "pre_L0": (_SWEEP + r"OpResid<double, double> >", 0),
+    "post_L0": (_SWEEP + r"OpPost<double, double, double, 0> >", 0),
 }
 
 
@@ -85,23 +103,39 @@ def _csv_rows(d, suffix):
     return rows
 
 
-def _working(durs):
+def _working(durs, spec=None):
     """Dispatches that did work: launches queued past convergence return at
-    once (a few microseconds) and are left out, as in the in-solve timing."""
+    once (a few microseconds) and are left out, as in the in-solve timing.
+    For kernels whose level is told apart by size, the level-0 dispatches."""
     if not durs:
         return []
+    if spec is not None and spec[1] == "top":
+        return [d for d in durs if d >= 0.6 * max(durs)]
     top = sorted(durs)[int(0.9 * (len(durs) - 1))]
     return [d for d in durs if d > 0.3 * top]
 
 
-def _level0(rows, pattern, grid_key):
+def _by_grid(rows, spec, grid_key):
+    """Dispatches of one kernel at one level: the kernel's launches whose grid
+    is the rank-th largest of its distinct grids (level 0 has the largest)."""
     import re
+    pattern, rank = spec
     rx = re.compile(pattern)
     sel = [r for r in rows if rx.search(r["Kernel_Name"])]
-    if not sel:
+    if rank == "top":
+        return sel
+    grids = sorted({int(r[grid_key]) for r in sel}, reverse=True)
+    if len(grids) <= rank:
         return []
-    g = max(int(r[grid_key]) for r in sel)
-    return [r for r in sel if int(r[grid_key]) == g]
+    return [r for r in sel if int(r[grid_key]) == grids[rank]]
+
+
+def profile_table(tag):
+    if "bicgstab" in tag:
+        return BICG_KERNELS
+    if "batched" in tag or "_x" in tag:
+        return WIDE_KERNELS
+    return FINE_KERNELS
 
 
 def summarize_profiles(a):
@@ -116,13 +150,13 @@ def summarize_profiles(a):
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:24]:
         lines.append(f"{int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['AverageNs']) / 1e3:9.2f} "
                      f"{float(r['MinNs']) / 1e3:8.2f} {float(r['MaxNs']) / 1e3:8.2f}  {r['Name'][:150]}")
-    lines += ["", "level-0 sweeps, FP64 solve (largest grid of each kernel; working dispatches only):"]
+    lines += ["", "sweeps by level, FP64 solve (level 0 = the largest grid of each kernel; working dispatches only):"]
     summary = {}
-    table = BICG_KERNELS if "bicgstab" in tag else FINE_KERNELS
+    table = profile_table(tag)
     for k, pat in table.items():
-        sel = _level0(trace, pat, "Grid_Size_X")
+        sel = _by_grid(trace, pat, "Grid_Size_X")
         durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
-        w = _working(durs)
+        w = _working(durs, pat)
         if not w:
             continue
         summary[k] = dict(dispatches=len(durs), working=len(w), avg_us=sum(w) / len(w), min_us=min(w), max_us=max(w))
@@ -141,10 +175,10 @@ def summarize_profiles(a):
             raise SystemExit(f"no calibration dispatch in {d}")
         factor = max(calib) / (CALIB_MIB * 1024.0)   # counter KiB per known KiB
         res = {}
-        for k, pat in FINE_KERNELS.items():
-            sel = _level0(rows, pat, "Grid_Size")
+        for k, pat in profile_table(tag).items():
+            sel = _by_grid(rows, pat, "Grid_Size")
             vals = [float(r["Counter_Value"]) for r in sel]
-            w = _working(vals)
+            w = _working(vals, pat)
             if w:
                 res[k] = dict(kib=sum(w) / len(w), n=len(w), bytes=sum(w) / len(w) / factor * 1024.0)
         return factor, res
@@ -156,7 +190,7 @@ def summarize_profiles(a):
            f"calibration: negation of {CALIB_MIB} MiB (reads and writes {CALIB_MIB * 1024} KiB); "
            f"FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f} (counter KiB per byte-exact KiB)", "",
            f"{'kernel':12s} {'FETCH KiB':>12} {'WRITE KiB':>12} {'traffic MB':>11}  dispatches"]
-    for k in FINE_KERNELS:
+    for k in profile_table(tag):
         if k not in fetch or k not in write:
             continue
         traffic = fetch[k]["bytes"] + write[k]["bytes"]
@@ -167,7 +201,7 @@ def summarize_profiles(a):
                        "write_kib_per_dispatch": write[k]["kib"], "fetch_factor": ff, "write_factor": wf,
                        "traffic_bytes_per_launch": round(traffic), "commands": [a.cmd_fetch, a.cmd_write],
                        "working_avg_us_from_trace": summary.get(k, {}).get("avg_us")}, f, indent=1)
-    txt.append(f"\nkernel source sha256 (solve.hip + amg_internal.hpp): {src}")
+    txt.append(f"\nkernel source sha256 (solve.hip + batch.hip + amg_internal.hpp): {src}")
     with open(os.path.join(out_dir, f"{tag}_pmc.txt"), "w") as f:
         f.write("\n".join(txt) + "\n")
     print("\n".join(txt))
@@ -441,22 +475,38 @@ def run_small(args, dev):
     n = len(rp) - 1
     d = [torch.from_numpy(a).to(dev) for a in (rp, ci, v, M.rhs_normal(n, 0))]
     x = torch.empty(n, dtype=torch.float64, device=dev)
-    H = AmgHierarchy(d[0], d[1], d[2])
-    _, info = H.solve(d[3], 1e-10, out=x)
-    torch.cuda.synchronize()
     k = 50
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(k):
+    out = {"workload": "2D Poisson 5-point 32^2 (1024 unknowns), b ~ N(0,1) seed 0, tol 1e-10, FP64"}
+    xs = {}
+    for fused in (1, 0):
+        # fused: the whole solve as one workgroup (hierarchy small enough); 0: per-kernel path
+        H = AmgHierarchy(d[0], d[1], d[2], fused_small=fused)
         _, info = H.solve(d[3], 1e-10, out=x)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / k
-    log(f"poisson 32^2: {ms * 1e3:.0f} us/solve ({1e3 / ms:.0f} solves/s), iters {info['iters']}")
-    H.close()
-    out = {"workload": "2D Poisson 5-point 32^2 (1024 unknowns), b ~ N(0,1) seed 0, tol 1e-10, FP64",
-           "ms_per_solve": round(ms, 4), "solves_per_s": round(1e3 / ms, 1), "iters": info["iters"],
-           "rel_resid": info["rel_resid"]}
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(k):
+            _, info = H.solve(d[3], 1e-10, out=x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / k
+        xs[fused] = x.cpu().numpy().copy()
+        tag = "one workgroup" if fused else "per-kernel"
+        log(f"poisson 32^2 {tag}: {ms * 1e3:.0f} us/solve ({1e3 / ms:.0f} solves/s), iters {info['iters']}")
+        r = {"ms_per_solve": round(ms, 4), "solves_per_s": round(1e3 / ms, 1), "iters": info["iters"],
+             "rel_resid": info["rel_resid"], "single_workgroup": H.stats()["single_workgroup"]}
+        if fused:
+            out.update(r)
+        else:
+            out["per_kernel_path"] = r
+        H.close()
+    if not args.no_oracle_errors:
+        import oracle
+        rp_, ci_, v_ = (a_.cpu().numpy() for a_ in d[:3])
+        xo, io = oracle.OracleHierarchy(rp_, ci_, v_).pcg(d[3].cpu().numpy(), tol=1e-10)
+        nx = np.linalg.norm(xo)
+        out["vs_oracle"] = {"oracle_iters": io["iters"], "err_fp64": float(np.linalg.norm(xs[1] - xo) / nx),
+                            "err_fp64_per_kernel": float(np.linalg.norm(xs[0] - xo) / nx)}
     # Section 3.1's example: b = 1, tol 1e-6, BiCGSTAB with and without the AMG preconditioner
     ones = torch.ones(n, dtype=torch.float64, device=dev)
     sec = {}

@@ -95,6 +95,11 @@ typedef struct {
                           BiCGSTAB; the setup keeps level 0 only; one right-hand side and one system) */
   int solver;          /* AMG_SOLVER_PCG (default) or AMG_SOLVER_BICGSTAB (right-preconditioned
                           BiCGSTAB; one right-hand side and one system) */
+  int fused_small;     /* 1 (default): a PCG solve of one right-hand side on a hierarchy small enough for
+                          one compute unit (two levels, <= 1024 fine rows of <= 8 entries, dense coarsest
+                          level <= 256 rows, FP64 V(1,1) cycle) runs as a single workgroup in one launch
+                          (vectors in LDS, q = A p formed directly); 0: always the per-kernel path.  A
+                          solve-time option (not part of the cache key) */
 } amg_params;
 
 typedef struct {
@@ -123,6 +128,7 @@ typedef struct {
   int group_r[AMG_MAX_LEVELS];
   int form_a[AMG_MAX_LEVELS];        /* sweep form over A_l: 0 lanes-per-row, 1 CSR-stream, 2 sliced */
   int64_t sliced_len[AMG_MAX_LEVELS]; /* stored entries of the sliced copy of A_l (0: none) */
+  int single_workgroup;              /* 1: small enough for the one-workgroup PCG solve (fused_small) */
 } amg_hier_stats;
 
 /* Fields of a level that amg_export_field can copy out (for bit-exact checks). */

@@ -55,7 +55,7 @@ class amg_params(C.Structure):
         ("max_levels", C.c_int), ("smoother", C.c_int), ("omega", C.c_double), ("nu_pre", C.c_int),
         ("nu_post", C.c_int), ("maxiter", C.c_int), ("flexible", C.c_int), ("symmetric", C.c_int),
         ("check_every", C.c_int), ("use_graphs", C.c_int), ("autotune", C.c_int), ("precondition", C.c_int),
-        ("solver", C.c_int),
+        ("solver", C.c_int), ("fused_small", C.c_int),
     ]
 
 
@@ -79,11 +79,13 @@ class amg_hier_stats(C.Structure):
         ("num_levels", C.c_int), ("n", _L20), ("nnz", _L20), ("nnz_p", _L20), ("nnz_g", _L20), ("rho", _D20),
         ("omega_p", _D20), ("mis_rounds", _I20), ("operator_complexity", C.c_double), ("group_a", _I20),
         ("group_p", _I20), ("group_r", _I20), ("form_a", _I20), ("sliced_len", _L20),
+        ("single_workgroup", C.c_int),
     ]
 
     def to_dict(self):
         L = self.num_levels
-        d = {"num_levels": L, "operator_complexity": self.operator_complexity}
+        d = {"num_levels": L, "operator_complexity": self.operator_complexity,
+             "single_workgroup": self.single_workgroup}
         for f in ("n", "nnz", "nnz_p", "nnz_g", "rho", "omega_p", "mis_rounds", "group_a", "group_p", "group_r",
                   "form_a", "sliced_len"):
             d[f] = list(getattr(self, f))[:L]

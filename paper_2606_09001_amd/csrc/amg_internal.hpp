@@ -68,6 +68,8 @@ struct DBuf {
 struct Shape {
   int stream = 1;  // 1: CSR-stream, 0: lanes-per-row, 2: sliced (thread per row), 3: sliced, slot offsets
   int g = 1;
+  int u = 8;       // CSR-stream: staged entries per thread (buffer of kBlock*u entries)
+  int nt = 0;      // 1: the operator's entry stream is read with nontemporal loads
   int rows_per_block = 256;
   int grid = 1;
   int max_block_nnz = 0;
@@ -167,7 +169,7 @@ struct Ctl {
   int done;               // nonzero: kernels of the current solve return at once
   int state;              // 0 running, 1 converged (recursive), 2 iteration limit, -1 breakdown
   int flexible;
-  int pad_;
+  int restarts;           // true-residual restarts (single-workgroup solve)
 };
 
 // Kernels that can be timed inside real solves (event pairs around every
@@ -267,6 +269,10 @@ struct Hierarchy {
   // status of a value refresh that failed part-way (the levels then hold a
   // mix of old and new values): solves refuse with it until a refresh succeeds
   amg_status broken = AMG_OK;
+  // single-workgroup solve (small.hip): lanes per R_0 row as a power-of-two
+  // exponent, -1 when the hierarchy is not small enough
+  int small_lgR = -1;
+  bool small_checked = false;
   int cache_event = AMG_CACHE_COLD;
   double setup_ms = 0.0;
   bool fp32() const { return prm.vcycle_prec == AMG_PREC_FP32; }
@@ -291,6 +297,7 @@ struct SolveOpts {
   int flexible;     // -1 auto
   int check_every;  // 0 auto
   int use_graphs;   // replay captured iterations
+  int fused_small;  // run small hierarchies' solves in one workgroup
 };
 
 }  // namespace amg
@@ -350,6 +357,10 @@ void apply_vcycle(Hierarchy& H, const double* d_r, double* d_z, hipStream_t s);
 void pattern_grad(Hierarchy& H, const double* d_lam, const double* d_x, double* d_g, hipStream_t s);
 void graph_stream(Hierarchy& H);
 void capture_graph(hipStream_t s, hipGraphExec_t& ex, const std::function<void()>& body);
+// small.hip
+bool small_solve_ok(Hierarchy& H);
+amg_status pcg_solve_small(Hierarchy& H, const SolveOpts& o, const SolveWork& w, const double* d_b, double* d_x,
+                           double tol, amg_info* info, hipStream_t s);
 // batch.hip
 amg_status pcg_solve_wide(Hierarchy& H, const SolveOpts& o, const double* d_b, double* d_x, double tol, int W,
                           amg_info* info, hipStream_t s);
@@ -366,7 +377,11 @@ void read_instrument(Hierarchy& H, int* launches, double* total_ms, double* min_
 
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kMaxGrid = 2048;     // blocks of grid-stride kernels
-constexpr int kStreamCap = 2048;   // nonzeros a stream workgroup stages in LDS
+constexpr int kStreamCap = 3072;   // most nonzeros a stream workgroup stages in LDS
+// Last-level (Infinity) cache of the device: an operator whose entry stream
+// is larger than this is read with nontemporal loads (it cannot stay cached
+// between its sweeps, and caching it would only evict the gathered vectors).
+constexpr double kLlcBytes = 256.0 * 1024 * 1024;
 constexpr int kVecPer = 4;         // vector elements per thread in BLAS1 kernels
 constexpr int kFinBlock = 1024;    // threads of the single-workgroup finalize kernels
 constexpr int kMaxWidth = 64;       // columns of a batched solve (right-hand sides or systems)
@@ -415,6 +430,13 @@ template <>
 struct ValCvt<uint16_t> { __device__ static float f(uint16_t v) { return bf16_to_f32(v); } };
 
 #ifdef __HIPCC__
+// Load of an operator's entry stream, nontemporal when NT.
+template <bool NT, class T>
+__device__ inline T stream_load(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 // Row-shift DPP move of a double within rows of 16 lanes (lanes shifted in
 // from outside the row read 0).
 template <int SHIFT>

@@ -43,16 +43,18 @@ inline int wide_grid(int64_t n, int LW) {
   return (int)std::max<int64_t>(g, 1);
 }
 
-// Value of stored entry k for column c.
+// Value of stored entry k for column c.  The per-system value arrays
+// ([entry][S]) are streamed once per sweep and are many times larger than
+// the last-level cache: nontemporal loads.
 template <bool SYS, class V>
 __device__ inline V val_at(const V* v, int k, int c, int W) {
-  if constexpr (SYS) return v[(int64_t)k * W + c];
+  if constexpr (SYS) return stream_load<true>(v + (int64_t)k * W + c);
   else return v[k];
 }
 // Per-row quantity (smoother weight) for column c.
 template <bool SYS, class V>
 __device__ inline V row_at(const V* v, int i, int c, int W) {
-  if constexpr (SYS) return v[(int64_t)i * W + c];
+  if constexpr (SYS) return stream_load<true>(v + (int64_t)i * W + c);
   else return v[i];
 }
 
@@ -698,7 +700,7 @@ __global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int b
           for (int u = 0; u < 8; ++u) {
             const int k = min(kb + u, e - 1);
             VT val;
-            if constexpr (SYS) val = op.v[(int64_t)(k0 + k) * W + c];
+            if constexpr (SYS) val = stream_load<true>(op.v + (int64_t)(k0 + k) * W + c);
             else val = s_v[k];
             pr[u] = op.prod_v(val, s_ci[k], c);
           }

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libamg355.so")
-SOURCES = ["setup.hip", "coarse.hip", "solve.hip", "batch.hip", "probe.hip", "capi.hip", "noalloc.hip"]
+SOURCES = ["setup.hip", "coarse.hip", "solve.hip", "batch.hip", "probe.hip", "capi.hip", "noalloc.hip", "small.hip"]
 BUILD_DIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

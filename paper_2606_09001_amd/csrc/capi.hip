@@ -122,6 +122,7 @@ amg_status check_params(const amg_params& p) {
   if (p.symmetric != 0 && p.symmetric != 1) return AMG_ERR_INVALID_ARG;
   if (p.precondition != 0 && p.precondition != 1) return AMG_ERR_INVALID_ARG;
   if (p.solver != AMG_SOLVER_PCG && p.solver != AMG_SOLVER_BICGSTAB) return AMG_ERR_INVALID_ARG;
+  if (p.fused_small != 0 && p.fused_small != 1) return AMG_ERR_INVALID_ARG;
   // CG needs A = A^T; a nonsymmetric A is solved by BiCGSTAB
   if (!p.symmetric && p.solver != AMG_SOLVER_BICGSTAB) return AMG_ERR_INVALID_ARG;
   return AMG_OK;
@@ -279,6 +280,7 @@ void amg_params_default(amg_params* p) {
   p->autotune = 0;
   p->precondition = 1;
   p->solver = AMG_SOLVER_PCG;
+  p->fused_small = 1;
 }
 
 amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
@@ -334,7 +336,7 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
         H->setup_ms = ms_since(t0);
       }
       ++H->refs;
-      *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every, prm.use_graphs}};
+      *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every, prm.use_graphs, prm.fused_small}};
       return AMG_OK;
     }
     Hierarchy* H = new Hierarchy;
@@ -362,7 +364,7 @@ amg_status amg_setup(const amg_params* params, int32_t n, int64_t nnz, const int
       g_lru.push_front(H);
       evict_to(g_capacity);
     }
-    *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every, prm.use_graphs}};
+    *out = new amg_handle_s{H, SolveOpts{prm.maxiter, prm.flexible, prm.check_every, prm.use_graphs, prm.fused_small}};
     return AMG_OK;
   });
 }
@@ -584,6 +586,7 @@ amg_status amg_hierarchy_stats(amg_handle h, amg_hier_stats* out) {
     tot += (double)L.nnz;
   }
   out->operator_complexity = tot / (double)H.lv[0].nnz;
+  out->single_workgroup = H.small_checked && H.small_lgR >= 0 ? 1 : 0;
   return AMG_OK;
 }
 

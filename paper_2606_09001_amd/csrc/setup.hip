@@ -1400,6 +1400,8 @@ void build_hierarchy(Hierarchy& H, const int* d_rp, const int* d_ci, const doubl
   alloc_cycle_vectors(H);
   choose_shapes(H, s);
   alloc_solve_workspace(H);
+  H.small_checked = false;
+  small_solve_ok(H);
   AMG_HIP(hipStreamSynchronize(s));
 }
 

@@ -1,0 +1,378 @@
+// Whole-solve PCG in one workgroup, for hierarchies small enough to live in
+// one compute unit: two levels (the fine level and a dense coarsest level),
+// at most 1024 fine rows.  The per-kernel path launches about twenty kernels
+// per iteration, so a 1024-unknown solve is bound by launch and
+// synchronisation latency, not by bytes.  Here one workgroup of 1024 threads
+// (thread i owns fine row i) runs every iteration, restart and the final
+// true-residual check in a single launch:
+//   - the CG vectors and the cycle vectors live in LDS, so every gather of
+//     a sweep is an LDS read;
+//   - each thread keeps its row of A_0 in registers for the whole solve
+//     (A_0 is applied three times per iteration);
+//   - R_0 is read with a group of lanes per coarse row, the explicit coarse
+//     inverse with all threads (column blocks reduced through LDS);
+//   - dot products are fixed-order block reductions (wave butterfly, then the
+//     16 wave sums in order), so a solve is bitwise reproducible.
+// The method is the one of pcg_solve: PCG from x0 = 0, damped-Jacobi (or L1)
+// V(1,1) cycle with R = P^T and the exact coarse solve, recursive-residual
+// stopping, true-residual verification with at most 5 restarts, flexible
+// beta = -<z, q>/<p, q> when requested.  Rows are summed in stored order and
+// q = A p is formed directly.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "amg_internal.hpp"
+
+namespace amg {
+namespace {
+
+constexpr int kST = 1024;        // threads = largest fine level
+constexpr int kSRow = 8;         // entries per row of A_0 and P_0 held in registers
+constexpr int kSCoarse = 256;    // largest padded coarsest level
+constexpr int kSRLane = 8;       // entries of an R_0 row per lane
+
+struct SmallArgs {
+  int n, nc, m, lgR, maxiter, flexible;
+  double tol;
+  const int* arp;
+  const int* aci;
+  const double* av;
+  const double* sw;
+  const int* prp;
+  const int* pci;
+  const double* pv;
+  const int* rrp;
+  const int* rci;
+  const double* rv;
+  const double* inv;
+  const double* b;
+  double* x;
+  Ctl* ctl;
+};
+
+// Keeps the compiler from moving memory operations across this point: the
+// matrix loads of a phase are loop-invariant, and hoisting all of them out
+// of the iteration loop would keep every phase's operands live in registers
+// at once.
+__device__ inline void phase_fence() { asm volatile("" ::: "memory"); }
+
+// Sum of v over the workgroup in a fixed order; every thread gets the total.
+// `red` must not be reused before the next barrier.
+__device__ inline double wg_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll 3
+  for (int k = 1; k < kST / 64; ++k) s += red[k];
+  return s;
+}
+
+__global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
+  __shared__ double s_r[kST], s_z[kST], s_p[kST], s_q[kST], s_xc[kST], s_rc[kST];
+  __shared__ double s_b1[kSCoarse], s_x1[kSCoarse];
+  __shared__ double s_gp[kST];
+  __shared__ double s_red[4][kST / 64];
+  const int t = threadIdx.x;
+  const bool own = t < a.n;
+  const int i = own ? t : a.n - 1;
+  // this thread's rows of A_0 and P_0 (indices clamped into the row; the
+  // entries past the row's length are masked out of every sum)
+  const int ka = a.arp[i];
+  const int na = own ? a.arp[i + 1] - ka : 0;
+  int acol[kSRow];
+  double aval[kSRow];
+#pragma unroll
+  for (int j = 0; j < kSRow; ++j) {
+    const int k = ka + min(j, max(na - 1, 0));
+    acol[j] = a.aci[k];
+    aval[j] = a.av[k];
+  }
+  const int kp = a.prp[i];
+  const int np = own ? a.prp[i + 1] - kp : 0;
+  const double swi = a.sw[i];
+  const double bi = own ? a.b[i] : 0.0;
+  double xi = 0.0;
+  // row i of A_0 applied to an LDS vector, summed in stored order
+  auto arow = [&](const double* v) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSRow; ++j) {
+      const double pr = aval[j] * v[acol[j]];
+      s = j < na ? s + pr : s;
+    }
+    return s;
+  };
+  const int gR = 1 << a.lgR;
+  const int rrow = t >> a.lgR, rl = t & (gR - 1);
+  const int nb = kST / a.m;                       // column blocks of the coarse product
+  const int ic = t % a.m, jb = t / a.m;
+  const int L = (a.nc + nb - 1) / nb;
+
+  // z = M^-1 r (s_r -> s_z); returns <r, z>, and <z, q> in zq when flexible
+  auto vcycle = [&](double& zq) -> double {
+    if (own) s_xc[t] = swi * s_r[t];               // pre-smoothing from zero
+    __syncthreads();
+    if (own) s_rc[t] = s_r[t] - arow(s_xc);        // its residual
+    __syncthreads();
+    {                                              // b_1 = R r_c, gR lanes per coarse row
+      phase_fence();
+      double s = 0.0;
+      if (rrow < a.nc) {
+        const int k0 = a.rrp[rrow], k1 = a.rrp[rrow + 1];
+        int c[kSRLane];
+        double v[kSRLane];
+#pragma unroll
+        for (int u = 0; u < kSRLane; ++u) {
+          const int k = min(k0 + rl + u * gR, k1 - 1);
+          c[u] = a.rci[k];
+          v[u] = a.rv[k];
+        }
+#pragma unroll
+        for (int u = 0; u < kSRLane; ++u) {
+          const double pr = v[u] * s_rc[c[u]];
+          s = k0 + rl + u * gR < k1 ? s + pr : s;
+        }
+      }
+      for (int o = 1; o < gR; o <<= 1) s += __shfl_xor(s, o, 64);
+      if (rrow < a.nc && rl == 0) s_b1[rrow] = s;
+    }
+    __syncthreads();
+    {                                              // x_1 = A_c^-1 b_1: column blocks, then their sum
+      phase_fence();
+      if (jb < nb) {
+        double s = 0.0;
+        if (ic < a.nc) {
+          const int j0 = jb * L, j1 = min(j0 + L, a.nc);
+          for (int jj = j0; jj < j1; jj += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = a.inv[(int64_t)min(jj + u, j1 - 1) * a.m + ic];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const double pr = v[u] * s_b1[min(jj + u, j1 - 1)];
+              s = jj + u < j1 ? s + pr : s;
+            }
+          }
+        }
+        s_gp[jb * a.m + ic] = s;
+      }
+      __syncthreads();
+      if (t < a.nc) {
+        double s = s_gp[t];
+        for (int q = 1; q < nb; ++q) s += s_gp[q * a.m + t];
+        s_x1[t] = s;
+      }
+    }
+    __syncthreads();
+    phase_fence();
+    if (own) {                                     // x_c += P x_1
+      int pcol[kSRow];
+      double pval[kSRow];
+#pragma unroll
+      for (int j = 0; j < kSRow; ++j) {
+        const int k = kp + min(j, max(np - 1, 0));
+        pcol[j] = a.pci[k];
+        pval[j] = a.pv[k];
+      }
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < kSRow; ++j) {
+        const double pr = pval[j] * s_x1[pcol[j]];
+        s = j < np ? s + pr : s;
+      }
+      s_xc[t] = s_xc[t] + s;
+    }
+    __syncthreads();
+    double z = 0.0;                                // post-smoothing
+    if (own) {
+      z = s_xc[t] + swi * (s_r[t] - arow(s_xc));
+      s_z[t] = z;
+    }
+    const double rz = wg_sum(own ? s_r[t] * z : 0.0, s_red[0]);
+    zq = a.flexible ? wg_sum(own ? z * s_q[t] : 0.0, s_red[1]) : 0.0;
+    return rz;
+  };
+
+  // r = b, x = 0, ||b||^2
+  if (own) s_r[t] = bi;
+  s_q[t] = 0.0;
+  const double bb = wg_sum(bi * bi, s_red[2]);
+  const double thresh = (a.tol * a.tol) * bb;
+  int iters = 0, restarts = 0, state = 0;
+  double rz = 0.0, pq = 0.0, rr = bb, trr = bb;
+  if (bb == 0.0) {
+    state = 3;
+    trr = 0.0;
+  } else if (!(bb == bb)) {
+    state = -1;
+  } else {
+    for (;;) {
+      // (re)start: z = M^-1 r, p = z
+      double zq;
+      rz = vcycle(zq);
+      if (!(rz > 0.0)) {
+        state = -1;
+        break;
+      }
+      if (own) s_p[t] = s_z[t];
+      state = 2;
+      while (iters < a.maxiter) {
+        __syncthreads();                           // p complete
+        const double qi = own ? arow(s_p) : 0.0;
+        if (own) s_q[t] = qi;
+        pq = wg_sum(own ? s_p[t] * qi : 0.0, s_red[3]);
+        if (!(pq > 0.0)) {
+          state = -1;
+          break;
+        }
+        const double alpha = rz / pq;
+        double ri = 0.0;
+        if (own) {
+          xi = xi + alpha * s_p[t];
+          ri = s_r[t] - alpha * qi;
+          s_r[t] = ri;
+        }
+        ++iters;
+        rr = wg_sum(ri * ri, s_red[2]);
+        if (rr <= thresh) {
+          state = 1;
+          break;
+        }
+        if (!(rr == rr)) {
+          state = -1;
+          break;
+        }
+        const double rzn = vcycle(zq);
+        if (!(rzn > 0.0)) {
+          state = -1;
+          break;
+        }
+        const double beta = a.flexible ? -zq / pq : rzn / rz;
+        rz = rzn;
+        if (own) s_p[t] = s_z[t] + beta * s_p[t];
+      }
+      if (state < 0) break;
+      // true residual r = b - A x
+      __syncthreads();
+      if (own) s_xc[t] = xi;
+      __syncthreads();
+      const double ti = own ? bi - arow(s_xc) : 0.0;
+      if (own) s_r[t] = ti;
+      trr = wg_sum(ti * ti, s_red[3]);
+      if (trr <= thresh) break;
+      if (state == 1 && restarts < 5 && iters < a.maxiter) {
+        ++restarts;
+        __syncthreads();
+        continue;
+      }
+      break;
+    }
+  }
+  if (own) a.x[t] = state == 3 ? 0.0 : xi;
+  if (t == 0) {
+    Ctl& c = *a.ctl;
+    c.bb = bb;
+    c.thresh = thresh;
+    c.rz = rz;
+    c.pq = pq;
+    c.rr = rr;
+    c.trr = trr;
+    c.iters = iters;
+    c.maxiter = a.maxiter;
+    c.state = state;
+    c.done = 1;
+    c.flexible = a.flexible;
+    c.restarts = restarts;
+  }
+}
+
+}  // namespace
+
+// Whether H's solves can run as one workgroup: two levels, at most 1024 fine
+// rows with at most 8 entries per row of A_0 and P_0, a dense coarsest level
+// of at most 256 (padded) rows, and R_0 rows that fit 8 entries per lane of
+// a lane group with (rows x lanes) <= 1024; FP64 V(1,1) cycle of one system,
+// PCG.  Decided once per hierarchy (host copies of the row pointers).
+bool small_solve_ok(Hierarchy& H) {
+  if (H.small_checked) return H.small_lgR >= 0;
+  H.small_checked = true;
+  H.small_lgR = -1;
+  if (H.lv.size() != 2 || H.S != 1 || H.fp32() || !H.prm.precondition || H.prm.nu_pre != 1 ||
+      H.prm.nu_post != 1 || H.prm.solver != AMG_SOLVER_PCG || !H.prm.symmetric)
+    return false;
+  const Level& L = H.lv[0];
+  if (L.n > kST || L.n < 1 || H.co.m > kSCoarse || H.co.n != L.nagg || L.nagg < 1) return false;
+  auto maxrow = [](const DBuf<int>& rp, int n) {
+    std::vector<int> h(n + 1);
+    AMG_HIP(hipMemcpy(h.data(), rp.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+    int mx = 0;
+    for (int r = 0; r < n; ++r) mx = std::max(mx, h[r + 1] - h[r]);
+    return mx;
+  };
+  if (maxrow(L.rp, L.n) > kSRow || maxrow(L.prp, L.n) > kSRow) return false;
+  const int mr = maxrow(L.rrp, L.nagg);
+  for (int lg = 0; lg <= 6; ++lg) {
+    const int g = 1 << lg;
+    if (mr <= kSRLane * g && (int64_t)L.nagg * g <= kST) {
+      H.small_lgR = lg;
+      return true;
+    }
+    if ((int64_t)L.nagg * g > kST) break;
+  }
+  return false;
+}
+
+amg_status pcg_solve_small(Hierarchy& H, const SolveOpts& o, const SolveWork& w, const double* d_b, double* d_x,
+                           double tol, amg_info* info, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  const Level& L = H.lv[0];
+  SmallArgs a{};
+  a.n = L.n;
+  a.nc = H.co.n;
+  a.m = H.co.m;
+  a.lgR = H.small_lgR;
+  a.maxiter = o.maxiter;
+  a.flexible = o.flexible < 0 ? 0 : o.flexible;
+  a.tol = tol;
+  a.arp = L.rp.p;
+  a.aci = L.ci.p;
+  a.av = L.v.p;
+  a.sw = L.sw.p;
+  a.prp = L.prp.p;
+  a.pci = L.pci.p;
+  a.pv = L.pv.p;
+  a.rrp = L.rrp.p;
+  a.rci = L.rci.p;
+  a.rv = L.rv.p;
+  a.inv = H.co.inv.p;
+  a.b = d_b;
+  a.x = d_x;
+  a.ctl = w.ctl;
+  hipLaunchKernelGGL(k_pcg_small, dim3(1), dim3(kST), 0, s, a);
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipMemcpyAsync(w.h_ctl, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  const Ctl& c = *w.h_ctl;
+  amg_status st;
+  if (c.state == 3 || c.trr <= c.thresh) st = AMG_OK;
+  else if (c.state < 0) st = AMG_ERR_BREAKDOWN;
+  else st = AMG_NOT_CONVERGED;
+  if (info) {
+    info->iters = c.iters;
+    info->status = st;
+    info->restarts = c.restarts;
+    info->rel_resid = c.state == 3 ? 0.0 : (c.bb > 0 ? std::sqrt(c.trr / c.bb) : 0.0);
+    if (st == AMG_ERR_BREAKDOWN) info->rel_resid = NAN;
+    info->cache_event = H.cache_event;
+    info->setup_ms = H.setup_ms;
+    info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+}  // namespace amg

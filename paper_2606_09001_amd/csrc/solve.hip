@@ -4,7 +4,7 @@
 // product, per-row epilogue):
 //   - k_stream (rows of moderate length): a workgroup stages the row
 //     pointers of a block of rows in LDS, loads all of the block's nonzeros
-//     at once (kStreamCap/kBlock independent loads per thread, coalesced
+//     at once (up to kStreamCap/kBlock independent loads per thread, coalesced
 //     column/value streams), stores the products in LDS and sums each row
 //     there; with one lane per row the sum is the sequential fold in stored
 //     order;
@@ -298,16 +298,18 @@ __device__ inline void publish_partials(double (&d)[NRED > 0 ? NRED : 1], double
 
 // ------------------------------------------------------------ CSR sweeps
 
-template <int G3, class Op>
+// U: staged entries per thread (the block's staging buffer holds kBlock*U
+// entries; the shape sizes it to the matrix's largest row block, so that few
+// of the unconditional loads are clamped duplicates).
+template <int G3, int U, bool NT, class Op>
 __global__ void __launch_bounds__(kBlock) k_stream(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    Op op, const Ctl* __restrict__ ctl,
                                                    double* __restrict__ partials) {
   if ((ctl && ctl->done) || n <= 0) return;
   constexpr int RB = kBlock / G3;
-  constexpr int U = kStreamCap / kBlock;
   using PT = typename Op::PT;
   __shared__ int s_rp[RB + 1];
-  __shared__ PT s_p[kStreamCap];
+  __shared__ PT s_p[kBlock * U];
   const int r0 = logical_block() * RB;
   for (int t = threadIdx.x; t <= RB; t += kBlock) s_rp[t] = rp[min(r0 + t, n)];
   const int lr = threadIdx.x / G3, lane = threadIdx.x & (G3 - 1);
@@ -321,10 +323,11 @@ __global__ void __launch_bounds__(kBlock) k_stream(int n, const int* __restrict_
     // that all of them are in flight at once; only the LDS stores are masked.
     int col[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) col[u] = ci[k0 + min((int)threadIdx.x + u * kBlock, nk - 1)];
+    for (int u = 0; u < U; ++u) col[u] = stream_load<NT>(ci + k0 + min((int)threadIdx.x + u * kBlock, nk - 1));
     PT pv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) pv[u] = op.prod(k0 + min((int)threadIdx.x + u * kBlock, nk - 1), col[u]);
+    for (int u = 0; u < U; ++u)
+      pv[u] = op.prod_v(stream_load<NT>(op.v + k0 + min((int)threadIdx.x + u * kBlock, nk - 1)), col[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = threadIdx.x + u * kBlock;
@@ -382,7 +385,7 @@ __global__ void __launch_bounds__(kBlock) k_vec(int n, const int* __restrict__ r
 // coalesced load.  The slice width is uniform across the wave; padding
 // entries (column -1) are masked out of the sum.  Each row sums its entries
 // in stored order (the same fold as a one-lane CSR sweep).
-template <class Op>
+template <bool NT, class Op>
 __global__ void __launch_bounds__(kBlock) k_sell(int n, const int* __restrict__ soff, const int* __restrict__ sci,
                                                  Op op, const Ctl* __restrict__ ctl, double* __restrict__ partials) {
   if ((ctl && ctl->done) || n <= 0) return;
@@ -400,8 +403,8 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, const int* __restrict__ 
 #pragma unroll
   for (int j = 0; j < kSellMaxW; ++j) {
     const int p = off + min(j, w - 1) * 64 + lane;
-    col[j] = sci[p];
-    val[j] = op.v[p];
+    col[j] = stream_load<NT>(sci + p);
+    val[j] = stream_load<NT>(op.v + p);
   }
   PT pv[kSellMaxW];
 #pragma unroll
@@ -418,7 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, const int* __restrict__ 
 // slots[j].x for every row whose mask bit is set; the slot records are
 // wave-uniform (scalar loads), so the only per-entry stream is the values.
 // Each row adds its present entries in ascending offset (= column) order.
-template <class Op>
+template <bool NT, class Op>
 __global__ void __launch_bounds__(kBlock) k_sello(int n, const int* __restrict__ soff, const int4* __restrict__ slots,
                                                   Op op, const Ctl* __restrict__ ctl, double* __restrict__ partials) {
   if ((ctl && ctl->done) || n <= 0) return;
@@ -432,7 +435,7 @@ __global__ void __launch_bounds__(kBlock) k_sello(int n, const int* __restrict__
   const int sb = off >> 6;
   typename std::remove_const<typename std::remove_pointer<decltype(op.v)>::type>::type val[kSellMaxW];
 #pragma unroll
-  for (int j = 0; j < kSellMaxW; ++j) val[j] = op.v[off + min(j, w - 1) * 64 + lane];
+  for (int j = 0; j < kSellMaxW; ++j) val[j] = stream_load<NT>(op.v + off + min(j, w - 1) * 64 + lane);
   // the slice's kSellMaxW records as one block (the array is padded so the
   // last slice's block stays in bounds)
   int4 rec[kSellMaxW];
@@ -468,23 +471,42 @@ __global__ void __launch_bounds__(kBlock) k_sello(int n, const int* __restrict__
     default: { constexpr int G = 64; __VA_ARGS__; } break; \
   }
 
+template <bool NT, class Op>
+void sweep_form(const Shape& sh, int n, const int* rp, const int* ci, const Op& op, const Ctl* ctl,
+                double* partials, hipStream_t s) {
+  if (sh.stream == 3) {
+    hipLaunchKernelGGL((k_sello<NT, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, reinterpret_cast<const int4*>(ci),
+                       op, ctl, partials);
+  } else if (sh.stream == 2) {
+    hipLaunchKernelGGL((k_sell<NT, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl, partials);
+  } else if (sh.stream) {
+    switch (sh.u) {
+      case 4:
+        AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_stream<G, 4, NT, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp,
+                                                ci, op, ctl, partials));
+        break;
+      case 8:
+        AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_stream<G, 8, NT, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp,
+                                                ci, op, ctl, partials));
+        break;
+      default:
+        AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_stream<G, 12, NT, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n,
+                                                rp, ci, op, ctl, partials));
+        break;
+    }
+  } else {
+    AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_vec<G, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl,
+                                            partials));
+  }
+}
+
 // One sweep over a CSR matrix with operator `op`; returns the grid size
 // (= number of partials written per reduced value).
 template <class Op>
 int sweep(const Shape& sh, int n, const int* rp, const int* ci, const Op& op, const Ctl* ctl, double* partials,
           hipStream_t s) {
-  if (sh.stream == 3) {
-    hipLaunchKernelGGL((k_sello<Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, reinterpret_cast<const int4*>(ci), op,
-                       ctl, partials);
-  } else if (sh.stream == 2) {
-    hipLaunchKernelGGL((k_sell<Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl, partials);
-  } else if (sh.stream) {
-    AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_stream<G, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl,
-                                            partials));
-  } else {
-    AMG_DISPATCH_G(sh.g, hipLaunchKernelGGL((k_vec<G, Op>), dim3(sh.grid), dim3(kBlock), 0, s, n, rp, ci, op, ctl,
-                                            partials));
-  }
+  if (sh.nt) sweep_form<true>(sh, n, rp, ci, op, ctl, partials, s);
+  else sweep_form<false>(sh, n, rp, ci, op, ctl, partials, s);
   return sh.grid;
 }
 
@@ -1249,6 +1271,13 @@ void read_ctl(Hierarchy& H, hipStream_t s) {
 // Launch shape of a sweep over a CSR matrix with `n` rows (host row
 // pointers): the most rows per workgroup whose nonzeros fit the staging
 // buffer, with enough lanes per row for the in-LDS sums of long rows.
+// Staged entries per thread of a CSR-stream launch whose largest row block
+// holds mx entries.
+int stream_u(int mx) {
+  for (int u : {4, 8}) if (mx <= u * kBlock) return u;
+  return 12;
+}
+
 Shape make_shape(const std::vector<int>& rp, int n) {
   Shape sh;
   const double avg = n > 0 ? (double)(rp[n] - rp[0]) / n : 1.0;
@@ -1260,6 +1289,7 @@ Shape make_shape(const std::vector<int>& rp, int n) {
     if (mx <= kStreamCap) {
       sh.stream = 1;
       sh.g = lanes;
+      sh.u = stream_u(mx);
       sh.rows_per_block = rb;
       sh.max_block_nnz = mx;
       sh.grid = round8(((int64_t)n + rb - 1) / rb);
@@ -1304,6 +1334,7 @@ std::vector<Shape> candidate_shapes(const std::vector<int>& rp, int n) {
     Shape sh;
     sh.stream = 1;
     sh.g = kBlock / rb;
+    sh.u = stream_u(mx);
     sh.rows_per_block = rb;
     sh.max_block_nnz = mx;
     sh.grid = round8(((int64_t)n + rb - 1) / rb);
@@ -1454,6 +1485,9 @@ void choose_shapes(Hierarchy& H, hipStream_t s) {
         return t;
       }, s);
     }
+    // nontemporal entry streams for operators larger than the last-level cache
+    const double abytes = L.sell ? (double)L.sell_len * (L.sell_form == 2 ? 8.0 : 12.0) : 12.0 * (double)L.nnz;
+    L.shA.nt = abytes > kLlcBytes ? 1 : 0;
     if (l + 1 == H.lv.size()) continue;
     if (f32 && H.bf16()) {
       L.shP = pick_shape(H, "P", (int)l, L.prp, L.pci, L.n, nc, [&](int64_t len) {
@@ -1504,6 +1538,8 @@ void choose_shapes(Hierarchy& H, hipStream_t s) {
         return t;
       }, s);
     }
+    const double pwb = f32 ? (H.bf16() ? 2.0 : 4.0) : 8.0;
+    L.shP.nt = L.shR.nt = (pwb + 4.0) * (double)L.pnnz > kLlcBytes ? 1 : 0;
   }
   AMG_HIP(hipStreamSynchronize(s));
 }
@@ -1711,6 +1747,9 @@ void graph_stream(Hierarchy& H) {
 
 amg_status pcg_solve(Hierarchy& H, const SolveOpts& o, const SolveWork& w, const double* d_b, double* d_x,
                      double tol, amg_info* info, hipStream_t caller) {
+  // hierarchies that fit one compute unit: the whole solve in one launch
+  if (o.fused_small && H.inst.kernel < 0 && small_solve_ok(H))
+    return pcg_solve_small(H, o, w, d_b, d_x, tol, info, caller);
   auto t0 = std::chrono::steady_clock::now();
   Level& L0 = H.lv[0];
   const int n = H.n;

@@ -21,7 +21,7 @@ __all__ = ["AmgHierarchy", "solve", "amg_solve", "AmgSolve", "make_params", "fin
 
 _PARAM_KEYS = ("vcycle_prec", "transfer_bf16", "theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre",
                "nu_post", "maxiter", "flexible", "symmetric", "check_every", "use_graphs", "autotune",
-               "precondition", "solver")
+               "precondition", "solver", "fused_small")
 
 
 def make_params(**kw) -> _lib.amg_params:
