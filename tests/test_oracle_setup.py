@@ -171,7 +171,18 @@ def _theta_cases():
         "upwind": (M.convection_diffusion(16, 2, (40.0, 20.0)), 0.35, False),
         "recirculating": (M.convection_diffusion(16, 2, M.recirculating_wind(16, 2, 120.0)), 0.3, False),
         "mixed_sign": (_random_mixed_sign(80, 0.08, 11), 0.1, False),
+        # every third row negated: negative diagonals, so the square root takes
+        # |a_ii a_jj| and a product of diagonals of opposite signs still counts
+        "negative_diagonal": (_negate_rows(_random_mixed_sign(80, 0.08, 12), 3), 0.1, False),
     }
+
+
+def _negate_rows(csr, k):
+    rp, ci, v = csr
+    v = v.copy()
+    for i in range(0, len(rp) - 1, k):
+        v[rp[i]:rp[i + 1]] *= -1.0
+    return rp, ci, v
 
 
 @pytest.mark.parametrize("case", list(_theta_cases()))
