@@ -163,7 +163,8 @@ struct WPost {
   }
 };
 
-// p' = z + beta_c p (p' = z for columns starting a (re)start), q = A p', <p', q>
+// p' = z + beta_c p and q' = A z + beta_c q (= A p'); p' = z and q' = A z for columns starting a
+// (re)start; <p', q'>
 template <bool SYS>
 struct WSpmvXpay {
   using PT = double;
@@ -178,27 +179,30 @@ struct WSpmvXpay {
   const WCtl* ctl;
   int W;
   struct Row {
-    double pr;
+    double pr, qo;
   };
-  // both operands are always loaded (no divergent branch around a load);
-  // a column that (re)starts takes p' = z
+  // q' = A p' is formed as A z + beta q (the same vector in exact
+  // arithmetic, since q = A p), so the sweep gathers z only; p and q are read
+  // at the row itself.  Both row operands are always loaded (no divergent
+  // branch around a load); a column that (re)starts takes p' = z, q' = A z.
   double beta_c = 0.0;  // this lane's column scalars, read once by bind()
   int first_c = 1;
   __device__ void bind(int c) {
     beta_c = ctl[c].beta;
     first_c = ctl[c].first;
   }
-  __device__ double dir(int64_t e, int) const {
-    const double zz = z[e], pp = p[e];
-    return first_c ? zz : zz + beta_c * pp;
+  __device__ PT prod_v(VT a, int j, int c) const { return a * z[(int64_t)j * W + c]; }
+  __device__ Row row_in(int row, int c) const {
+    const int64_t e = (int64_t)row * W + c;
+    const double zz = z[e], pp = p[e], qq = q[e];
+    return {first_c ? zz : zz + beta_c * pp, qq};
   }
-  __device__ PT prod_v(VT a, int j, int c) const { return a * dir((int64_t)j * W + c, c); }
-  __device__ Row row_in(int row, int c) const { return {dir((int64_t)row * W + c, c)}; }
   __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
     const int64_t e = (int64_t)row * W + c;
     pn[e] = a.pr;
-    q[e] = s;
-    d[0] += a.pr * s;
+    const double qn = first_c ? s : s + beta_c * a.qo;
+    q[e] = qn;
+    d[0] += a.pr * qn;
   }
 };
 
@@ -1245,8 +1249,8 @@ double wide_kernel_bytes(const Hierarchy& H, int kid, int level, int flexible, i
   const bool has_next = level + 1 < nl;
   const bool next_coarsest = level + 2 == nl;
   switch (kid) {
-    // p' = z + beta p gathered (z and p), p' and q = A p' written
-    case KID_SPMV_DOT: return M((double)L.nnz, n, 8.0) + 32.0 * n * w;
+    // z gathered, p and q read at the row, p' = z + beta p and q' = A z + beta q written
+    case KID_SPMV_DOT: return M((double)L.nnz, n, 8.0) + 40.0 * n * w;
     case KID_PRE: return M((double)L.nnz, n, v) + (bw + 2.0 * v) * n * w;
     case KID_POST: {
       const double ow = level == 0 ? 8.0 : v;
