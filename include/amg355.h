@@ -66,8 +66,9 @@ enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_L1 = 1 };
 enum { AMG_CACHE_COLD = 0, AMG_CACHE_HIT = 1, AMG_CACHE_REFRESH = 2 };
 enum { AMG_SOLVER_PCG = 0, AMG_SOLVER_BICGSTAB = 1 };
 
-/* Largest coarsest level that receives a dense factorization. */
-#define AMG_MAX_DENSE_COARSE 4096
+/* Largest coarsest level that receives a dense factorization (its explicit
+ * inverse is applied once per cycle, m^2 values). */
+#define AMG_MAX_DENSE_COARSE 2048
 #define AMG_MAX_LEVELS 20
 
 typedef struct {

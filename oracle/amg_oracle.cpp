@@ -48,7 +48,7 @@ enum {
 
 // Largest coarsest level that gets a dense factorization; a hierarchy whose
 // coarsening stalls above this size is rejected instead.
-constexpr int kMaxDenseCoarse = 4096;
+constexpr int kMaxDenseCoarse = 2048;
 
 struct Csr {
   int nrows = 0, ncols = 0;

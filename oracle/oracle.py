@@ -14,7 +14,7 @@ __all__ = ["OracleHierarchy", "spmv", "pattern_grad", "rel_residual", "node_key"
            "color_columns", "probe_vectors", "probe_assemble", "probe_scatter",
            "diffusion_theta_grad", "OR_OK", "OR_NOT_CONVERGED", "OR_ERR_INVALID_ARG", "OR_ERR_ZERO_DIAG",
            "OR_ERR_PATTERN_MISMATCH", "OR_ERR_BREAKDOWN", "OR_ERR_COARSE_TOO_LARGE", "load",
-           "set_threads", "get_threads", "host_cores"]
+           "set_threads", "get_threads", "host_cores", "OracleError"]
 
 OR_OK = 0
 OR_NOT_CONVERGED = 1

@@ -22,6 +22,7 @@ AMG_ERR_HIP = -6
 AMG_ERR_COARSE_TOO_LARGE = -7
 AMG_ERR_SCRATCH_LIMIT = -8
 AMG_NOALLOC_MAX_N = 2097152
+AMG_MAX_DENSE_COARSE = 2048
 
 AMG_PREC_FP64 = 0
 AMG_PREC_FP32 = 1

@@ -112,17 +112,40 @@ __global__ void __launch_bounds__(kCoBlock) k_cholesky(int m, double* __restrict
   if (tid == 0 && s_bad) atomicOr(flags, 1);
 }
 
-// Linv = L^-1 by forward substitution, one column per thread.
-__global__ void k_tri_inverse(int m, const double* __restrict__ L, double* __restrict__ Linv) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
-  for (int i = 0; i < j; ++i) Linv[(int64_t)i * m + j] = 0.0;
-  Linv[(int64_t)j * m + j] = 1.0 / L[(int64_t)j * m + j];
+// Column solves of the triangular inverses: one wavefront per column, the
+// column in LDS, each row's dot product spread over the wavefront (lane-
+// strided partial sums, then a fixed butterfly).
+constexpr int kTriWaves = 2;
+
+// Makes the LDS writes of a wavefront visible to its other lanes.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Linv = L^-1 by forward substitution: Linv[i][j] = -(sum_{j<=k<i} L[i][k]
+// Linv[k][j]) / L[i][i], Linv[j][j] = 1 / L[j][j].
+__global__ void __launch_bounds__(64 * kTriWaves) k_tri_inverse(int m, const double* __restrict__ L,
+                                                                double* __restrict__ Linv) {
+  __shared__ double s_col[kTriWaves][AMG_MAX_DENSE_COARSE];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int j = blockIdx.x * kTriWaves + w;
+  if (j >= m) return;  // the whole wavefront
+  double* col = s_col[w];
+  for (int i = l; i < m; i += 64) col[i] = 0.0;
+  wave_lds_sync();
+  if (l == 0) col[j] = 1.0 / L[(int64_t)j * m + j];
+  wave_lds_sync();
   for (int i = j + 1; i < m; ++i) {
+    const double* Li = L + (int64_t)i * m;
     double s = 0.0;
-    for (int k = j; k < i; ++k) s += L[(int64_t)i * m + k] * Linv[(int64_t)k * m + j];
-    Linv[(int64_t)i * m + j] = -s / L[(int64_t)i * m + i];
+    for (int k = j + l; k < i; k += 64) s += Li[k] * col[k];
+    s = wave_sum(s);
+    if (l == 0) col[i] = -s / Li[i];
+    wave_lds_sync();
   }
+  for (int i = l; i < m; i += 64) Linv[(int64_t)i * m + j] = col[i];
 }
 
 // Transpose (m x m): Y = X^T.
@@ -225,32 +248,43 @@ __global__ void __launch_bounds__(kLuBlock) k_lu(int m, double* __restrict__ W, 
 }
 
 // Row j of invT = column j of A^-1: y = P e_j (the recorded exchanges in
-// order), unit-lower forward substitution, then upper back substitution.
-// One thread per column, its row of invT as the work vector.
-__global__ void k_lu_inverse_t(int m, const double* __restrict__ LU, const int* __restrict__ piv,
-                               double* __restrict__ invT) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
-  double* y = invT + (int64_t)j * m;
-  for (int i = 0; i < m; ++i) y[i] = i == j ? 1.0 : 0.0;
+// order move the single 1 of e_j), unit-lower forward substitution
+// y_i -= sum_{q<i} l_iq y_q, then upper back substitution
+// y_i = (y_i - sum_{q>i} u_iq y_q) / u_ii.  One wavefront per column (as
+// k_tri_inverse).
+__global__ void __launch_bounds__(64 * kTriWaves) k_lu_inverse_t(int m, const double* __restrict__ LU,
+                                                                 const int* __restrict__ piv,
+                                                                 double* __restrict__ invT) {
+  __shared__ double s_y[kTriWaves][AMG_MAX_DENSE_COARSE];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int j = blockIdx.x * kTriWaves + w;
+  if (j >= m) return;  // the whole wavefront
+  double* y = s_y[w];
+  int pos = j;
   for (int k = 0; k < m; ++k) {
     const int p = piv[k];
-    if (p != k) {
-      const double t = y[k];
-      y[k] = y[p];
-      y[p] = t;
-    }
+    if (pos == k) pos = p;
+    else if (pos == p) pos = k;
   }
-  for (int i = 1; i < m; ++i) {
-    double s = y[i];
-    for (int q = 0; q < i; ++q) s -= LU[(int64_t)i * m + q] * y[q];
-    y[i] = s;
+  for (int i = l; i < m; i += 64) y[i] = i == pos ? 1.0 : 0.0;
+  wave_lds_sync();
+  for (int i = pos + 1; i < m; ++i) {  // entries before pos stay zero
+    const double* Ri = LU + (int64_t)i * m;
+    double s = 0.0;
+    for (int q = pos + l; q < i; q += 64) s += Ri[q] * y[q];
+    s = wave_sum(s);
+    if (l == 0) y[i] = y[i] - s;
+    wave_lds_sync();
   }
   for (int i = m - 1; i >= 0; --i) {
-    double s = y[i];
-    for (int q = i + 1; q < m; ++q) s -= LU[(int64_t)i * m + q] * y[q];
-    y[i] = s / LU[(int64_t)i * m + i];
+    const double* Ri = LU + (int64_t)i * m;
+    double s = 0.0;
+    for (int q = i + 1 + l; q < m; q += 64) s += Ri[q] * y[q];
+    s = wave_sum(s);
+    if (l == 0) y[i] = (y[i] - s) / Ri[i];
+    wave_lds_sync();
   }
+  for (int i = l; i < m; i += 64) invT[(int64_t)j * m + i] = y[i];
 }
 
 __global__ void k_inv_to_f32(int64_t mm, const double* __restrict__ a, float* __restrict__ b) {
@@ -287,11 +321,13 @@ void coarse_setup(Hierarchy& H, hipStream_t s) {
     if (lu) {
       int* ps = C.piv.p + (int64_t)sy * m;
       hipLaunchKernelGGL(k_lu, dim3(1), dim3(kLuBlock), 0, s, m, Ls, ps, H.flags.p);
-      hipLaunchKernelGGL(k_lu_inverse_t, dim3((m + 63) / 64), dim3(64), 0, s, m, Ls, ps, Is);
+      hipLaunchKernelGGL(k_lu_inverse_t, dim3((m + kTriWaves - 1) / kTriWaves), dim3(64 * kTriWaves), 0, s, m, Ls,
+                         ps, Is);
       continue;
     }
     hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(kCoBlock), 0, s, m, Ls, H.flags.p);
-    hipLaunchKernelGGL(k_tri_inverse, dim3((m + 63) / 64), dim3(64), 0, s, m, Ls, Is);
+    hipLaunchKernelGGL(k_tri_inverse, dim3((m + kTriWaves - 1) / kTriWaves), dim3(64 * kTriWaves), 0, s, m, Ls,
+                       Is);
     hipLaunchKernelGGL(k_transpose, dim3((int)((mm + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, m, Is, C.work.p);
     hipLaunchKernelGGL(k_gram, dim3((T * T * 64 + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m, C.work.p, Is);
   }

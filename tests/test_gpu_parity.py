@@ -385,3 +385,47 @@ def test_plain_cg_large_tridiagonal():
     assert info["status"] == 0 and info["rel_resid"] <= 1e-10
     assert oracle.rel_residual(rp, ci, v, b, host(x)) <= 1e-10
     assert H.stats()["form_a"][0] == 3
+
+
+@pytest.mark.parametrize("kind", ["spd", "nonsymmetric"])
+def test_dense_coarse_at_the_size_limit(kind):
+    """A single-level hierarchy of 2025 unknowns (the dense coarse-solve limit
+    is 2048): the explicit inverse against LAPACK's, the solve is the direct
+    solve, and a level beyond the limit is refused at setup on both sides."""
+    import time
+    import oracle
+    from paper_2606_09001_amd import _lib
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    if kind == "spd":
+        rp, ci, v = M.diffusion(np.exp(M.grf(45, 2, seed=6)))        # 2025 unknowns
+        kw = dict(max_levels=1)
+    else:
+        rp, ci, v = M.convection_diffusion(45, 2, M.recirculating_wind(45, 2, 40.0))
+        kw = dict(max_levels=1, symmetric=False, solver="bicgstab")
+    n = len(rp) - 1
+    assert n == 2025 and n <= _lib.AMG_MAX_DENSE_COARSE
+    print(f"[case] dense coarse limit {kind} n={n}", flush=True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    H = AmgHierarchy(dev(rp), dev(ci), dev(v), **kw)
+    torch.cuda.synchronize()
+    print(f"[dense coarse {kind}] setup {1e3 * (time.time() - t0):.1f} ms", flush=True)
+    assert H.stats()["num_levels"] == 1
+    A = np.zeros((n, n))
+    A[np.repeat(np.arange(n), np.diff(rp)), ci] = v
+    Ig = host(H.export(0, "coarse_inv"))
+    m = int(round(np.sqrt(Ig.size)))                                # padded to a multiple of 16
+    Ig = Ig.reshape(m, m)[:n, :n].T
+    Iref = np.linalg.inv(A)
+    assert np.max(np.abs(Ig - Iref)) <= 1e-10 * np.abs(Iref).max()
+    b = M.rhs_normal(n, 5)
+    x, info = H.solve(dev(b), 1e-12)
+    xd = np.linalg.solve(A, b)
+    assert info["status"] == 0 and np.linalg.norm(host(x) - xd) <= 1e-10 * np.linalg.norm(xd)
+    # one unknown beyond the limit: refused by the library and by the oracle
+    rp2, ci2, v2 = M.tridiagonal(_lib.AMG_MAX_DENSE_COARSE + 1, 2.5)
+    with pytest.raises(_lib.AmgError) as e:
+        AmgHierarchy(dev(rp2), dev(ci2), dev(v2), max_levels=1)
+    assert e.value.status == _lib.AMG_ERR_COARSE_TOO_LARGE
+    with pytest.raises(oracle.OracleError):
+        oracle.OracleHierarchy(rp2, ci2, v2, max_levels=1)
