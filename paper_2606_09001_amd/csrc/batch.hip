@@ -259,7 +259,11 @@ __device__ inline void publish_w(double (&d)[NRED > 0 ? NRED : 1], int W, double
 // groups in turn, so a stream advances as one front: the rows a front
 // gathers from (its neighbours at short index distance) stay in that XCD's
 // L2 while the front passes.  spx = G/8 gives every workgroup a contiguous
-// range of its own.
+// range of its own.  spx = -1 is one front for the whole device:
+// consecutive chunks of G/8 row groups go to the XCDs in turn, so the 8 XCDs
+// sweep 8 neighbouring chunks at a time (for a 3D grid with chunks of about a
+// plane, a row's neighbours in the adjacent planes are being swept by the
+// neighbouring XCDs at the same time and are still in the last-level cache).
 struct WideSched {
   int64_t first, end;
   int step;
@@ -267,6 +271,10 @@ struct WideSched {
 
 __device__ inline WideSched wide_sched(int64_t groups, int spx) {
   const int G = gridDim.x;
+  if (spx < 0 && (G & 7) == 0) {
+    const int gx = G >> 3;
+    return {(int64_t)(blockIdx.x & 7) * gx + (blockIdx.x >> 3), groups, G};
+  }
   if ((G & 7) == 0 && spx > 0 && ((G >> 3) % spx) == 0) {
     const int gx = G >> 3;
     const int team = gx / spx;
@@ -969,7 +977,7 @@ double time_wide(int LWv, int spx, int br, int n, int W, const int* rp, const in
 // launch's grid depends on the kernel's residency, so the candidates are
 // taken for the smallest resident grid that divides into 8 XCDs evenly).
 std::vector<int> spx_candidates() {
-  std::vector<int> out{0};
+  std::vector<int> out{0, -1};
   for (int spx : {64, 32, 16, 8, 4, 2, 1}) out.push_back(spx);
   return out;
 }

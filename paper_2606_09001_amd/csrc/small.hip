@@ -30,10 +30,13 @@
 namespace amg {
 namespace {
 
-constexpr int kST = 1024;        // threads = largest fine level
-constexpr int kSRow = 8;         // entries per row of A_0 and P_0 held in registers
+constexpr int kST = 512;         // threads of the workgroup
+constexpr int kSR = 2;           // fine rows per thread (rows t and t + kST)
+constexpr int kSN = kST * kSR;   // largest fine level
+constexpr int kSRow = 8;         // entries per row of A_0 and P_0
 constexpr int kSCoarse = 256;    // largest padded coarsest level
-constexpr int kSRLane = 8;       // entries of an R_0 row per lane
+constexpr int kSRLane = 16;      // entries of an R_0 row per lane
+constexpr int kSInv = 16;        // coarse-inverse entries per thread in flight
 
 struct SmallArgs {
   int n, nc, m, lgR, maxiter, flexible;
@@ -60,6 +63,14 @@ struct SmallArgs {
 // at once.
 __device__ inline void phase_fence() { asm volatile("" ::: "memory"); }
 
+// Returns v through an empty asm statement: the compiler cannot treat values
+// derived from it as loop-invariant, so the loads they address stay in their
+// phase instead of being hoisted out of the iteration loop.
+__device__ inline int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Sum of v over the workgroup in a fixed order; every thread gets the total.
 // `red` must not be reused before the next barrier.
 __device__ inline double wg_sum(double v, double* red) {
@@ -67,63 +78,73 @@ __device__ inline double wg_sum(double v, double* red) {
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = red[0];
-#pragma unroll 3
+#pragma unroll
   for (int k = 1; k < kST / 64; ++k) s += red[k];
   return s;
 }
 
 __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
-  __shared__ double s_r[kST], s_z[kST], s_p[kST], s_q[kST], s_xc[kST], s_rc[kST];
+  __shared__ double s_r[kSN], s_z[kSN], s_p[kSN], s_q[kSN], s_xc[kSN], s_rc[kSN];
   __shared__ double s_b1[kSCoarse], s_x1[kSCoarse];
   __shared__ double s_gp[kST];
   __shared__ double s_red[4][kST / 64];
   const int t = threadIdx.x;
-  const bool own = t < a.n;
-  const int i = own ? t : a.n - 1;
-  // this thread's rows of A_0 and P_0 (indices clamped into the row; the
-  // entries past the row's length are masked out of every sum)
-  const int ka = a.arp[i];
-  const int na = own ? a.arp[i + 1] - ka : 0;
-  int acol[kSRow];
-  double aval[kSRow];
+  // this thread's rows t + q kST: their rows of A_0 in registers (indices
+  // clamped into the row; entries past the row's length are masked out of
+  // every sum), their smoother weights, right-hand side and iterate
+  int row[kSR], na[kSR], acol[kSR][kSRow], kp[kSR], np[kSR];
+  bool own[kSR];
+  double aval[kSR][kSRow], swi[kSR], bi[kSR], xi[kSR];
 #pragma unroll
-  for (int j = 0; j < kSRow; ++j) {
-    const int k = ka + min(j, max(na - 1, 0));
-    acol[j] = a.aci[k];
-    aval[j] = a.av[k];
+  for (int q = 0; q < kSR; ++q) {
+    own[q] = t + q * kST < a.n;
+    row[q] = own[q] ? t + q * kST : a.n - 1;
+    const int ka = a.arp[row[q]];
+    na[q] = own[q] ? a.arp[row[q] + 1] - ka : 0;
+#pragma unroll
+    for (int j = 0; j < kSRow; ++j) {
+      const int k = ka + min(j, max(na[q] - 1, 0));
+      acol[q][j] = a.aci[k];
+      aval[q][j] = a.av[k];
+    }
+    swi[q] = a.sw[row[q]];
+    bi[q] = own[q] ? a.b[row[q]] : 0.0;
+    xi[q] = 0.0;
+    kp[q] = a.prp[row[q]];
+    np[q] = a.prp[row[q] + 1] - kp[q];
   }
-  const int kp = a.prp[i];
-  const int np = own ? a.prp[i + 1] - kp : 0;
-  const double swi = a.sw[i];
-  const double bi = own ? a.b[i] : 0.0;
-  double xi = 0.0;
-  // row i of A_0 applied to an LDS vector, summed in stored order
-  auto arow = [&](const double* v) {
+  // row q of A_0 applied to an LDS vector, summed in stored order
+  auto arow = [&](int q, const double* v) {
     double s = 0.0;
 #pragma unroll
     for (int j = 0; j < kSRow; ++j) {
-      const double pr = aval[j] * v[acol[j]];
-      s = j < na ? s + pr : s;
+      const double pr = aval[q][j] * v[acol[q][j]];
+      s = j < na[q] ? s + pr : s;
     }
     return s;
   };
   const int gR = 1 << a.lgR;
   const int rrow = t >> a.lgR, rl = t & (gR - 1);
+  const int rk0 = rrow < a.nc ? a.rrp[rrow] : 0, rk1 = rrow < a.nc ? a.rrp[rrow + 1] : 0;
   const int nb = kST / a.m;                       // column blocks of the coarse product
   const int ic = t % a.m, jb = t / a.m;
   const int L = (a.nc + nb - 1) / nb;
 
   // z = M^-1 r (s_r -> s_z); returns <r, z>, and <z, q> in zq when flexible
   auto vcycle = [&](double& zq) -> double {
-    if (own) s_xc[t] = swi * s_r[t];               // pre-smoothing from zero
+#pragma unroll
+    for (int q = 0; q < kSR; ++q)                  // pre-smoothing from zero
+      if (own[q]) s_xc[row[q]] = swi[q] * s_r[row[q]];
     __syncthreads();
-    if (own) s_rc[t] = s_r[t] - arow(s_xc);        // its residual
+#pragma unroll
+    for (int q = 0; q < kSR; ++q)                  // its residual
+      if (own[q]) s_rc[row[q]] = s_r[row[q]] - arow(q, s_xc);
     __syncthreads();
     {                                              // b_1 = R r_c, gR lanes per coarse row
       phase_fence();
       double s = 0.0;
       if (rrow < a.nc) {
-        const int k0 = a.rrp[rrow], k1 = a.rrp[rrow + 1];
+        const int k0 = opaque(rk0), k1 = rk1;
         int c[kSRLane];
         double v[kSRLane];
 #pragma unroll
@@ -147,13 +168,13 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
       if (jb < nb) {
         double s = 0.0;
         if (ic < a.nc) {
-          const int j0 = jb * L, j1 = min(j0 + L, a.nc);
-          for (int jj = j0; jj < j1; jj += 8) {
-            double v[8];
+          const int j0 = opaque(jb * L), j1 = min(j0 + L, a.nc);
+          for (int jj = j0; jj < j1; jj += kSInv) {
+            double v[kSInv];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = a.inv[(int64_t)min(jj + u, j1 - 1) * a.m + ic];
+            for (int u = 0; u < kSInv; ++u) v[u] = a.inv[(int64_t)min(jj + u, j1 - 1) * a.m + ic];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kSInv; ++u) {
               const double pr = v[u] * s_b1[min(jj + u, j1 - 1)];
               s = jj + u < j1 ? s + pr : s;
             }
@@ -170,12 +191,15 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
     }
     __syncthreads();
     phase_fence();
-    if (own) {                                     // x_c += P x_1
+#pragma unroll
+    for (int q = 0; q < kSR; ++q) {                // x_c += P x_1
+      if (!own[q]) continue;
       int pcol[kSRow];
       double pval[kSRow];
+      const int kq = opaque(kp[q]);
 #pragma unroll
       for (int j = 0; j < kSRow; ++j) {
-        const int k = kp + min(j, max(np - 1, 0));
+        const int k = kq + min(j, max(np[q] - 1, 0));
         pcol[j] = a.pci[k];
         pval[j] = a.pv[k];
       }
@@ -183,25 +207,35 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
 #pragma unroll
       for (int j = 0; j < kSRow; ++j) {
         const double pr = pval[j] * s_x1[pcol[j]];
-        s = j < np ? s + pr : s;
+        s = j < np[q] ? s + pr : s;
       }
-      s_xc[t] = s_xc[t] + s;
+      s_xc[row[q]] = s_xc[row[q]] + s;
     }
     __syncthreads();
-    double z = 0.0;                                // post-smoothing
-    if (own) {
-      z = s_xc[t] + swi * (s_r[t] - arow(s_xc));
-      s_z[t] = z;
+    double rz = 0.0, zqp = 0.0;                    // post-smoothing
+#pragma unroll
+    for (int q = 0; q < kSR; ++q) {
+      if (!own[q]) continue;
+      const int i = row[q];
+      const double z = s_xc[i] + swi[q] * (s_r[i] - arow(q, s_xc));
+      s_z[i] = z;
+      rz += s_r[i] * z;
+      zqp += z * s_q[i];
     }
-    const double rz = wg_sum(own ? s_r[t] * z : 0.0, s_red[0]);
-    zq = a.flexible ? wg_sum(own ? z * s_q[t] : 0.0, s_red[1]) : 0.0;
-    return rz;
+    const double rzt = wg_sum(rz, s_red[0]);
+    zq = a.flexible ? wg_sum(zqp, s_red[1]) : 0.0;
+    return rzt;
   };
 
   // r = b, x = 0, ||b||^2
-  if (own) s_r[t] = bi;
-  s_q[t] = 0.0;
-  const double bb = wg_sum(bi * bi, s_red[2]);
+  double bbp = 0.0;
+#pragma unroll
+  for (int q = 0; q < kSR; ++q) {
+    if (own[q]) s_r[row[q]] = bi[q];
+    s_q[t + q * kST] = 0.0;
+    bbp += bi[q] * bi[q];
+  }
+  const double bb = wg_sum(bbp, s_red[2]);
   const double thresh = (a.tol * a.tol) * bb;
   int iters = 0, restarts = 0, state = 0;
   double rz = 0.0, pq = 0.0, rr = bb, trr = bb;
@@ -219,26 +253,39 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
         state = -1;
         break;
       }
-      if (own) s_p[t] = s_z[t];
+#pragma unroll
+      for (int q = 0; q < kSR; ++q)
+        if (own[q]) s_p[row[q]] = s_z[row[q]];
       state = 2;
       while (iters < a.maxiter) {
         __syncthreads();                           // p complete
-        const double qi = own ? arow(s_p) : 0.0;
-        if (own) s_q[t] = qi;
-        pq = wg_sum(own ? s_p[t] * qi : 0.0, s_red[3]);
+        double qi[kSR], pqp = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSR; ++q) {
+          qi[q] = own[q] ? arow(q, s_p) : 0.0;
+          if (own[q]) {
+            s_q[row[q]] = qi[q];
+            pqp += s_p[row[q]] * qi[q];
+          }
+        }
+        pq = wg_sum(pqp, s_red[3]);
         if (!(pq > 0.0)) {
           state = -1;
           break;
         }
         const double alpha = rz / pq;
-        double ri = 0.0;
-        if (own) {
-          xi = xi + alpha * s_p[t];
-          ri = s_r[t] - alpha * qi;
-          s_r[t] = ri;
+        double rrp = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSR; ++q) {
+          if (!own[q]) continue;
+          const int i = row[q];
+          xi[q] = xi[q] + alpha * s_p[i];
+          const double ri = s_r[i] - alpha * qi[q];
+          s_r[i] = ri;
+          rrp += ri * ri;
         }
         ++iters;
-        rr = wg_sum(ri * ri, s_red[2]);
+        rr = wg_sum(rrp, s_red[2]);
         if (rr <= thresh) {
           state = 1;
           break;
@@ -254,16 +301,26 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
         }
         const double beta = a.flexible ? -zq / pq : rzn / rz;
         rz = rzn;
-        if (own) s_p[t] = s_z[t] + beta * s_p[t];
+#pragma unroll
+        for (int q = 0; q < kSR; ++q)
+          if (own[q]) s_p[row[q]] = s_z[row[q]] + beta * s_p[row[q]];
       }
       if (state < 0) break;
       // true residual r = b - A x
       __syncthreads();
-      if (own) s_xc[t] = xi;
+#pragma unroll
+      for (int q = 0; q < kSR; ++q)
+        if (own[q]) s_xc[row[q]] = xi[q];
       __syncthreads();
-      const double ti = own ? bi - arow(s_xc) : 0.0;
-      if (own) s_r[t] = ti;
-      trr = wg_sum(ti * ti, s_red[3]);
+      double tp = 0.0;
+#pragma unroll
+      for (int q = 0; q < kSR; ++q) {
+        if (!own[q]) continue;
+        const double ti = bi[q] - arow(q, s_xc);
+        s_r[row[q]] = ti;
+        tp += ti * ti;
+      }
+      trr = wg_sum(tp, s_red[3]);
       if (trr <= thresh) break;
       if (state == 1 && restarts < 5 && iters < a.maxiter) {
         ++restarts;
@@ -273,7 +330,9 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
       break;
     }
   }
-  if (own) a.x[t] = state == 3 ? 0.0 : xi;
+#pragma unroll
+  for (int q = 0; q < kSR; ++q)
+    if (own[q]) a.x[row[q]] = state == 3 ? 0.0 : xi[q];
   if (t == 0) {
     Ctl& c = *a.ctl;
     c.bb = bb;
@@ -306,7 +365,7 @@ bool small_solve_ok(Hierarchy& H) {
       H.prm.nu_post != 1 || H.prm.solver != AMG_SOLVER_PCG || !H.prm.symmetric)
     return false;
   const Level& L = H.lv[0];
-  if (L.n > kST || L.n < 1 || H.co.m > kSCoarse || H.co.n != L.nagg || L.nagg < 1) return false;
+  if (L.n > kSN || L.n < 1 || H.co.m > kSCoarse || H.co.n != L.nagg || L.nagg < 1) return false;
   auto maxrow = [](const DBuf<int>& rp, int n) {
     std::vector<int> h(n + 1);
     AMG_HIP(hipMemcpy(h.data(), rp.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
