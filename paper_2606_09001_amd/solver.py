@@ -17,7 +17,7 @@ import torch
 from . import _lib
 
 __all__ = ["AmgHierarchy", "solve", "amg_solve", "AmgSolve", "make_params", "finalize", "cache_size",
-           "set_cache_capacity", "make_preconditioner", "MatrixFreeOperator", "detect_pattern"]
+           "set_cache_capacity", "make_preconditioner", "MatrixFreeOperator"]
 
 _PARAM_KEYS = ("vcycle_prec", "transfer_bf16", "theta", "max_coarse", "max_levels", "smoother", "omega", "nu_pre",
                "nu_post", "maxiter", "flexible", "symmetric", "check_every", "use_graphs", "autotune",
@@ -354,27 +354,6 @@ class MatrixFreeOperator:
     def solve(self, b: torch.Tensor, tol: float = 1e-8, **params):
         """Differentiable solve A x = b with the assembled operator."""
         return amg_solve(self.row_ptr, self.col, self.assemble(), b, tol, **params)
-
-
-def detect_pattern(matvec, n: int, device="cuda"):
-    """Sparsity pattern of an operator by probing with one-hot vectors (the
-    paper's fallback when the operator cannot be traced): n applications, so
-    meant for modest n.  Returns (row_ptr, col) with every diagonal included."""
-    rows, cols = [], []
-    with torch.no_grad():
-        for j in range(n):
-            e = torch.zeros(n, dtype=torch.float64, device=device)
-            e[j] = 1.0
-            nz = torch.nonzero(matvec(e) != 0).flatten()
-            rows.append(nz)
-            cols.append(torch.full_like(nz, j))
-    r = torch.cat(rows + [torch.arange(n, device=device)])
-    c = torch.cat(cols + [torch.arange(n, device=device)])
-    key = torch.unique(r.to(torch.int64) * n + c.to(torch.int64))   # sorted: by row, then column
-    r, c = key // n, key % n
-    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
-    row_ptr[1:] = torch.cumsum(torch.bincount(r, minlength=n), 0)
-    return row_ptr.to(torch.int32), c.to(torch.int32)
 
 
 def make_preconditioner(row_ptr, col, val, **params):

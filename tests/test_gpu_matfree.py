@@ -118,13 +118,6 @@ def test_probe_entry_points_reject_bad_colors():
     assert st == _lib.AMG_ERR_INVALID_ARG
 
 
-def test_detect_pattern_by_one_hot_probing():
-    from paper_2606_09001_amd.solver import detect_pattern
-    rp, ci, v = M.drop_entries(*M.convection_diffusion(9, 2, (10.0, 4.0)), frac=0.3, seed=2)
-    drp, dci = detect_pattern(_stencil_operator(rp, ci, v), len(rp) - 1)
-    assert np.array_equal(host(drp), rp) and np.array_equal(host(dci), ci)
-
-
 def _tridiag_operator(d):
     """tridiag(-1, d, -1) with Dirichlet ends as a callable (the operator of
     Section 3.3; d a torch scalar): y_i = d x_i - x_{i-1} - x_{i+1}, with
