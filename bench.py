@@ -46,9 +46,12 @@ def traffic_from_profiles(kernel_tag: str, src_hash: str):
     return d.get("traffic_bytes_per_launch")
 
 
-def kernel_source_hash():
+def kernel_source_hash(batched=False):
+    """sha256 of the sources that define the profiled kernels: the
+    single-system sweeps (solve.hip) or the batched ones (batch.hip), with the
+    shared header."""
     h = hashlib.sha256()
-    for name in ("solve.hip", "batch.hip", "amg_internal.hpp"):
+    for name in (("batch.hip" if batched else "solve.hip"), "amg_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2606_09001_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -75,16 +78,19 @@ FINE_KERNELS = {  # tag -> (regex on the demangled name, grid rank: 0 = largest 
     "prolong_L1": (_SWEEP + r"OpProlong<double, double> >", 1),
 }
 _WIDE = r"k_wide(?:_st)?<\d+, [^>]*"
-# level-0 sweeps of the batched solves (FP64 cycle).  Their grids are the
-# resident workgroup count on every level, so level 0 is told apart by size:
-# the dispatches within 60 % of the kernel's largest (duration or counter).
-WIDE_KERNELS = {
-    "wide_spmv_dot_L0": (_WIDE + r"WSpmvXpay<", "top"),
-    "wide_pre_L0": (_WIDE + r"WResid<(?:true|false), double, double> >", "top"),
-    "wide_post_L0": (_WIDE + r"WPost<(?:true|false), double, double, double, 1> >", "top"),
-    "wide_restrict_L0": (_WIDE + r"WRestrict<(?:true|false), double, double> >", "top"),
-    "wide_prolong_L0": (_WIDE + r"WProlong<(?:true|false), double, double> >", "top"),
-}
+# level-0 sweeps of the batched solves (FP64 cycle): rhs_* the right-hand
+# sides of one matrix, sys_* the systems sharing a pattern.  Their grids are
+# the resident workgroup count on every level, so level 0 is told apart by
+# size (see _by_grid and _working).
+WIDE_KERNELS = {}
+for _form, _sys in (("rhs", "false"), ("sys", "true")):
+    WIDE_KERNELS.update({
+        f"{_form}_spmv_dot_L0": (_WIDE + rf"WSpmvXpay<{_sys}>", "top"),
+        f"{_form}_pre_L0": (_WIDE + rf"WResid<{_sys}, double, double> >", "top"),
+        f"{_form}_post_L0": (_WIDE + rf"WPost<{_sys}, double, double, double, 1> >", "top"),
+        f"{_form}_restrict_L0": (_WIDE + rf"WRestrict<{_sys}, double, double> >", "top"),
+        f"{_form}_prolong_L0": (_WIDE + rf"WProlong<{_sys}, double, double> >", "top"),
+    })
 BICG_KERNELS = {  # the BiCGSTAB solve's level-0 sweeps (FP64 cycle)
     "A_y_dot_L0": (_SWEEP + r"OpSpmvDots<1> >", 0),
     "A_z_dots_L0": (_SWEEP + r"OpSpmvDots<2> >", 0),
@@ -115,15 +121,29 @@ def _working(durs, spec=None):
     return [d for d in durs if d > 0.3 * top]
 
 
-def _by_grid(rows, spec, grid_key):
+def _by_grid(rows, spec, grid_key, value):
     """Dispatches of one kernel at one level: the kernel's launches whose grid
-    is the rank-th largest of its distinct grids (level 0 has the largest)."""
+    is the rank-th largest of its distinct grids (level 0 has the largest).
+    Rank "top": of the dispatches within 30 % of the largest value (duration
+    or counter; coarser levels are well below that), those of the launch
+    shape (kernel and grid) seen most often there: the autotuner tries each
+    candidate once or twice, the one it keeps for the level runs every
+    iteration."""
     import re
     pattern, rank = spec
     rx = re.compile(pattern)
     sel = [r for r in rows if rx.search(r["Kernel_Name"])]
+    if not sel:
+        return []
     if rank == "top":
-        return sel
+        top = max(value(r) for r in sel)
+        count = {}
+        for r in sel:
+            if value(r) >= 0.3 * top:
+                key = (r["Kernel_Name"], r[grid_key])
+                count[key] = count.get(key, 0) + 1
+        shape = max(count, key=count.get)
+        return [r for r in sel if (r["Kernel_Name"], r[grid_key]) == shape]
     grids = sorted({int(r[grid_key]) for r in sel}, reverse=True)
     if len(grids) <= rank:
         return []
@@ -154,14 +174,16 @@ def summarize_profiles(a):
     summary = {}
     table = profile_table(tag)
     for k, pat in table.items():
-        sel = _by_grid(trace, pat, "Grid_Size_X")
+        sel = _by_grid(trace, pat, "Grid_Size_X", lambda r: int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
         durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
         w = _working(durs, pat)
         if not w:
             continue
         summary[k] = dict(dispatches=len(durs), working=len(w), avg_us=sum(w) / len(w), min_us=min(w), max_us=max(w))
-        lines.append(f"  {k:12s} dispatches {len(durs):5d} working {len(w):5d} avg {summary[k]['avg_us']:8.2f} us "
+        lines.append(f"  {k:16s} dispatches {len(durs):5d} working {len(w):5d} avg {summary[k]['avg_us']:8.2f} us "
                      f"min {min(w):8.2f} max {max(w):8.2f}")
+        if pat[1] == "top":
+            lines.append(f"      {sel[0]['Kernel_Name'][:140]}")
     with open(os.path.join(out_dir, f"{tag}_kernels.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -176,7 +198,7 @@ def summarize_profiles(a):
         factor = max(calib) / (CALIB_MIB * 1024.0)   # counter KiB per known KiB
         res = {}
         for k, pat in profile_table(tag).items():
-            sel = _by_grid(rows, pat, "Grid_Size")
+            sel = _by_grid(rows, pat, "Grid_Size", lambda r: float(r["Counter_Value"]))
             vals = [float(r["Counter_Value"]) for r in sel]
             w = _working(vals, pat)
             if w:
@@ -185,23 +207,24 @@ def summarize_profiles(a):
 
     ff, fetch = per_dispatch(a.fetch_dir, "FETCH_SIZE")
     wf, write = per_dispatch(a.write_dir, "WRITE_SIZE")
-    src = kernel_source_hash()
+    batched = profile_table(tag) is WIDE_KERNELS
+    src = kernel_source_hash(batched)
     txt = [f"# HBM traffic per dispatch: {tag}", "", "commands:", f"    {a.cmd_fetch}", f"    {a.cmd_write}", "",
            f"calibration: negation of {CALIB_MIB} MiB (reads and writes {CALIB_MIB * 1024} KiB); "
            f"FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f} (counter KiB per byte-exact KiB)", "",
-           f"{'kernel':12s} {'FETCH KiB':>12} {'WRITE KiB':>12} {'traffic MB':>11}  dispatches"]
+           f"{'kernel':16s} {'FETCH KiB':>12} {'WRITE KiB':>12} {'traffic MB':>11}  dispatches"]
     for k in profile_table(tag):
         if k not in fetch or k not in write:
             continue
         traffic = fetch[k]["bytes"] + write[k]["bytes"]
-        txt.append(f"{k:12s} {fetch[k]['kib']:12.0f} {write[k]['kib']:12.0f} {traffic / 1e6:11.2f}  "
+        txt.append(f"{k:16s} {fetch[k]['kib']:12.0f} {write[k]['kib']:12.0f} {traffic / 1e6:11.2f}  "
                    f"{fetch[k]['n']}/{write[k]['n']}")
         with open(os.path.join(out_dir, f"{tag}_{k}_pmc.json"), "w") as f:
             json.dump({"kernel": k, "source_sha256": src, "fetch_kib_per_dispatch": fetch[k]["kib"],
                        "write_kib_per_dispatch": write[k]["kib"], "fetch_factor": ff, "write_factor": wf,
                        "traffic_bytes_per_launch": round(traffic), "commands": [a.cmd_fetch, a.cmd_write],
                        "working_avg_us_from_trace": summary.get(k, {}).get("avg_us")}, f, indent=1)
-    txt.append(f"\nkernel source sha256 (solve.hip + batch.hip + amg_internal.hpp): {src}")
+    txt.append(f"\nkernel source sha256 ({'batch.hip' if batched else 'solve.hip'} + amg_internal.hpp): {src}")
     with open(os.path.join(out_dir, f"{tag}_pmc.txt"), "w") as f:
         f.write("\n".join(txt) + "\n")
     print("\n".join(txt))
