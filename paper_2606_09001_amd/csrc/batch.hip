@@ -43,42 +43,125 @@ inline int wide_grid(int64_t n, int LW) {
   return (int)std::max<int64_t>(g, 1);
 }
 
-// Value of stored entry k for column c.  The per-system value arrays
-// ([entry][S]) are streamed once per sweep and are many times larger than
-// the last-level cache: nontemporal loads.
-template <bool SYS, class V>
-__device__ inline V val_at(const V* v, int k, int c, int W) {
-  if constexpr (SYS) return stream_load<true>(v + (int64_t)k * W + c);
-  else return v[k];
+// V consecutive columns of a row-major [rows][W] array as one vector access:
+// a lane of a wide sweep owns V adjacent columns (16-byte accesses for FP64
+// vectors when V = 2).  The element index is a multiple of V and the arrays
+// are aligned to V elements.
+template <class T, int V>
+struct LaneVec {
+  using type = T __attribute__((ext_vector_type(V)));
+};
+template <class T>
+struct LaneVec<T, 1> {
+  using type = T;
+};
+
+template <int V, bool NT = false, class T>
+__device__ inline void ldv(const T* p, int64_t e, T (&o)[V]) {
+  using LT = typename LaneVec<T, V>::type;
+  const LT x = stream_load<NT>(reinterpret_cast<const LT*>(p + e));
+  if constexpr (V == 1) {
+    o[0] = x;
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = x[v];
+  }
 }
-// Per-row quantity (smoother weight) for column c.
-template <bool SYS, class V>
-__device__ inline V row_at(const V* v, int i, int c, int W) {
+
+template <int V, class T>
+__device__ inline void stv(T* p, int64_t e, const T (&in)[V]) {
+  using LT = typename LaneVec<T, V>::type;
+  LT x;
+  if constexpr (V == 1) {
+    x = in[0];
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[v] = in[v];
+  }
+  *reinterpret_cast<LT*>(p + e) = x;
+}
+
+// Values of stored entry k for columns c0 .. c0+V-1.  The per-system value
+// arrays ([entry][S]) are streamed once per sweep and are many times larger
+// than the last-level cache: nontemporal loads.
+template <bool SYS, int V, class VT>
+__device__ inline void vals_at(const VT* v, int64_t k, int c0, int W, VT (&o)[V]) {
+  if constexpr (SYS) {
+    ldv<V, true>(v, k * W + c0, o);
+  } else {
+    const VT a = v[k];
+#pragma unroll
+    for (int u = 0; u < V; ++u) o[u] = a;
+  }
+}
+// Per-row quantity (smoother weight) for columns c0 .. c0+V-1.
+template <bool SYS, int V, class T>
+__device__ inline void rows_at(const T* p, int i, int c0, int W, T (&o)[V]) {
+  if constexpr (SYS) {
+    ldv<V, true>(p, (int64_t)i * W + c0, o);
+  } else {
+    const T a = p[i];
+#pragma unroll
+    for (int u = 0; u < V; ++u) o[u] = a;
+  }
+}
+// Per-row quantity for one column (elementwise kernels).
+template <bool SYS, class T>
+__device__ inline T row_at(const T* v, int i, int c, int W) {
   if constexpr (SYS) return stream_load<true>(v + (int64_t)i * W + c);
   else return v[i];
 }
 
 // ----------------------------------------------------------- operators
+//
+// A wide sweep forms, per row and column, s = sum_k mul(a_k, gv[col_k]) over
+// the row's entries in stored order.  Each operator supplies
+//   GT, VT, PT          gathered-vector, matrix-value and sum types
+//   v, gv               the values and the gathered vector ([operand rows][W])
+//   kSquare             gv is indexed like the rows, so a window of it
+//                       around a block's rows can be staged in LDS
+//   cols<V>(c0)         per-column scalars of columns c0 .. c0+V-1
+//   row_in<V>, epi<V>   the row's own operands and its outputs
+// and the sweep's per-column reductions in d[m * V + v].
+
+struct NoCols {};
 
 // r = b - A x  (x = sw o b written by the producer of b)
 template <bool SYS, class T, class BT>
 struct WResid {
   using PT = T;
   using VT = T;
-  static constexpr bool kSys = SYS;
+  using GT = T;
+  static constexpr bool kSys = SYS, kSquare = true;
   static constexpr int NRED = 0;
-  __device__ void bind(int) {}
   const T* v;
   const BT* b;
-  const T* x;
+  const T* gv;
   T* r;
   int W;
-  __device__ PT prod_v(VT a, int j, int c) const { return a * x[(int64_t)j * W + c]; }
+  template <int V>
+  __device__ NoCols cols(int) const { return {}; }
+  __device__ static PT mul(VT a, GT g) { return a * g; }
+  template <int V>
   struct Row {
-    T b;
+    T b[V];
   };
-  __device__ Row row_in(int row, int c) const { return {(T)b[(int64_t)row * W + c]}; }
-  __device__ void epi(int row, int c, PT s, const Row& a, double*) const { r[(int64_t)row * W + c] = a.b - s; }
+  template <int V>
+  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+    BT bb[V];
+    ldv<V>(b, (int64_t)row * W + c0, bb);
+    Row<V> a;
+#pragma unroll
+    for (int u = 0; u < V; ++u) a.b[u] = (T)bb[u];
+    return a;
+  }
+  template <int V>
+  __device__ void epi(int row, int c0, const PT (&s)[V], const Row<V>& a, NoCols, double*) const {
+    T o[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) o[u] = a.b[u] - s[u];
+    stv<V>(r, (int64_t)row * W + c0, o);
+  }
 };
 
 // y = R x ; xc = swc o y
@@ -86,24 +169,43 @@ template <bool SYS, class RT, class T>
 struct WRestrict {
   using PT = T;
   using VT = RT;
-  static constexpr bool kSys = SYS;
+  using GT = T;
+  static constexpr bool kSys = SYS, kSquare = false;
   static constexpr int NRED = 0;
-  __device__ void bind(int) {}
   const RT* v;
-  const T* x;
+  const T* gv;
   T* y;
   const T* swc;
   T* xc;
   int W;
-  __device__ PT prod_v(VT a, int j, int c) const { return (T)ValCvt<RT>::f(a) * x[(int64_t)j * W + c]; }
+  template <int V>
+  __device__ NoCols cols(int) const { return {}; }
+  __device__ static PT mul(VT a, GT g) { return (T)ValCvt<RT>::f(a) * g; }
+  template <int V>
   struct Row {
-    T w;
+    T w[V];
   };
-  __device__ Row row_in(int row, int c) const { return {xc ? row_at<SYS>(swc, row, c, W) : (T)0}; }
-  __device__ void epi(int row, int c, PT s, const Row& a, double*) const {
-    const int64_t e = (int64_t)row * W + c;
-    y[e] = s;
-    if (xc) xc[e] = a.w * s;
+  template <int V>
+  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+    Row<V> a;
+    if (xc) {
+      rows_at<SYS, V>(swc, row, c0, W, a.w);
+    } else {
+#pragma unroll
+      for (int u = 0; u < V; ++u) a.w[u] = (T)0;
+    }
+    return a;
+  }
+  template <int V>
+  __device__ void epi(int row, int c0, const PT (&s)[V], const Row<V>& a, NoCols, double*) const {
+    const int64_t e = (int64_t)row * W + c0;
+    stv<V>(y, e, s);
+    if (xc) {
+      T o[V];
+#pragma unroll
+      for (int u = 0; u < V; ++u) o[u] = a.w[u] * s[u];
+      stv<V>(xc, e, o);
+    }
   }
 };
 
@@ -112,19 +214,33 @@ template <bool SYS, class RT, class T>
 struct WProlong {
   using PT = T;
   using VT = RT;
-  static constexpr bool kSys = SYS;
+  using GT = T;
+  static constexpr bool kSys = SYS, kSquare = false;
   static constexpr int NRED = 0;
-  __device__ void bind(int) {}
   const RT* v;
-  const T* xc;
+  const T* gv;
   T* x;
   int W;
-  __device__ PT prod_v(VT a, int j, int c) const { return (T)ValCvt<RT>::f(a) * xc[(int64_t)j * W + c]; }
+  template <int V>
+  __device__ NoCols cols(int) const { return {}; }
+  __device__ static PT mul(VT a, GT g) { return (T)ValCvt<RT>::f(a) * g; }
+  template <int V>
   struct Row {
-    T x;
+    T x[V];
   };
-  __device__ Row row_in(int row, int c) const { return {x[(int64_t)row * W + c]}; }
-  __device__ void epi(int row, int c, PT s, const Row& a, double*) const { x[(int64_t)row * W + c] = a.x + s; }
+  template <int V>
+  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+    Row<V> a;
+    ldv<V>(x, (int64_t)row * W + c0, a.x);
+    return a;
+  }
+  template <int V>
+  __device__ void epi(int row, int c0, const PT (&s)[V], const Row<V>& a, NoCols, double*) const {
+    T o[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) o[u] = a.x[u] + s[u];
+    stv<V>(x, (int64_t)row * W + c0, o);
+  }
 };
 
 // out = x + sw o (b - A x); RED >= 1: <b, out>, RED == 2: <out, q> per column
@@ -132,34 +248,46 @@ template <bool SYS, class T, class BT, class OT, int RED>
 struct WPost {
   using PT = T;
   using VT = T;
-  static constexpr bool kSys = SYS;
+  using GT = T;
+  static constexpr bool kSys = SYS, kSquare = true;
   static constexpr int NRED = RED;
-  __device__ void bind(int) {}
   const T* v;
   const T* sw;
   const BT* b;
-  const T* x;
+  const T* gv;
   OT* out;
   const double* q;
   int W;
-  __device__ PT prod_v(VT a, int j, int c) const { return a * x[(int64_t)j * W + c]; }
+  template <int V>
+  __device__ NoCols cols(int) const { return {}; }
+  __device__ static PT mul(VT a, GT g) { return a * g; }
+  template <int V>
   struct Row {
-    BT b;
-    T x, w;
-    double q;
+    BT b[V];
+    T x[V], w[V];
+    double q[V];
   };
-  __device__ Row row_in(int row, int c) const {
-    const int64_t e = (int64_t)row * W + c;
-    Row a{b[e], x[e], row_at<SYS>(sw, row, c, W), 0.0};
-    if constexpr (RED >= 2) a.q = q[e];
+  template <int V>
+  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+    const int64_t e = (int64_t)row * W + c0;
+    Row<V> a;
+    ldv<V>(b, e, a.b);
+    ldv<V>(gv, e, a.x);
+    rows_at<SYS, V>(sw, row, c0, W, a.w);
+    if constexpr (RED >= 2) ldv<V>(q, e, a.q);
     return a;
   }
-  __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
-    const T o = a.x + a.w * ((T)a.b - s);
-    const OT oo = (OT)o;
-    out[(int64_t)row * W + c] = oo;
-    if constexpr (RED >= 1) d[0] += (double)a.b * (double)oo;
-    if constexpr (RED >= 2) d[1] += (double)oo * a.q;
+  template <int V>
+  __device__ void epi(int row, int c0, const PT (&s)[V], const Row<V>& a, NoCols, double* d) const {
+    OT oo[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const T o = a.x[u] + a.w[u] * ((T)a.b[u] - s[u]);
+      oo[u] = (OT)o;
+      if constexpr (RED >= 1) d[u] += (double)a.b[u] * (double)oo[u];
+      if constexpr (RED >= 2) d[V + u] += (double)oo[u] * a.q[u];
+    }
+    stv<V>(out, (int64_t)row * W + c0, oo);
   }
 };
 
@@ -169,40 +297,63 @@ template <bool SYS>
 struct WSpmvXpay {
   using PT = double;
   using VT = double;
-  static constexpr bool kSys = SYS;
+  using GT = double;
+  static constexpr bool kSys = SYS, kSquare = true;
   static constexpr int NRED = 1;
   const double* v;
-  const double* z;
+  const double* gv;  // z
   const double* p;
   double* pn;
   double* q;
   const WCtl* ctl;
   int W;
-  struct Row {
-    double pr, qo;
-  };
   // q' = A p' is formed as A z + beta q (the same vector in exact
   // arithmetic, since q = A p), so the sweep gathers z only; p and q are read
   // at the row itself.  Both row operands are always loaded (no divergent
   // branch around a load); a column that (re)starts takes p' = z, q' = A z.
-  double beta_c = 0.0;  // this lane's column scalars, read once by bind()
-  int first_c = 1;
-  __device__ void bind(int c) {
-    beta_c = ctl[c].beta;
-    first_c = ctl[c].first;
+  template <int V>
+  struct Cols {
+    double beta[V];
+    int first[V];
+  };
+  template <int V>
+  __device__ Cols<V> cols(int c0) const {
+    Cols<V> k;
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      k.beta[u] = ctl[c0 + u].beta;
+      k.first[u] = ctl[c0 + u].first;
+    }
+    return k;
   }
-  __device__ PT prod_v(VT a, int j, int c) const { return a * z[(int64_t)j * W + c]; }
-  __device__ Row row_in(int row, int c) const {
-    const int64_t e = (int64_t)row * W + c;
-    const double zz = z[e], pp = p[e], qq = q[e];
-    return {first_c ? zz : zz + beta_c * pp, qq};
+  __device__ static PT mul(VT a, GT g) { return a * g; }
+  template <int V>
+  struct Row {
+    double pr[V], qo[V];
+  };
+  template <int V>
+  __device__ Row<V> row_in(int row, int c0, const Cols<V>& k) const {
+    const int64_t e = (int64_t)row * W + c0;
+    double zz[V], pp[V];
+    Row<V> a;
+    ldv<V>(gv, e, zz);
+    ldv<V>(p, e, pp);
+    ldv<V>(q, e, a.qo);
+#pragma unroll
+    for (int u = 0; u < V; ++u) a.pr[u] = k.first[u] ? zz[u] : zz[u] + k.beta[u] * pp[u];
+    return a;
   }
-  __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
-    const int64_t e = (int64_t)row * W + c;
-    pn[e] = a.pr;
-    const double qn = first_c ? s : s + beta_c * a.qo;
-    q[e] = qn;
-    d[0] += a.pr * qn;
+  template <int V>
+  __device__ void epi(int row, int c0, const PT (&s)[V], const Row<V>& a, const Cols<V>& k, double* d) const {
+    const int64_t e = (int64_t)row * W + c0;
+    double qn[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      qn[u] = k.first[u] ? s[u] : s[u] + k.beta[u] * a.qo[u];
+      d[u] += a.pr[u] * qn[u];
+    }
+    stv<V>(pn, e, a.pr);
+    stv<V>(q, e, qn);
   }
 };
 
@@ -211,42 +362,58 @@ template <bool SYS>
 struct WTrueResid {
   using PT = double;
   using VT = double;
-  static constexpr bool kSys = SYS;
+  using GT = double;
+  static constexpr bool kSys = SYS, kSquare = true;
   static constexpr int NRED = 1;
-  __device__ void bind(int) {}
   const double* v;
-  const double* x;
+  const double* gv;  // x
   const double* b;
   double* r;
   int W;
+  template <int V>
+  __device__ NoCols cols(int) const { return {}; }
+  __device__ static PT mul(VT a, GT g) { return a * g; }
+  template <int V>
   struct Row {
-    double b;
+    double b[V];
   };
-  __device__ PT prod_v(VT a, int j, int c) const { return a * x[(int64_t)j * W + c]; }
-  __device__ Row row_in(int row, int c) const { return {b[(int64_t)row * W + c]}; }
-  __device__ void epi(int row, int c, PT s, const Row& a, double* d) const {
-    const double ri = a.b - s;
-    r[(int64_t)row * W + c] = ri;
-    d[0] += ri * ri;
+  template <int V>
+  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+    Row<V> a;
+    ldv<V>(b, (int64_t)row * W + c0, a.b);
+    return a;
+  }
+  template <int V>
+  __device__ void epi(int row, int c0, const PT (&s)[V], const Row<V>& a, NoCols, double* d) const {
+    double o[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      o[u] = a.b[u] - s[u];
+      d[u] += o[u] * o[u];
+    }
+    stv<V>(r, (int64_t)row * W + c0, o);
   }
 };
 
 // Column-wise partial sums of one workgroup, folded over its rows in a
-// fixed order: partials[(m*W + c)*gridDim + block].
-template <int LW, int NRED>
-__device__ inline void publish_w(double (&d)[NRED > 0 ? NRED : 1], int W, double* partials) {
+// fixed order: partials[(m*W + c)*gridDim + block].  d holds the lane's sums
+// for its V columns, d[m*V + v]; lane l of a row group owns columns l*V + v.
+template <int LW, int V, int NRED>
+__device__ inline void publish_w(const double* d, int W, double* partials) {
   if constexpr (NRED > 0) {
-    constexpr int RB = kBlock / LW;
-    __shared__ double red[NRED][kBlock];
+    constexpr int RB = kBlock / LW, LV = LW * V;
+    __shared__ double red[NRED][kBlock * V];
 #pragma unroll
-    for (int m = 0; m < NRED; ++m) red[m][threadIdx.x] = d[m];
+    for (int m = 0; m < NRED; ++m)
+#pragma unroll
+      for (int u = 0; u < V; ++u) red[m][threadIdx.x * V + u] = d[m * V + u];
     __syncthreads();
-    if (threadIdx.x < LW && (int)threadIdx.x < W) {
+    if ((int)threadIdx.x < LV && (int)threadIdx.x < W) {
       const int c = threadIdx.x;
 #pragma unroll
       for (int m = 0; m < NRED; ++m) {
         double s = 0.0;
-        for (int r = 0; r < RB; ++r) s += red[m][r * LW + c];
+        for (int r = 0; r < RB; ++r) s += red[m][r * LV + c];
         partials[((int64_t)m * W + c) * gridDim.x + blockIdx.x] = s;
       }
     }
@@ -288,24 +455,27 @@ __device__ inline WideSched wide_sched(int64_t groups, int spx) {
   return {groups * lb / G, groups * (lb + 1) / G, 1};
 }
 
-template <int LW, class Op>
+template <int LW, int V, class Op>
 __global__ void __launch_bounds__(kBlock) k_wide(int n, int W, int spx, const int* __restrict__ rp,
-                                                 const int* __restrict__ ci, Op op_in,
+                                                 const int* __restrict__ ci, Op op,
                                                  const BatchHead* __restrict__ head, double* __restrict__ partials) {
   if ((head && head->ndone >= head->W) || n <= 0) return;
   using PT = typename Op::PT;
+  using VT = typename Op::VT;
+  using GT = typename Op::GT;
   constexpr int RB = kBlock / LW;
   constexpr int U = 8;
-  const int lr = threadIdx.x / LW, c = threadIdx.x & (LW - 1);
+  constexpr int NR = Op::NRED > 0 ? Op::NRED : 1;
+  const int lr = threadIdx.x / LW, c0 = (threadIdx.x & (LW - 1)) * V;
+  const bool live = c0 < W;
+  const int cc0 = min(c0, W - V);  // lanes past the last column load a valid one and store nothing
   const int64_t groups = ((int64_t)n + RB - 1) / RB;
   const WideSched sc = wide_sched(groups, spx);
-  double d[Op::NRED > 0 ? Op::NRED : 1] = {};
-  const int cc = min(c, W - 1);
-  Op op = op_in;  // per-lane copy holding the column's scalars
-  op.bind(cc);
-  // row pointers of the next row group are loaded one iteration ahead, and
-  // the row's own operands together with its first entries, so that one
-  // iteration waits on memory twice (entries, then gathers)
+  double d[NR * V] = {};
+  const auto cs = op.template cols<V>(cc0);
+  // row pointers of the next row group are loaded one iteration ahead; the
+  // entries of a row are loaded only where they exist (no loads past the
+  // row's end), column indices first so that the U gathers go out together
   int k0 = 0, k1 = 0;
   if (sc.first < sc.end) {
     const int r = (int)min<int64_t>(sc.first * RB + lr, n - 1);
@@ -316,30 +486,38 @@ __global__ void __launch_bounds__(kBlock) k_wide(int n, int W, int spx, const in
     const int row = (int)(g * RB + lr);
     const int rn = min(row + sc.step * RB, n - 1);
     const int kn0 = rp[rn], kn1 = rp[rn + 1];
-    const typename Op::Row in = op.row_in(min(row, n - 1), cc);
-    PT s = 0;
-    if (row < n && c < W) {
+    const auto in = op.template row_in<V>(min(row, n - 1), cc0, cs);
+    PT s[V] = {};
+    if (row < n && live) {
       for (int kb = k0; kb < k1; kb += U) {
-        // unconditional loads (indices clamped to the row's last entry) so
-        // that the U gathers are in flight together; the sum is masked
         int cols[U];
 #pragma unroll
-        for (int e = 0; e < U; ++e) cols[e] = ci[min(kb + e, k1 - 1)];
-        PT pr[U];
+        for (int e = 0; e < U; ++e)
+          if (kb + e < k1) cols[e] = ci[kb + e];
+        PT pr[U][V];
 #pragma unroll
         for (int e = 0; e < U; ++e) {
-          const int k = min(kb + e, k1 - 1);
-          pr[e] = op.prod_v(val_at<Op::kSys>(op.v, k, cc, W), cols[e], c);
+          if (kb + e < k1) {
+            VT a[V];
+            GT x[V];
+            vals_at<Op::kSys, V>(op.v, kb + e, c0, W, a);
+            ldv<V>(op.gv, (int64_t)cols[e] * W + c0, x);
+#pragma unroll
+            for (int u = 0; u < V; ++u) pr[e][u] = Op::mul(a[u], x[u]);
+          }
         }
 #pragma unroll
-        for (int e = 0; e < U; ++e) s = kb + e < k1 ? s + pr[e] : s;
+        for (int e = 0; e < U; ++e)
+          if (kb + e < k1)
+#pragma unroll
+            for (int u = 0; u < V; ++u) s[u] += pr[e][u];
       }
-      op.epi(row, c, s, in, d);
+      op.template epi<V>(row, c0, s, in, cs, d);
     }
     k0 = kn0;
     k1 = kn1;
   }
-  publish_w<LW, Op::NRED>(d, W, partials);
+  publish_w<LW, V, Op::NRED>(d, W, partials);
 }
 
 // Instrumented launches (amg_instrument) of the batched solve: the done
@@ -394,7 +572,7 @@ __global__ void __launch_bounds__(kBlock) k_winit(int n, int W, const double* __
       d[0] += bi * bi;
     }
   }
-  publish_w<LW, 1>(d, W, partials);
+  publish_w<LW, 1, 1>(d, W, partials);
 }
 
 // Active columns: x += alpha p, r -= alpha q, x0 = sw o r, <r, r>.
@@ -424,7 +602,7 @@ __global__ void __launch_bounds__(kBlock) k_wupdate(int n, int W, double* __rest
       d[0] += ri * ri;
     }
   }
-  publish_w<LW, 1>(d, W, partials);
+  publish_w<LW, 1, 1>(d, W, partials);
 }
 
 // x0 = sw o r (start of a solve or restart)
@@ -649,36 +827,61 @@ __global__ void __launch_bounds__(kBlock) k_wpattern_grad(int n, int W, const in
 // Staged wide sweep: per block of `br` rows, the workgroup loads the row
 // pointers, the column indices and (shared-value form) the values with
 // coalesced loads into LDS; each group of LW lanes then reads its row's
-// entries from LDS and gathers x[j][c] for its column.  Blocks are scheduled
-// like the row groups of k_wide (streams per XCD); the grid is the number of
-// workgroups that are resident at once.
-constexpr int kWCap = 1024;  // staged entries per block
+// entries from LDS and gathers x[j][c0 .. c0+V) for its columns.  For a
+// square operator the block also stages the window of the gathered vector
+// around its rows (rows r0 - 1 .. r0 + br, when it fits kWinBytes): entries
+// whose column falls in it (the diagonal and its neighbours) are read from
+// LDS, the others from global memory.  Blocks are scheduled like the row
+// groups of k_wide (streams per XCD); the grid is the number of workgroups
+// that are resident at once.
+constexpr int kWCap = 1024;       // staged entries per block
+constexpr int kWinBytes = 17408;  // staged window of the gathered vector
 
-template <int LW, class Op>
+// Rows per block for which the window of a W-column FP64 vector fits.
+inline int window_rows(int W) { return std::max(1, kWinBytes / (8 * std::max(W, 1)) - 2); }
+
+template <int LW, int V, class Op>
 __global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int br, const int* __restrict__ rp,
-                                                    const int* __restrict__ ci, Op op_in,
+                                                    const int* __restrict__ ci, Op op,
                                                     const BatchHead* __restrict__ head,
                                                     double* __restrict__ partials) {
   if ((head && head->ndone >= head->W) || n <= 0) return;
   using PT = typename Op::PT;
   using VT = typename Op::VT;
+  using GT = typename Op::GT;
   constexpr bool SYS = Op::kSys;
   constexpr int RB = kBlock / LW;
   constexpr int U = kWCap / kBlock;
+  constexpr int NR = Op::NRED > 0 ? Op::NRED : 1;
+  constexpr int WE = Op::kSquare ? kWinBytes / (int)sizeof(GT) : 1;
   __shared__ int s_rp[kBlock + 1];
   __shared__ int s_ci[kWCap];
   __shared__ VT s_v[SYS ? 1 : kWCap];
-  const int lr = threadIdx.x / LW, c = threadIdx.x & (LW - 1);
-  const int cc = min(c, W - 1);
-  Op op = op_in;
-  op.bind(cc);
+  __shared__ __align__(16) GT s_g[WE];
+  const int lr = threadIdx.x / LW, c0 = (threadIdx.x & (LW - 1)) * V;
+  const bool live = c0 < W;
+  const int cc0 = min(c0, W - V);
+  const auto cs = op.template cols<V>(cc0);
   const int64_t blocks = ((int64_t)n + br - 1) / br;
   const WideSched sc = wide_sched(blocks, spx);
-  double d[Op::NRED > 0 ? Op::NRED : 1] = {};
+  const bool win = Op::kSquare && (int64_t)(br + 2) * W <= WE;
+  double d[NR * V] = {};
   for (int64_t blk = sc.first; blk < sc.end; blk += sc.step) {
     const int r0 = (int)(blk * br);
-    __syncthreads();  // the previous block's entries have been read
+    __syncthreads();  // the previous block's entries and window have been read
     for (int t = threadIdx.x; t <= br; t += kBlock) s_rp[t] = rp[min(r0 + t, n)];
+    if (win) {
+      // window row wr holds gathered row r0 - 1 + wr (clamped into the
+      // operand: rows outside it are never referenced)
+      const int nv = (br + 2) * W / V;
+      for (int t = threadIdx.x; t < nv; t += kBlock) {
+        const int wr = t * V / W, cw = t * V - wr * W;
+        const int rr = min(max(r0 - 1 + wr, 0), n - 1);
+        GT x[V];
+        ldv<V>(op.gv, (int64_t)rr * W + cw, x);
+        stv<V>(s_g, (int64_t)wr * W + cw, x);
+      }
+    }
     __syncthreads();
     const int k0 = s_rp[0], nk = s_rp[br] - k0;
     if (nk > 0) {
@@ -702,28 +905,44 @@ __global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int b
     __syncthreads();
     for (int q = lr; q < br; q += RB) {
       const int row = r0 + q;
-      const typename Op::Row in = op.row_in(min(row, n - 1), cc);
-      PT acc = 0;
-      if (row < n && c < W) {
+      const auto in = op.template row_in<V>(min(row, n - 1), cc0, cs);
+      PT acc[V] = {};
+      if (row < n && live) {
         const int a = s_rp[q] - k0, e = s_rp[q + 1] - k0;
         for (int kb = a; kb < e; kb += 8) {
-          PT pr[8];
+          PT pr[8][V];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const int k = min(kb + u, e - 1);
-            VT val;
-            if constexpr (SYS) val = stream_load<true>(op.v + (int64_t)(k0 + k) * W + c);
-            else val = s_v[k];
-            pr[u] = op.prod_v(val, s_ci[k], c);
+            const int k = kb + u;
+            if (k < e) {
+              VT val[V];
+              GT x[V];
+              if constexpr (SYS) {
+                ldv<V, true>(op.v, (int64_t)(k0 + k) * W + c0, val);
+              } else {
+                const VT a1 = s_v[k];
+#pragma unroll
+                for (int w = 0; w < V; ++w) val[w] = a1;
+              }
+              const int col = s_ci[k];
+              const int wr = col - r0 + 1;
+              if (win && wr >= 0 && wr < br + 2) ldv<V>(s_g, (int64_t)wr * W + c0, x);
+              else ldv<V>(op.gv, (int64_t)col * W + c0, x);
+#pragma unroll
+              for (int w = 0; w < V; ++w) pr[u][w] = Op::mul(val[w], x[w]);
+            }
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc = kb + u < e ? acc + pr[u] : acc;
+          for (int u = 0; u < 8; ++u)
+            if (kb + u < e)
+#pragma unroll
+              for (int w = 0; w < V; ++w) acc[w] += pr[u][w];
         }
-        op.epi(row, c, acc, in, d);
+        op.template epi<V>(row, c0, acc, in, cs, d);
       }
     }
   }
-  publish_w<LW, Op::NRED>(d, W, partials);
+  publish_w<LW, V, Op::NRED>(d, W, partials);
 }
 
 // Workgroups of `kernel` resident at once on the device (a multiple of 8).
@@ -747,22 +966,36 @@ int resident_grid(const void* kernel) {
   return g;
 }
 
-// br > 0: staged kernel with br rows per block; 0: direct kernel.
+// Columns per lane of the wide sweeps: two when the width is even (16-byte
+// accesses of FP64 vectors), else one; and the lanes per row that gives.
+inline int wide_v(int W) { return W % 2 == 0 ? 2 : 1; }
+inline int wide_lanes(int W, int V) { return pow2_ceil((W + V - 1) / V); }
+
+#define AMG_DISPATCH_V(vv, ...)                          \
+  switch (vv) {                                          \
+    case 2: { constexpr int V = 2; __VA_ARGS__; } break; \
+    default: { constexpr int V = 1; __VA_ARGS__; } break; \
+  }
+
+// br > 0: staged kernel with br rows per block; 0: direct kernel.  V columns
+// per lane (V divides W; every vector of the operator aligned to V elements).
 template <class Op>
-int wsweep(int LWv, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op,
+int wsweep(int Vc, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op,
            const BatchHead* head, double* partials, hipStream_t s) {
+  if (W % Vc != 0) Vc = 1;
+  const int LWv = wide_lanes(W, Vc);
   int grid = 0;
   if (br > 0) {
-    AMG_DISPATCH_LW(LWv, {
-      const void* kp = reinterpret_cast<const void*>(&k_wide_st<LW, Op>);
+    AMG_DISPATCH_V(Vc, AMG_DISPATCH_LW(LWv, {
+      const void* kp = reinterpret_cast<const void*>(&k_wide_st<LW, V, Op>);
       grid = std::min<int64_t>(resident_grid(kp), std::max<int64_t>(8, ((int64_t)n + br - 1) / br / 8 * 8));
-      hipLaunchKernelGGL((k_wide_st<LW, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, br, rp, ci, op, head,
+      hipLaunchKernelGGL((k_wide_st<LW, V, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, br, rp, ci, op, head,
                          partials);
-    });
+    }));
   } else {
     grid = wide_grid(n, LWv);
-    AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, rp, ci,
-                                            op, head, partials));
+    AMG_DISPATCH_V(Vc, AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, V, Op>), dim3(grid), dim3(kBlock), 0, s, n,
+                                                               W, spx, rp, ci, op, head, partials)));
   }
   return grid;
 }
@@ -774,12 +1007,12 @@ std::vector<int> host_rows(const DBuf<int>& rp, int n) {
 }
 
 // Rows per staged block for a matrix: the largest power of two from the
-// lane group's rows per step up to 256 whose blocks all fit the staging
-// buffer; 0 when even the smallest does not (direct kernel).
-int wide_block_rows(const std::vector<int>& rp, int n, int LWv) {
+// lane group's rows per step up to min(256, max_rows) whose blocks all fit
+// the staging buffer; 0 when even the smallest does not (direct kernel).
+int wide_block_rows(const std::vector<int>& rp, int n, int LWv, int max_rows) {
   const int rb = kBlock / LWv;
   int best = 0;
-  for (int br = rb; br <= kBlock; br <<= 1) {
+  for (int br = rb; br <= kBlock && (br == rb || br <= max_rows); br <<= 1) {
     int mx = 0;
     for (int r0 = 0; r0 < n; r0 += br) mx = std::max(mx, rp[std::min(r0 + br, n)] - rp[r0]);
     if (mx > kWCap) break;
@@ -810,28 +1043,28 @@ struct WB<float> {
 };
 
 template <bool SYS, class T>
-void w_restrict(Hierarchy& H, Level& L, int LWv, int spx, int br, int W, const T* r, T* bc, const T* swc, T* xc,
+void w_restrict(Hierarchy& H, Level& L, int Vc, int spx, int br, int W, const T* r, T* bc, const T* swc, T* xc,
                 hipStream_t s) {
   const BatchHead* hd = H.bt.head.p;
   if constexpr (std::is_same<T, double>::value) {
-    wsweep(LWv, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, double, T>{L.rv.p, r, bc, swc, xc, W}, hd, nullptr, s);
+    wsweep(Vc, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, double, T>{L.rv.p, r, bc, swc, xc, W}, hd, nullptr, s);
   } else if (H.bf16()) {
-    wsweep(LWv, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, uint16_t, T>{L.rbf.p, r, bc, swc, xc, W}, hd, nullptr,
+    wsweep(Vc, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, uint16_t, T>{L.rbf.p, r, bc, swc, xc, W}, hd, nullptr,
            s);
   } else {
-    wsweep(LWv, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, float, T>{L.rv32.p, r, bc, swc, xc, W}, hd, nullptr, s);
+    wsweep(Vc, spx, br, L.nagg, W, L.rrp.p, L.rci.p, WRestrict<SYS, float, T>{L.rv32.p, r, bc, swc, xc, W}, hd, nullptr, s);
   }
 }
 
 template <bool SYS, class T>
-void w_prolong(Hierarchy& H, Level& L, int LWv, int spx, int br, int W, const T* xc, T* x, hipStream_t s) {
+void w_prolong(Hierarchy& H, Level& L, int Vc, int spx, int br, int W, const T* xc, T* x, hipStream_t s) {
   const BatchHead* hd = H.bt.head.p;
   if constexpr (std::is_same<T, double>::value) {
-    wsweep(LWv, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, double, T>{L.pv.p, xc, x, W}, hd, nullptr, s);
+    wsweep(Vc, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, double, T>{L.pv.p, xc, x, W}, hd, nullptr, s);
   } else if (H.bf16()) {
-    wsweep(LWv, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, uint16_t, T>{L.pbf.p, xc, x, W}, hd, nullptr, s);
+    wsweep(Vc, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, uint16_t, T>{L.pbf.p, xc, x, W}, hd, nullptr, s);
   } else {
-    wsweep(LWv, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, float, T>{L.pv32.p, xc, x, W}, hd, nullptr, s);
+    wsweep(Vc, spx, br, L.n, W, L.prp.p, L.pci.p, WProlong<SYS, float, T>{L.pv32.p, xc, x, W}, hd, nullptr, s);
   }
 }
 
@@ -841,7 +1074,7 @@ void w_prolong(Hierarchy& H, Level& L, int LWv, int spx, int br, int W, const T*
 template <bool SYS, class T>
 void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q, int red, hipStream_t s) {
   Batch& B = H.bt;
-  const int LWv = pow2_ceil(W);
+  const int Vc = wide_v(W);
   const int nl = (int)H.lv.size();
   const BatchHead* hd = B.head.p;
   double* part = B.partials.p;
@@ -852,17 +1085,17 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
     {
       WInstScope is(H, KID_PRE, l, s);
       if (l == 0)
-        wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
+        wsweep(Vc, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
                WResid<SYS, T, double>{WB<T>::v(L), r0, WB<T>::x(BL), WB<T>::r(BL), W}, hd, nullptr, s);
       else
-        wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
+        wsweep(Vc, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
                WResid<SYS, T, T>{WB<T>::v(L), WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), W}, hd, nullptr, s);
     }
     Level& Ln = H.lv[l + 1];
     BatchLevel& BN = B.lv[l + 1];
     const bool coarsest = (l + 1 == nl - 1);
     WInstScope is(H, KID_RESTRICT, l, s);
-    w_restrict<SYS, T>(H, L, LWv, BL.spxR, BL.brR, W, WB<T>::r(BL), WB<T>::b(BN), coarsest ? nullptr : WB<T>::sw(Ln),
+    w_restrict<SYS, T>(H, L, Vc, BL.spxR, BL.brR, W, WB<T>::r(BL), WB<T>::b(BN), coarsest ? nullptr : WB<T>::sw(Ln),
                        coarsest ? nullptr : WB<T>::x(BN), s);
   }
   {
@@ -878,7 +1111,7 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
     BatchLevel& BL = B.lv[l];
     {
       WInstScope is(H, KID_PROLONG, l, s);
-      w_prolong<SYS, T>(H, L, LWv, BL.spxP, BL.brP, W, res, WB<T>::x(BL), s);
+      w_prolong<SYS, T>(H, L, Vc, BL.spxP, BL.brP, W, res, WB<T>::x(BL), s);
     }
     const T* vv = WB<T>::v(L);
     const T* sw = WB<T>::sw(L);
@@ -886,13 +1119,13 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
     if (l == 0) {
       int np = 0;
       if (red == 2)
-        np = wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 2>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
+        np = wsweep(Vc, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 2>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
                     hd, part, s);
       else if (red == 1)
-        np = wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 1>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
+        np = wsweep(Vc, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 1>{vv, sw, r0, WB<T>::x(BL), z0, q, W},
                     hd, part, s);
       else
-        wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 0>{vv, sw, r0, WB<T>::x(BL), z0, q, W}, hd,
+        wsweep(Vc, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p, WPost<SYS, T, double, double, 0>{vv, sw, r0, WB<T>::x(BL), z0, q, W}, hd,
                nullptr, s);
       is.end();
       if (red == 2)
@@ -900,7 +1133,7 @@ void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q,
       else if (red == 1)
         hipLaunchKernelGGL(k_wfin_beta<1>, dim3(W), dim3(kWFin), 0, s, B.ctl.p, B.head.p, part, W, np);
     } else {
-      wsweep(LWv, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
+      wsweep(Vc, BL.spxA, BL.brA, L.n, W, L.rp.p, L.ci.p,
              WPost<SYS, T, T, T, 0>{vv, sw, WB<T>::b(BL), WB<T>::x(BL), WB<T>::r(BL), nullptr, W}, hd, nullptr, s);
       res = WB<T>::r(BL);
     }
@@ -960,12 +1193,12 @@ void read_batch(Hierarchy& H, int W, hipStream_t s) {
 // operands and the fastest is kept and recorded in the tuning cache.
 
 template <class Op>
-double time_wide(int LWv, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op, hipStream_t s,
+double time_wide(int Vc, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op, hipStream_t s,
                  hipEvent_t e0, hipEvent_t e1) {
-  wsweep(LWv, spx, br, n, W, rp, ci, op, nullptr, nullptr, s);
+  wsweep(Vc, spx, br, n, W, rp, ci, op, nullptr, nullptr, s);
   AMG_HIP(hipEventRecord(e0, s));
   constexpr int reps = 3;
-  for (int r = 0; r < reps; ++r) wsweep(LWv, spx, br, n, W, rp, ci, op, nullptr, nullptr, s);
+  for (int r = 0; r < reps; ++r) wsweep(Vc, spx, br, n, W, rp, ci, op, nullptr, nullptr, s);
   AMG_HIP(hipEventRecord(e1, s));
   AMG_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -995,7 +1228,7 @@ int pick_spx(Hierarchy& H, const char* kind, int W, int& br, int n, int nnz, con
     br = sh.g ? br : 0;
     return sh.stream;
   }
-  const int LWv = pow2_ceil(W);
+  const int Vc = wide_v(W);
   hipEvent_t e0, e1;
   AMG_HIP(hipEventCreate(&e0));
   AMG_HIP(hipEventCreate(&e1));
@@ -1003,7 +1236,7 @@ int pick_spx(Hierarchy& H, const char* kind, int W, int& br, int n, int nnz, con
   double tbest = 1e300;
   for (int form : {br, 0}) {  // staged (when the blocks fit), then direct
     for (int spx : spx_candidates()) {
-      const double t = time_wide(LWv, spx, form, n, W, rp, ci, op, s, e0, e1);
+      const double t = time_wide(Vc, spx, form, n, W, rp, ci, op, s, e0, e1);
       if (t < tbest) {
         tbest = t;
         best = spx;
@@ -1027,16 +1260,17 @@ void tune_wide(Hierarchy& H, int W, hipStream_t s) {
   Batch& B = H.bt;
   if (B.tuned_W == W) return;
   B.tuned_W = W;
-  const int LWv = pow2_ceil(W);
+  const int LWv = wide_lanes(W, wide_v(W));
   for (size_t l = 0; l < H.lv.size(); ++l) {
     BatchLevel& BL = B.lv[l];
     Level& L = H.lv[l];
     BL.spxA = BL.spxP = BL.spxR = 0;
     BL.brA = BL.brP = BL.brR = 0;
     if (l + 1 == H.lv.size()) continue;
-    BL.brA = wide_block_rows(host_rows(L.rp, L.n), L.n, LWv);
-    BL.brP = wide_block_rows(host_rows(L.prp, L.n), L.n, LWv);
-    BL.brR = wide_block_rows(host_rows(L.rrp, L.nagg), L.nagg, LWv);
+    // A's blocks are sized so that the window of its gathered vector fits
+    BL.brA = wide_block_rows(host_rows(L.rp, L.n), L.n, LWv, window_rows(W));
+    BL.brP = wide_block_rows(host_rows(L.prp, L.n), L.n, LWv, kBlock);
+    BL.brR = wide_block_rows(host_rows(L.rrp, L.nagg), L.nagg, LWv, kBlock);
     // per-system values cannot be staged: the direct form is the default there
     if (SYS && !H.prm.autotune) BL.brA = BL.brP = BL.brR = 0;
   }
@@ -1120,7 +1354,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
     int np;
     {
       WInstScope is(H, KID_SPMV_DOT, 0, stq);
-      np = wsweep(LWv, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p,
+      np = wsweep(wide_v(W), B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p,
                   WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W}, B.head.p, part, stq);
     }
     hipLaunchKernelGGL(k_wfin_alpha, dim3(W), dim3(kWFin), 0, stq, B.ctl.p, B.head.p, part, W, np);
@@ -1183,7 +1417,10 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
       }
     }
     // true residuals of every column
-    const int np = wsweep(LWv, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p, WTrueResid<SYS>{L0.v.p, d_x, d_b, B.r.p, W}, nullptr, part, s);
+    // the caller's x and b take two columns per lane only when 16-byte aligned
+    const bool al = (((uintptr_t)d_x | (uintptr_t)d_b) & 15) == 0;
+    const int np = wsweep(al ? wide_v(W) : 1, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p,
+                          WTrueResid<SYS>{L0.v.p, d_x, d_b, B.r.p, W}, nullptr, part, s);
     hipLaunchKernelGGL(k_wfin_trr, dim3(W), dim3(kWFin), 0, s, B.ctl.p, part, W, np);
     read_batch(H, W, s);
     int nre = 0;
