@@ -121,7 +121,9 @@ __device__ inline T row_at(const T* v, int i, int c, int W) {
 //   kSquare             gv is indexed like the rows, so a window of it
 //                       around a block's rows can be staged in LDS
 //   cols<V>(c0)         per-column scalars of columns c0 .. c0+V-1
-//   row_in<V>, epi<V>   the row's own operands and its outputs
+//   row_in<V>, epi<V>   the row's own operands and its outputs; kOwn: row_in
+//                       takes the row's own entries of gv (xo), which the
+//                       sweep reads from the staged window when it has one
 // and the sweep's per-column reductions in d[m * V + v].
 
 struct NoCols {};
@@ -132,7 +134,7 @@ struct WResid {
   using PT = T;
   using VT = T;
   using GT = T;
-  static constexpr bool kSys = SYS, kSquare = true;
+  static constexpr bool kSys = SYS, kSquare = true, kOwn = false;
   static constexpr int NRED = 0;
   const T* v;
   const BT* b;
@@ -147,7 +149,7 @@ struct WResid {
     T b[V];
   };
   template <int V>
-  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+  __device__ Row<V> row_in(int row, int c0, NoCols, const GT (&)[V]) const {
     BT bb[V];
     ldv<V>(b, (int64_t)row * W + c0, bb);
     Row<V> a;
@@ -170,7 +172,7 @@ struct WRestrict {
   using PT = T;
   using VT = RT;
   using GT = T;
-  static constexpr bool kSys = SYS, kSquare = false;
+  static constexpr bool kSys = SYS, kSquare = false, kOwn = false;
   static constexpr int NRED = 0;
   const RT* v;
   const T* gv;
@@ -186,7 +188,7 @@ struct WRestrict {
     T w[V];
   };
   template <int V>
-  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+  __device__ Row<V> row_in(int row, int c0, NoCols, const GT (&)[V]) const {
     Row<V> a;
     if (xc) {
       rows_at<SYS, V>(swc, row, c0, W, a.w);
@@ -215,7 +217,7 @@ struct WProlong {
   using PT = T;
   using VT = RT;
   using GT = T;
-  static constexpr bool kSys = SYS, kSquare = false;
+  static constexpr bool kSys = SYS, kSquare = false, kOwn = false;
   static constexpr int NRED = 0;
   const RT* v;
   const T* gv;
@@ -229,7 +231,7 @@ struct WProlong {
     T x[V];
   };
   template <int V>
-  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+  __device__ Row<V> row_in(int row, int c0, NoCols, const GT (&)[V]) const {
     Row<V> a;
     ldv<V>(x, (int64_t)row * W + c0, a.x);
     return a;
@@ -249,7 +251,7 @@ struct WPost {
   using PT = T;
   using VT = T;
   using GT = T;
-  static constexpr bool kSys = SYS, kSquare = true;
+  static constexpr bool kSys = SYS, kSquare = true, kOwn = true;
   static constexpr int NRED = RED;
   const T* v;
   const T* sw;
@@ -268,11 +270,12 @@ struct WPost {
     double q[V];
   };
   template <int V>
-  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+  __device__ Row<V> row_in(int row, int c0, NoCols, const GT (&xo)[V]) const {
     const int64_t e = (int64_t)row * W + c0;
     Row<V> a;
     ldv<V>(b, e, a.b);
-    ldv<V>(gv, e, a.x);
+#pragma unroll
+    for (int u = 0; u < V; ++u) a.x[u] = xo[u];
     rows_at<SYS, V>(sw, row, c0, W, a.w);
     if constexpr (RED >= 2) ldv<V>(q, e, a.q);
     return a;
@@ -298,7 +301,7 @@ struct WSpmvXpay {
   using PT = double;
   using VT = double;
   using GT = double;
-  static constexpr bool kSys = SYS, kSquare = true;
+  static constexpr bool kSys = SYS, kSquare = true, kOwn = true;
   static constexpr int NRED = 1;
   const double* v;
   const double* gv;  // z
@@ -332,11 +335,10 @@ struct WSpmvXpay {
     double pr[V], qo[V];
   };
   template <int V>
-  __device__ Row<V> row_in(int row, int c0, const Cols<V>& k) const {
+  __device__ Row<V> row_in(int row, int c0, const Cols<V>& k, const GT (&zz)[V]) const {
     const int64_t e = (int64_t)row * W + c0;
-    double zz[V], pp[V];
+    double pp[V];
     Row<V> a;
-    ldv<V>(gv, e, zz);
     ldv<V>(p, e, pp);
     ldv<V>(q, e, a.qo);
 #pragma unroll
@@ -363,7 +365,7 @@ struct WTrueResid {
   using PT = double;
   using VT = double;
   using GT = double;
-  static constexpr bool kSys = SYS, kSquare = true;
+  static constexpr bool kSys = SYS, kSquare = true, kOwn = false;
   static constexpr int NRED = 1;
   const double* v;
   const double* gv;  // x
@@ -378,7 +380,7 @@ struct WTrueResid {
     double b[V];
   };
   template <int V>
-  __device__ Row<V> row_in(int row, int c0, NoCols) const {
+  __device__ Row<V> row_in(int row, int c0, NoCols, const GT (&)[V]) const {
     Row<V> a;
     ldv<V>(b, (int64_t)row * W + c0, a.b);
     return a;
@@ -486,7 +488,9 @@ __global__ void __launch_bounds__(kBlock) k_wide(int n, int W, int spx, const in
     const int row = (int)(g * RB + lr);
     const int rn = min(row + sc.step * RB, n - 1);
     const int kn0 = rp[rn], kn1 = rp[rn + 1];
-    const auto in = op.template row_in<V>(min(row, n - 1), cc0, cs);
+    GT xo[V];
+    if constexpr (Op::kOwn) ldv<V>(op.gv, (int64_t)min(row, n - 1) * W + cc0, xo);
+    const auto in = op.template row_in<V>(min(row, n - 1), cc0, cs, xo);
     PT s[V] = {};
     if (row < n && live) {
       for (int kb = k0; kb < k1; kb += U) {
@@ -905,7 +909,12 @@ __global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int b
     __syncthreads();
     for (int q = lr; q < br; q += RB) {
       const int row = r0 + q;
-      const auto in = op.template row_in<V>(min(row, n - 1), cc0, cs);
+      GT xo[V];
+      if constexpr (Op::kOwn) {
+        if (win) ldv<V>(s_g, (int64_t)(min(row, n - 1) - r0 + 1) * W + cc0, xo);
+        else ldv<V>(op.gv, (int64_t)min(row, n - 1) * W + cc0, xo);
+      }
+      const auto in = op.template row_in<V>(min(row, n - 1), cc0, cs, xo);
       PT acc[V] = {};
       if (row < n && live) {
         const int a = s_rp[q] - k0, e = s_rp[q + 1] - k0;
@@ -966,38 +975,49 @@ int resident_grid(const void* kernel) {
   return g;
 }
 
-// Columns per lane of the wide sweeps: two when the width is even (16-byte
-// accesses of FP64 vectors), else one; and the lanes per row that gives.
-inline int wide_v(int W) { return W % 2 == 0 ? 2 : 1; }
+// Columns per lane of a wide sweep: as many as make a 16-byte access of the
+// gathered vector (two FP64 or four FP32 columns) and divide the width, at
+// most vmax (1 for vectors not aligned to 16 bytes); and the lanes per row.
+inline int wide_v(int W, int elem_bytes, int vmax) {
+  int v = std::min(vmax, 16 / elem_bytes);
+  while (v > 1 && W % v != 0) v >>= 1;
+  return std::max(v, 1);
+}
 inline int wide_lanes(int W, int V) { return pow2_ceil((W + V - 1) / V); }
 
-#define AMG_DISPATCH_V(vv, ...)                          \
-  switch (vv) {                                          \
-    case 2: { constexpr int V = 2; __VA_ARGS__; } break; \
-    default: { constexpr int V = 1; __VA_ARGS__; } break; \
-  }
-
-// br > 0: staged kernel with br rows per block; 0: direct kernel.  V columns
-// per lane (V divides W; every vector of the operator aligned to V elements).
-template <class Op>
-int wsweep(int Vc, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op,
-           const BatchHead* head, double* partials, hipStream_t s) {
-  if (W % Vc != 0) Vc = 1;
-  const int LWv = wide_lanes(W, Vc);
+// br > 0: staged kernel with br rows per block; 0: direct kernel.
+template <int V, class Op>
+int wsweep_v(int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op, const BatchHead* head,
+             double* partials, hipStream_t s) {
+  const int LWv = wide_lanes(W, V);
   int grid = 0;
   if (br > 0) {
-    AMG_DISPATCH_V(Vc, AMG_DISPATCH_LW(LWv, {
+    AMG_DISPATCH_LW(LWv, {
       const void* kp = reinterpret_cast<const void*>(&k_wide_st<LW, V, Op>);
       grid = std::min<int64_t>(resident_grid(kp), std::max<int64_t>(8, ((int64_t)n + br - 1) / br / 8 * 8));
       hipLaunchKernelGGL((k_wide_st<LW, V, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, br, rp, ci, op, head,
                          partials);
-    }));
+    });
   } else {
     grid = wide_grid(n, LWv);
-    AMG_DISPATCH_V(Vc, AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, V, Op>), dim3(grid), dim3(kBlock), 0, s, n,
-                                                               W, spx, rp, ci, op, head, partials)));
+    AMG_DISPATCH_LW(LWv, hipLaunchKernelGGL((k_wide<LW, V, Op>), dim3(grid), dim3(kBlock), 0, s, n, W, spx, rp, ci,
+                                            op, head, partials));
   }
   return grid;
+}
+
+// A wide sweep with the columns per lane wide_v gives (every vector of the
+// operator aligned to 16 bytes unless vmax = 1).
+template <class Op>
+int wsweep(int vmax, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op,
+           const BatchHead* head, double* partials, hipStream_t s) {
+  constexpr int eb = (int)sizeof(typename Op::GT);
+  const int v = wide_v(W, eb, vmax);
+  if constexpr (eb == 4) {
+    if (v == 4) return wsweep_v<4>(spx, br, n, W, rp, ci, op, head, partials, s);
+  }
+  if (v >= 2) return wsweep_v<2>(spx, br, n, W, rp, ci, op, head, partials, s);
+  return wsweep_v<1>(spx, br, n, W, rp, ci, op, head, partials, s);
 }
 
 std::vector<int> host_rows(const DBuf<int>& rp, int n) {
@@ -1074,7 +1094,7 @@ void w_prolong(Hierarchy& H, Level& L, int Vc, int spx, int br, int W, const T* 
 template <bool SYS, class T>
 void wvcycle(Hierarchy& H, int W, const double* r0, double* z0, const double* q, int red, hipStream_t s) {
   Batch& B = H.bt;
-  const int Vc = wide_v(W);
+  const int Vc = 4;  // columns per lane: the widest the operands allow
   const int nl = (int)H.lv.size();
   const BatchHead* hd = B.head.p;
   double* part = B.partials.p;
@@ -1228,7 +1248,7 @@ int pick_spx(Hierarchy& H, const char* kind, int W, int& br, int n, int nnz, con
     br = sh.g ? br : 0;
     return sh.stream;
   }
-  const int Vc = wide_v(W);
+  const int Vc = 4;
   hipEvent_t e0, e1;
   AMG_HIP(hipEventCreate(&e0));
   AMG_HIP(hipEventCreate(&e1));
@@ -1260,7 +1280,7 @@ void tune_wide(Hierarchy& H, int W, hipStream_t s) {
   Batch& B = H.bt;
   if (B.tuned_W == W) return;
   B.tuned_W = W;
-  const int LWv = wide_lanes(W, wide_v(W));
+  const int LWv = wide_lanes(W, wide_v(W, 8, 2));
   for (size_t l = 0; l < H.lv.size(); ++l) {
     BatchLevel& BL = B.lv[l];
     Level& L = H.lv[l];
@@ -1354,7 +1374,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
     int np;
     {
       WInstScope is(H, KID_SPMV_DOT, 0, stq);
-      np = wsweep(wide_v(W), B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p,
+      np = wsweep(4, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p,
                   WSpmvXpay<SYS>{L0.v.p, B.z.p, pb[c], pb[c ^ 1], B.q.p, B.ctl.p, W}, B.head.p, part, stq);
     }
     hipLaunchKernelGGL(k_wfin_alpha, dim3(W), dim3(kWFin), 0, stq, B.ctl.p, B.head.p, part, W, np);
@@ -1419,7 +1439,7 @@ amg_status solve_wide_impl(Hierarchy& H, const SolveOpts& o, const double* d_b, 
     // true residuals of every column
     // the caller's x and b take two columns per lane only when 16-byte aligned
     const bool al = (((uintptr_t)d_x | (uintptr_t)d_b) & 15) == 0;
-    const int np = wsweep(al ? wide_v(W) : 1, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p,
+    const int np = wsweep(al ? 4 : 1, B.lv[0].spxA, B.lv[0].brA, n, W, L0.rp.p, L0.ci.p,
                           WTrueResid<SYS>{L0.v.p, d_x, d_b, B.r.p, W}, nullptr, part, s);
     hipLaunchKernelGGL(k_wfin_trr, dim3(W), dim3(kWFin), 0, s, B.ctl.p, part, W, np);
     read_batch(H, W, s);
