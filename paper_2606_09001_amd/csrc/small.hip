@@ -7,10 +7,14 @@
 // true-residual check in a single launch:
 //   - the CG vectors and the cycle vectors live in LDS, so every gather of
 //     a sweep is an LDS read;
-//   - each thread keeps its row of A_0 in registers for the whole solve
+//   - each thread keeps its rows of A_0 in registers for the whole solve
 //     (A_0 is applied three times per iteration);
-//   - R_0 is read with a group of lanes per coarse row, the explicit coarse
-//     inverse with all threads (column blocks reduced through LDS);
+//   - P_0 and R_0 are staged in LDS once per solve; R_0 is applied with a
+//     group of lanes per coarse row;
+//   - the explicit coarse inverse is read from global memory (L2) by
+//     wavefront column blocks: a wave takes a block of columns, so each
+//     column's loads have a wave-uniform base and are coalesced over rows,
+//     and the block sums are added per row in wave order;
 //   - dot products are fixed-order block reductions (wave butterfly, then the
 //     16 wave sums in order), so a solve is bitwise reproducible.
 // The method is the one of pcg_solve: PCG from x0 = 0, damped-Jacobi (or L1)
@@ -33,10 +37,12 @@ namespace {
 constexpr int kST = 512;         // threads of the workgroup
 constexpr int kSR = 2;           // fine rows per thread (rows t and t + kST)
 constexpr int kSN = kST * kSR;   // largest fine level
-constexpr int kSRow = 8;         // entries per row of A_0 and P_0
+constexpr int kSRow = 8;         // entries per row of A_0
 constexpr int kSCoarse = 256;    // largest padded coarsest level
-constexpr int kSRLane = 16;      // entries of an R_0 row per lane
-constexpr int kSInv = 16;        // coarse-inverse entries per thread in flight
+constexpr int kSPCap = 3200;     // entries of P_0 (and of R_0 = P_0^T) staged in LDS
+constexpr int kSWaves = kST / 64;
+constexpr int kSRowsPerLane = kSCoarse / 64;  // coarse rows per lane in the inverse product
+constexpr int kSCols = 4;        // inverse columns per step (loads in flight: kSCols x rows per lane)
 
 struct SmallArgs {
   int n, nc, m, lgR, maxiter, flexible;
@@ -71,10 +77,32 @@ __device__ inline int opaque(int v) {
   return v;
 }
 
+// DPP move of a double within rows of 16 lanes (pattern `ctrl`).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the wavefront, every lane gets the same bits: partner sums within
+// quads (lane ^ 1, lane ^ 2), then the mirrored half row and row (lane i with
+// 7 - i and 15 - i of its group), then across rows (lane ^ 16, lane ^ 32).
+// Each step adds two equal-rank partial sums, so all lanes agree.
+__device__ inline double wave_sum_fast(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // Sum of v over the workgroup in a fixed order; every thread gets the total.
 // `red` must not be reused before the next barrier.
 __device__ inline double wg_sum(double v, double* red) {
-  v = wave_sum(v);
+  v = wave_sum_fast(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = red[0];
@@ -86,13 +114,26 @@ __device__ inline double wg_sum(double v, double* red) {
 __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
   __shared__ double s_r[kSN], s_z[kSN], s_p[kSN], s_q[kSN], s_xc[kSN], s_rc[kSN];
   __shared__ double s_b1[kSCoarse], s_x1[kSCoarse];
-  __shared__ double s_gp[kST];
+  __shared__ double s_gp[kSWaves][kSCoarse];
   __shared__ double s_red[4][kST / 64];
+  __shared__ int s_prp[kSN + 1], s_rrp[kSCoarse + 1];
+  __shared__ int s_pci[kSPCap], s_rci[kSPCap];
+  __shared__ double s_pv[kSPCap], s_rv[kSPCap];
   const int t = threadIdx.x;
+  // P_0 and R_0 into LDS (their entry counts are at most kSPCap)
+  const int pnz = a.prp[a.n];
+  for (int i = t; i <= a.n; i += kST) s_prp[i] = a.prp[i];
+  for (int i = t; i <= a.nc; i += kST) s_rrp[i] = a.rrp[i];
+  for (int k = t; k < pnz; k += kST) {
+    s_pci[k] = a.pci[k];
+    s_pv[k] = a.pv[k];
+    s_rci[k] = a.rci[k];
+    s_rv[k] = a.rv[k];
+  }
   // this thread's rows t + q kST: their rows of A_0 in registers (indices
   // clamped into the row; entries past the row's length are masked out of
   // every sum), their smoother weights, right-hand side and iterate
-  int row[kSR], na[kSR], acol[kSR][kSRow], kp[kSR], np[kSR];
+  int row[kSR], na[kSR], acol[kSR][kSRow];
   bool own[kSR];
   double aval[kSR][kSRow], swi[kSR], bi[kSR], xi[kSR];
 #pragma unroll
@@ -110,9 +151,8 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
     swi[q] = a.sw[row[q]];
     bi[q] = own[q] ? a.b[row[q]] : 0.0;
     xi[q] = 0.0;
-    kp[q] = a.prp[row[q]];
-    np[q] = a.prp[row[q] + 1] - kp[q];
   }
+  __syncthreads();
   // row q of A_0 applied to an LDS vector, summed in stored order
   auto arow = [&](int q, const double* v) {
     double s = 0.0;
@@ -125,10 +165,14 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
   };
   const int gR = 1 << a.lgR;
   const int rrow = t >> a.lgR, rl = t & (gR - 1);
-  const int rk0 = rrow < a.nc ? a.rrp[rrow] : 0, rk1 = rrow < a.nc ? a.rrp[rrow + 1] : 0;
-  const int nb = kST / a.m;                       // column blocks of the coarse product
-  const int ic = t % a.m, jb = t / a.m;
-  const int L = (a.nc + nb - 1) / nb;
+  // coarse product: wave wv takes columns [c0w, c1w), lane ln rows ln + 64 r
+  // (r < rpl); the wave index, column range and row-chunk count are
+  // wave-uniform, so the column loads have scalar base addresses and the
+  // loop has no divergent branches
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6), ln = t & 63;
+  const int Lw = (a.nc + kSWaves - 1) / kSWaves;
+  const int c0w = min(wv * Lw, a.nc), c1w = min(c0w + Lw, a.nc);
+  const int rpl = (a.nc + 63) >> 6;
 
   // z = M^-1 r (s_r -> s_z); returns <r, z>, and <z, q> in zq when flexible
   auto vcycle = [&](double& zq) -> double {
@@ -141,74 +185,73 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
       if (own[q]) s_rc[row[q]] = s_r[row[q]] - arow(q, s_xc);
     __syncthreads();
     {                                              // b_1 = R r_c, gR lanes per coarse row
-      phase_fence();
       double s = 0.0;
       if (rrow < a.nc) {
-        const int k0 = opaque(rk0), k1 = rk1;
-        int c[kSRLane];
-        double v[kSRLane];
-#pragma unroll
-        for (int u = 0; u < kSRLane; ++u) {
-          const int k = min(k0 + rl + u * gR, k1 - 1);
-          c[u] = a.rci[k];
-          v[u] = a.rv[k];
+        const int k1 = s_rrp[rrow + 1];
+        int k = s_rrp[rrow] + rl;
+        for (; k + 3 * gR < k1; k += 4 * gR) {     // four entries per step, summed in order
+          const double p0 = s_rv[k] * s_rc[s_rci[k]];
+          const double p1 = s_rv[k + gR] * s_rc[s_rci[k + gR]];
+          const double p2 = s_rv[k + 2 * gR] * s_rc[s_rci[k + 2 * gR]];
+          const double p3 = s_rv[k + 3 * gR] * s_rc[s_rci[k + 3 * gR]];
+          s = s + p0;
+          s = s + p1;
+          s = s + p2;
+          s = s + p3;
         }
-#pragma unroll
-        for (int u = 0; u < kSRLane; ++u) {
-          const double pr = v[u] * s_rc[c[u]];
-          s = k0 + rl + u * gR < k1 ? s + pr : s;
-        }
+        for (; k < k1; k += gR) s = s + s_rv[k] * s_rc[s_rci[k]];
       }
       for (int o = 1; o < gR; o <<= 1) s += __shfl_xor(s, o, 64);
       if (rrow < a.nc && rl == 0) s_b1[rrow] = s;
     }
     __syncthreads();
-    {                                              // x_1 = A_c^-1 b_1: column blocks, then their sum
+    {                                              // x_1 = A_c^-1 b_1
       phase_fence();
-      if (jb < nb) {
-        double s = 0.0;
-        if (ic < a.nc) {
-          const int j0 = opaque(jb * L), j1 = min(j0 + L, a.nc);
-          for (int jj = j0; jj < j1; jj += kSInv) {
-            double v[kSInv];
+      double acc[kSRowsPerLane];
 #pragma unroll
-            for (int u = 0; u < kSInv; ++u) v[u] = a.inv[(int64_t)min(jj + u, j1 - 1) * a.m + ic];
+      for (int r = 0; r < kSRowsPerLane; ++r) acc[r] = 0.0;
+      const int jend = opaque(c1w);
+      for (int j0 = c0w; j0 < jend; j0 += kSCols) {
+        // columns past the block's end and rows past nc load a valid entry
+        // (clamped) and are left out of the sums
+        double v[kSCols][kSRowsPerLane];
 #pragma unroll
-            for (int u = 0; u < kSInv; ++u) {
-              const double pr = v[u] * s_b1[min(jj + u, j1 - 1)];
-              s = jj + u < j1 ? s + pr : s;
+        for (int u = 0; u < kSCols; ++u) {
+          const double* col = a.inv + (int64_t)min(j0 + u, jend - 1) * a.m;
+#pragma unroll
+          for (int r = 0; r < kSRowsPerLane; ++r)
+            if (r < rpl) v[u][r] = col[min(ln + 64 * r, a.nc - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kSCols; ++u) {
+          const double bj = s_b1[min(j0 + u, jend - 1)];
+#pragma unroll
+          for (int r = 0; r < kSRowsPerLane; ++r) {
+            if (r < rpl) {
+              const double pr = v[u][r] * bj;
+              acc[r] = j0 + u < jend ? acc[r] + pr : acc[r];
             }
           }
         }
-        s_gp[jb * a.m + ic] = s;
       }
+#pragma unroll
+      for (int r = 0; r < kSRowsPerLane; ++r)
+        if (ln + 64 * r < a.nc) s_gp[wv][ln + 64 * r] = acc[r];
       __syncthreads();
-      if (t < a.nc) {
-        double s = s_gp[t];
-        for (int q = 1; q < nb; ++q) s += s_gp[q * a.m + t];
+      if (t < a.nc) {                              // the column blocks' sums in wave order
+        double s = 0.0;
+        for (int q = 0; q < kSWaves; ++q)
+          if (q * Lw < a.nc) s += s_gp[q][t];
         s_x1[t] = s;
       }
     }
     __syncthreads();
-    phase_fence();
 #pragma unroll
     for (int q = 0; q < kSR; ++q) {                // x_c += P x_1
       if (!own[q]) continue;
-      int pcol[kSRow];
-      double pval[kSRow];
-      const int kq = opaque(kp[q]);
-#pragma unroll
-      for (int j = 0; j < kSRow; ++j) {
-        const int k = kq + min(j, max(np[q] - 1, 0));
-        pcol[j] = a.pci[k];
-        pval[j] = a.pv[k];
-      }
+      const int k1 = s_prp[row[q] + 1];
       double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < kSRow; ++j) {
-        const double pr = pval[j] * s_x1[pcol[j]];
-        s = j < np[q] ? s + pr : s;
-      }
+      for (int k = s_prp[row[q]]; k < k1; ++k) s = s + s_pv[k] * s_x1[s_pci[k]];
       s_xc[row[q]] = s_xc[row[q]] + s;
     }
     __syncthreads();
@@ -353,10 +396,11 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
 }  // namespace
 
 // Whether H's solves can run as one workgroup: two levels, at most 1024 fine
-// rows with at most 8 entries per row of A_0 and P_0, a dense coarsest level
-// of at most 256 (padded) rows, and R_0 rows that fit 8 entries per lane of
-// a lane group with (rows x lanes) <= 1024; FP64 V(1,1) cycle of one system,
-// PCG.  Decided once per hierarchy (host copies of the row pointers).
+// rows with at most 8 entries per row of A_0, at most kSPCap entries of P_0,
+// a dense coarsest level of at most 256 (padded) rows; FP64 V(1,1) cycle of
+// one system, PCG.  Decided once per hierarchy (host copies of the row
+// pointers).  R_0 is applied with the most lanes per coarse row (a power of
+// two up to 64) that keeps every coarse row's group within the workgroup.
 bool small_solve_ok(Hierarchy& H) {
   if (H.small_checked) return H.small_lgR >= 0;
   H.small_checked = true;
@@ -365,25 +409,15 @@ bool small_solve_ok(Hierarchy& H) {
       H.prm.nu_post != 1 || H.prm.solver != AMG_SOLVER_PCG || !H.prm.symmetric)
     return false;
   const Level& L = H.lv[0];
-  if (L.n > kSN || L.n < 1 || H.co.m > kSCoarse || H.co.n != L.nagg || L.nagg < 1) return false;
-  auto maxrow = [](const DBuf<int>& rp, int n) {
-    std::vector<int> h(n + 1);
-    AMG_HIP(hipMemcpy(h.data(), rp.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
-    int mx = 0;
-    for (int r = 0; r < n; ++r) mx = std::max(mx, h[r + 1] - h[r]);
-    return mx;
-  };
-  if (maxrow(L.rp, L.n) > kSRow || maxrow(L.prp, L.n) > kSRow) return false;
-  const int mr = maxrow(L.rrp, L.nagg);
-  for (int lg = 0; lg <= 6; ++lg) {
-    const int g = 1 << lg;
-    if (mr <= kSRLane * g && (int64_t)L.nagg * g <= kST) {
-      H.small_lgR = lg;
-      return true;
-    }
-    if ((int64_t)L.nagg * g > kST) break;
-  }
-  return false;
+  if (L.n > kSN || L.n < 1 || H.co.m > kSCoarse || H.co.n != L.nagg || L.nagg < 1 || L.pnnz > kSPCap) return false;
+  std::vector<int> h(L.n + 1);
+  AMG_HIP(hipMemcpy(h.data(), L.rp.p, sizeof(int) * (L.n + 1), hipMemcpyDeviceToHost));
+  for (int r = 0; r < L.n; ++r)
+    if (h[r + 1] - h[r] > kSRow) return false;
+  int lg = 0;
+  while (lg < 6 && (int64_t)L.nagg * (2 << lg) <= kST) ++lg;
+  H.small_lgR = lg;
+  return true;
 }
 
 amg_status pcg_solve_small(Hierarchy& H, const SolveOpts& o, const SolveWork& w, const double* d_b, double* d_x,
