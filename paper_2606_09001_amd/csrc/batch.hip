@@ -400,25 +400,33 @@ struct WTrueResid {
 // Column-wise partial sums of one workgroup, folded over its rows in a
 // fixed order: partials[(m*W + c)*gridDim + block].  d holds the lane's sums
 // for its V columns, d[m*V + v]; lane l of a row group owns columns l*V + v.
+// `red` is LDS scratch of NRED * kBlock * V doubles that no thread reads or
+// writes any more.
 template <int LW, int V, int NRED>
-__device__ inline void publish_w(const double* d, int W, double* partials) {
+__device__ inline void publish_w(const double* d, int W, double* partials, double* red) {
   if constexpr (NRED > 0) {
     constexpr int RB = kBlock / LW, LV = LW * V;
-    __shared__ double red[NRED][kBlock * V];
 #pragma unroll
     for (int m = 0; m < NRED; ++m)
 #pragma unroll
-      for (int u = 0; u < V; ++u) red[m][threadIdx.x * V + u] = d[m * V + u];
+      for (int u = 0; u < V; ++u) red[m * kBlock * V + threadIdx.x * V + u] = d[m * V + u];
     __syncthreads();
     if ((int)threadIdx.x < LV && (int)threadIdx.x < W) {
       const int c = threadIdx.x;
 #pragma unroll
       for (int m = 0; m < NRED; ++m) {
         double s = 0.0;
-        for (int r = 0; r < RB; ++r) s += red[m][r * LV + c];
+        for (int r = 0; r < RB; ++r) s += red[m * kBlock * V + r * LV + c];
         partials[((int64_t)m * W + c) * gridDim.x + blockIdx.x] = s;
       }
     }
+  }
+}
+template <int LW, int V, int NRED>
+__device__ inline void publish_w(const double* d, int W, double* partials) {
+  if constexpr (NRED > 0) {
+    __shared__ double red[NRED * kBlock * V];
+    publish_w<LW, V, NRED>(d, W, partials, red);
   }
 }
 
@@ -951,7 +959,14 @@ __global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int b
       }
     }
   }
-  publish_w<LW, V, Op::NRED>(d, W, partials);
+  if constexpr (Op::NRED > 0) {
+    // the reduction reuses the window's LDS (every operator with a
+    // reduction is square, and its window holds at least NRED*kBlock*V doubles)
+    static_assert(Op::kSquare && (int64_t)WE * sizeof(GT) >= (int64_t)Op::NRED * kBlock * V * 8,
+                  "window too small for the reduction");
+    __syncthreads();
+    publish_w<LW, V, Op::NRED>(d, W, partials, reinterpret_cast<double*>(s_g));
+  }
 }
 
 // Workgroups of `kernel` resident at once on the device (a multiple of 8).
