@@ -847,6 +847,7 @@ __global__ void __launch_bounds__(kBlock) k_wpattern_grad(int n, int W, const in
 // groups of k_wide (streams per XCD); the grid is the number of workgroups
 // that are resident at once.
 constexpr int kWCap = 1024;       // staged entries per block
+constexpr int kWCapSq = 512;      // staged entries per block of a square operator (with its window)
 constexpr int kWinBytes = 17408;  // staged window of the gathered vector
 
 // Rows per block for which the window of a W-column FP64 vector fits.
@@ -863,12 +864,13 @@ __global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int b
   using GT = typename Op::GT;
   constexpr bool SYS = Op::kSys;
   constexpr int RB = kBlock / LW;
-  constexpr int U = kWCap / kBlock;
+  constexpr int CAP = Op::kSquare ? kWCapSq : kWCap;
+  constexpr int U = CAP / kBlock;
   constexpr int NR = Op::NRED > 0 ? Op::NRED : 1;
   constexpr int WE = Op::kSquare ? kWinBytes / (int)sizeof(GT) : 1;
   __shared__ int s_rp[kBlock + 1];
-  __shared__ int s_ci[kWCap];
-  __shared__ VT s_v[SYS ? 1 : kWCap];
+  __shared__ int s_ci[CAP];
+  __shared__ VT s_v[SYS ? 1 : CAP];
   __shared__ __align__(16) GT s_g[WE];
   const int lr = threadIdx.x / LW, c0 = (threadIdx.x & (LW - 1)) * V;
   const bool live = c0 < W;
@@ -1043,14 +1045,14 @@ std::vector<int> host_rows(const DBuf<int>& rp, int n) {
 
 // Rows per staged block for a matrix: the largest power of two from the
 // lane group's rows per step up to min(256, max_rows) whose blocks all fit
-// the staging buffer; 0 when even the smallest does not (direct kernel).
-int wide_block_rows(const std::vector<int>& rp, int n, int LWv, int max_rows) {
+// `cap` staged entries; 0 when even the smallest does not (direct kernel).
+int wide_block_rows(const std::vector<int>& rp, int n, int LWv, int max_rows, int cap) {
   const int rb = kBlock / LWv;
   int best = 0;
   for (int br = rb; br <= kBlock && (br == rb || br <= max_rows); br <<= 1) {
     int mx = 0;
     for (int r0 = 0; r0 < n; r0 += br) mx = std::max(mx, rp[std::min(r0 + br, n)] - rp[r0]);
-    if (mx > kWCap) break;
+    if (mx > cap) break;
     best = br;
   }
   return best;
@@ -1303,9 +1305,9 @@ void tune_wide(Hierarchy& H, int W, hipStream_t s) {
     BL.brA = BL.brP = BL.brR = 0;
     if (l + 1 == H.lv.size()) continue;
     // A's blocks are sized so that the window of its gathered vector fits
-    BL.brA = wide_block_rows(host_rows(L.rp, L.n), L.n, LWv, window_rows(W));
-    BL.brP = wide_block_rows(host_rows(L.prp, L.n), L.n, LWv, kBlock);
-    BL.brR = wide_block_rows(host_rows(L.rrp, L.nagg), L.nagg, LWv, kBlock);
+    BL.brA = wide_block_rows(host_rows(L.rp, L.n), L.n, LWv, window_rows(W), kWCapSq);
+    BL.brP = wide_block_rows(host_rows(L.prp, L.n), L.n, LWv, kBlock, kWCap);
+    BL.brR = wide_block_rows(host_rows(L.rrp, L.nagg), L.nagg, LWv, kBlock, kWCap);
     // per-system values cannot be staged: the direct form is the default there
     if (SYS && !H.prm.autotune) BL.brA = BL.brP = BL.brR = 0;
   }
