@@ -118,7 +118,13 @@ class AmgHierarchy:
         nrhs = 1 if b.dim() == 1 else b.shape[1]
         if b.shape[0] != self.n:
             raise ValueError(f"rhs has {b.shape[0]} rows, matrix has {self.n}")
-        x = torch.empty_like(b) if out is None else out
+        if out is None:
+            x = torch.empty_like(b)
+        else:
+            if (not out.is_cuda or out.dtype != torch.float64 or out.shape != b.shape
+                    or not out.is_contiguous()):
+                raise ValueError("out must be a contiguous float64 device tensor shaped like b")
+            x = out
         info = _lib.amg_info()
         st = fn(self._h, b.data_ptr(), x.data_ptr(), float(tol), nrhs, C.byref(info), _stream())
         _lib.check(st, fn.__name__, allow=(_lib.AMG_OK, _lib.AMG_NOT_CONVERGED))

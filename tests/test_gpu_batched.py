@@ -164,3 +164,59 @@ def test_multi_system_refresh_and_adjoint():
         assert np.linalg.norm(Lh[:, s] - lo) <= 1e-7 * np.linalg.norm(lo)
         o = O.level(0)
         assert np.array_equal(host(H.export(0, "P_v")).reshape(-1, S)[:, s], o["P_v"])
+
+
+@pytest.mark.parametrize("k,prec", [(6, "fp64"), (12, "fp32"), (3, "fp32")])
+def test_multi_rhs_widths_with_idle_lanes(k, prec):
+    """Widths whose lane groups hold idle lanes (6 FP64 columns: three lanes of
+    two columns in a group of four; 12 FP32: three of four columns each; 3:
+    one column per lane): each column against the oracle."""
+    import oracle
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    rp, ci, v = M.diffusion(np.exp(M.grf(14, 3, seed=21)))
+    n = len(rp) - 1
+    B = M.rhs_normal(n, 31, nrhs=k)
+    print(f"[case] multi-rhs widths n={n} k={k} prec={prec}", flush=True)
+    O = _oracle(rp, ci, v, max_coarse=32)
+    if prec == "fp64":
+        kk = 6
+        H = AmgHierarchy(dev(rp), dev(ci), dev(v), max_coarse=32, maxiter=kk)
+        X, info = H.solve(dev(B), 0.0)
+        Xh = host(X)
+        assert info["iters"] == kk
+        for c in range(k):
+            xo, _ = O.pcg(B[:, c].copy(), tol=0.0, maxiter=kk)
+            assert np.linalg.norm(Xh[:, c] - xo) <= 1e-9 * np.linalg.norm(xo), c
+    else:
+        H = AmgHierarchy(dev(rp), dev(ci), dev(v), max_coarse=32, vcycle_prec=prec)
+        X, info = H.solve(dev(B), 1e-9)
+        Xh = host(X)
+        cols = H.columns(k)
+        for c in range(k):
+            rr = oracle.rel_residual(rp, ci, v, B[:, c].copy(), Xh[:, c].copy())
+            assert cols["status"][c] == 0 and rr <= 1e-9, (c, rr)
+
+
+def test_multi_rhs_unaligned_caller_buffers():
+    """b and x 8 bytes off a 16-byte boundary (views into larger buffers): the
+    sweeps that read the caller's arrays take one column per lane; the
+    solution equals the aligned solve's."""
+    from paper_2606_09001_amd.solver import AmgHierarchy
+    rp, ci, v = M.poisson(20, 3)
+    n, k = len(rp) - 1, 8
+    B = M.rhs_normal(n, 41, nrhs=k)
+    H = AmgHierarchy(dev(rp), dev(ci), dev(v))
+    X0, i0 = H.solve(dev(B), 1e-10)
+    bbuf = torch.zeros(n * k + 1, dtype=torch.float64, device="cuda")
+    xbuf = torch.zeros(n * k + 1, dtype=torch.float64, device="cuda")
+    bmis = bbuf[1:].view(n, k)
+    xmis = xbuf[1:].view(n, k)
+    bmis.copy_(dev(B))
+    assert bmis.data_ptr() % 16 == 8 and xmis.data_ptr() % 16 == 8
+    X1, i1 = H.solve(bmis, 1e-10, out=xmis)
+    assert X1.data_ptr() == xmis.data_ptr()
+    assert i1["iters"] == i0["iters"] and i1["status"] == 0
+    assert np.allclose(host(X1), host(X0), rtol=0, atol=1e-12 * np.abs(host(X0)).max())
+    assert xbuf[0].item() == 0.0          # nothing written before the view
+    with pytest.raises(ValueError):
+        H.solve(dev(B), 1e-10, out=torch.empty((n, k + 1), dtype=torch.float64, device="cuda")[:, :k])
