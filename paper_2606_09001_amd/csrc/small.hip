@@ -41,7 +41,7 @@ constexpr int kSRow = 8;         // entries per row of A_0
 constexpr int kSCoarse = 256;    // largest padded coarsest level
 constexpr int kSPCap = 3200;     // entries of P_0 (and of R_0 = P_0^T) staged in LDS
 constexpr int kSWaves = kST / 64;
-constexpr int kSRowsPerLane = kSCoarse / 64;  // coarse rows per lane in the inverse product
+constexpr int kSPairs = kSCoarse / 128;  // row-pair chunks per lane in the inverse product
 constexpr int kSCols = 4;        // inverse columns per step (loads in flight: kSCols x rows per lane)
 
 struct SmallArgs {
@@ -165,14 +165,16 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
   };
   const int gR = 1 << a.lgR;
   const int rrow = t >> a.lgR, rl = t & (gR - 1);
-  // coarse product: wave wv takes columns [c0w, c1w), lane ln rows ln + 64 r
-  // (r < rpl); the wave index, column range and row-chunk count are
+  // coarse product: wave wv takes columns [c0w, c1w), lane ln the row pairs
+  // (2 ln + 128 r, +1) for r < rpl, one 16-byte load per pair (a compute
+  // unit reads L2 at twice the rate with 16-byte as with 8-byte lane
+  // accesses); the wave index, column range and chunk count are
   // wave-uniform, so the column loads have scalar base addresses and the
-  // loop has no divergent branches
+  // loop has no divergent branches.  The padded order m is a multiple of 16.
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6), ln = t & 63;
   const int Lw = (a.nc + kSWaves - 1) / kSWaves;
   const int c0w = min(wv * Lw, a.nc), c1w = min(c0w + Lw, a.nc);
-  const int rpl = (a.nc + 63) >> 6;
+  const int rpl = (a.nc + 127) >> 7;
 
   // z = M^-1 r (s_r -> s_z); returns <r, z>, and <z, q> in zq when flexible
   auto vcycle = [&](double& zq) -> double {
@@ -207,36 +209,39 @@ __global__ void __launch_bounds__(kST) k_pcg_small(SmallArgs a) {
     __syncthreads();
     {                                              // x_1 = A_c^-1 b_1
       phase_fence();
-      double acc[kSRowsPerLane];
+      double acc[kSPairs][2];
 #pragma unroll
-      for (int r = 0; r < kSRowsPerLane; ++r) acc[r] = 0.0;
+      for (int r = 0; r < kSPairs; ++r) acc[r][0] = acc[r][1] = 0.0;
       const int jend = opaque(c1w);
       for (int j0 = c0w; j0 < jend; j0 += kSCols) {
-        // columns past the block's end and rows past nc load a valid entry
-        // (clamped) and are left out of the sums
-        double v[kSCols][kSRowsPerLane];
+        // columns past the block's end and pairs past the padded order load
+        // a valid pair (clamped) and are left out of the sums
+        double2 v[kSCols][kSPairs];
 #pragma unroll
         for (int u = 0; u < kSCols; ++u) {
           const double* col = a.inv + (int64_t)min(j0 + u, jend - 1) * a.m;
 #pragma unroll
-          for (int r = 0; r < kSRowsPerLane; ++r)
-            if (r < rpl) v[u][r] = col[min(ln + 64 * r, a.nc - 1)];
+          for (int r = 0; r < kSPairs; ++r)
+            if (r < rpl) v[u][r] = *reinterpret_cast<const double2*>(col + min(2 * ln + 128 * r, a.m - 2));
         }
 #pragma unroll
         for (int u = 0; u < kSCols; ++u) {
           const double bj = s_b1[min(j0 + u, jend - 1)];
 #pragma unroll
-          for (int r = 0; r < kSRowsPerLane; ++r) {
+          for (int r = 0; r < kSPairs; ++r) {
             if (r < rpl) {
-              const double pr = v[u][r] * bj;
-              acc[r] = j0 + u < jend ? acc[r] + pr : acc[r];
+              const double p0 = v[u][r].x * bj, p1 = v[u][r].y * bj;
+              acc[r][0] = j0 + u < jend ? acc[r][0] + p0 : acc[r][0];
+              acc[r][1] = j0 + u < jend ? acc[r][1] + p1 : acc[r][1];
             }
           }
         }
       }
 #pragma unroll
-      for (int r = 0; r < kSRowsPerLane; ++r)
-        if (ln + 64 * r < a.nc) s_gp[wv][ln + 64 * r] = acc[r];
+      for (int r = 0; r < kSPairs; ++r)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (2 * ln + 128 * r + h < a.nc) s_gp[wv][2 * ln + 128 * r + h] = acc[r][h];
       __syncthreads();
       if (t < a.nc) {                              // the column blocks' sums in wave order
         double s = 0.0;
