@@ -70,7 +70,7 @@ def test_lognormal_diffusion_192_cached_setup():
         assert info32["status"] == 0 and oracle.rel_residual(rp, ci, v, b, host(x32)) <= 1e-8
         if seed == 100:
             xo, io = O.pcg(b, tol=1e-8)
-            print(f"[c3] gpu iters={info['iters']} fp32 iters={info32['iters']} oracle iters={io['iters']}",
+            print(f"[diffusion 192^3] gpu iters={info['iters']} fp32 iters={info32['iters']} oracle iters={io['iters']}",
                   flush=True)
             assert abs(info["iters"] - io["iters"]) <= 1
             # iterate parity at the oracle's iteration count (the cached
@@ -80,7 +80,7 @@ def test_lognormal_diffusion_192_cached_setup():
             xk, ik = Hk.solve(dev(b), 0.0)
             xok, _ = O.pcg(b, tol=0.0, maxiter=k)
             err = np.linalg.norm(host(xk) - xok) / np.linalg.norm(xok)
-            print(f"[c3 iterate parity] k={k} err={err:.3e}", flush=True)
+            print(f"[diffusion 192^3 iterate parity] k={k} err={err:.3e}", flush=True)
             assert ik["iters"] == k and ik["cache_event"] in (0, 1) and err <= 1e-9
             Hk.close()
 
@@ -118,7 +118,7 @@ def test_adjoint_512_vs_oracle_gradient(prec):
     lo, _ = O.solve_adjoint(xo - u_obs, tol=1e-10)
     go = oracle.diffusion_theta_grad(k, rp, ci, O.pattern_grad(lo, xo))
     rel = np.linalg.norm(g - go) / np.linalg.norm(go)
-    print(f"[c4 {prec}] loss={L:.6e} grad rel err vs oracle={rel:.3e}", flush=True)
+    print(f"[adjoint 512^2 {prec}] loss={L:.6e} grad rel err vs oracle={rel:.3e}", flush=True)
     assert rel <= 1e-5
     # directional central differences of the oracle's loss (tol 1e-12)
     for seed in (7, 8, 9):
@@ -132,7 +132,7 @@ def test_adjoint_512_vs_oracle_gradient(prec):
 
         fd = (loss_at(theta + eps * d) - loss_at(theta - eps * d)) / (2 * eps)
         an = float(np.sum(g * d))
-        print(f"[c4 {prec}] direction {seed}: fd={fd:.10e} adjoint={an:.10e} rel={abs(fd - an) / abs(fd):.2e}",
+        print(f"[adjoint 512^2 {prec}] direction {seed}: fd={fd:.10e} adjoint={an:.10e} rel={abs(fd - an) / abs(fd):.2e}",
               flush=True)
         assert abs(fd - an) <= 1e-5 * abs(fd)
 
@@ -213,7 +213,7 @@ def test_batched_64_systems_96_full():
                         assert np.array_equal(g.view(np.int64), o[name].view(np.int64)), (s, l, name)
                     assert np.array_equal(host(H.export(l, "agg")), o["agg"])
                 xo, io = O.pcg(B[:, s].copy(), tol=1e-8)
-                print(f"[c5a] system {s}: gpu iters {cols['iters'][s]} oracle {io['iters']}", flush=True)
+                print(f"[64 systems 96^3] system {s}: gpu iters {cols['iters'][s]} oracle {io['iters']}", flush=True)
                 assert abs(cols["iters"][s] - io["iters"]) <= 1
                 sampled[s] = (O, io["iters"])
             # iterate parity at a fixed count (the smallest sampled oracle count):
@@ -226,7 +226,7 @@ def test_batched_64_systems_96_full():
             for s, (O, _) in sampled.items():
                 xo, _ = O.pcg(B[:, s].copy(), tol=0.0, maxiter=kk)
                 err = np.linalg.norm(Xkh[:, s] - xo) / np.linalg.norm(xo)
-                print(f"[c5a iterate parity] system {s} k={kk} err={err:.3e}", flush=True)
+                print(f"[64 systems 96^3 iterate parity] system {s} k={kk} err={err:.3e}", flush=True)
                 assert err <= 1e-9, (s, err)
             Hk.close()
             del sampled
@@ -265,13 +265,13 @@ def test_batched_32_rhs_poisson_256_full():
             assert abs(cols["rel_resid"][c] - rr) <= 1e-6 * rr + 1e-15
         if prec == "fp64":
             del X
-            print("[c5b] oracle setup 256^3", flush=True)
+            print("[32 rhs 256^3] oracle setup 256^3", flush=True)
             O = oracle.OracleHierarchy(rp, ci, v)
             sampled = (0, 15, 31)
             counts = {}
             for c in sampled:
                 xo, io = O.pcg(B[:, c].copy(), tol=1e-8)
-                print(f"[c5b] column {c}: batched iters {cols['iters'][c]} oracle {io['iters']}", flush=True)
+                print(f"[32 rhs 256^3] column {c}: batched iters {cols['iters'][c]} oracle {io['iters']}", flush=True)
                 assert io["status"] == 0 and abs(cols["iters"][c] - io["iters"]) <= 1
                 counts[c] = io["iters"]
             kk = min(counts.values())
@@ -281,7 +281,7 @@ def test_batched_32_rhs_poisson_256_full():
             for c in sampled:
                 xo, _ = O.pcg(B[:, c].copy(), tol=0.0, maxiter=kk)
                 err = np.linalg.norm(host(X[:, c].contiguous()) - xo) / np.linalg.norm(xo)
-                print(f"[c5b iterate parity] column {c} k={kk} err={err:.3e}", flush=True)
+                print(f"[32 rhs 256^3 iterate parity] column {c} k={kk} err={err:.3e}", flush=True)
                 assert err <= 1e-9, (c, err)
             Hk.close()
             del O
