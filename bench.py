@@ -46,12 +46,21 @@ def traffic_from_profiles(kernel_tag: str, src_hash: str):
     return d.get("traffic_bytes_per_launch")
 
 
-def kernel_source_hash(batched=False):
-    """sha256 of the sources that define the profiled kernels: the
-    single-system sweeps (solve.hip) or the batched ones (batch.hip), with the
-    shared header."""
+def kernel_source(table=None):
+    """The source file that defines the kernels of a profile table."""
+    if table is WIDE_KERNELS:
+        return "batch.hip"
+    if table is SMALL_KERNELS:
+        return "small.hip"
+    return "solve.hip"
+
+
+def kernel_source_hash(source="solve.hip"):
+    """sha256 of the sources that define the profiled kernels (the
+    single-system sweeps in solve.hip, the batched ones in batch.hip, the
+    one-workgroup solve in small.hip), with the shared header."""
     h = hashlib.sha256()
-    for name in (("batch.hip" if batched else "solve.hip"), "amg_internal.hpp"):
+    for name in (source, "amg_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2606_09001_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -150,9 +159,16 @@ def _by_grid(rows, spec, grid_key, value):
     return [r for r in sel if int(r[grid_key]) == grids[rank]]
 
 
+SMALL_KERNELS = {  # the one-workgroup solve of the 32^2 Poisson system (one dispatch per solve)
+    "one_workgroup_solve": (r"k_pcg_small", "top"),
+}
+
+
 def profile_table(tag):
     if "bicgstab" in tag:
         return BICG_KERNELS
+    if "poisson2d" in tag:
+        return SMALL_KERNELS
     if "batched" in tag or "_x" in tag:
         return WIDE_KERNELS
     return FINE_KERNELS
@@ -207,8 +223,8 @@ def summarize_profiles(a):
 
     ff, fetch = per_dispatch(a.fetch_dir, "FETCH_SIZE")
     wf, write = per_dispatch(a.write_dir, "WRITE_SIZE")
-    batched = profile_table(tag) is WIDE_KERNELS
-    src = kernel_source_hash(batched)
+    source = kernel_source(profile_table(tag))
+    src = kernel_source_hash(source)
     txt = [f"# HBM traffic per dispatch: {tag}", "", "commands:", f"    {a.cmd_fetch}", f"    {a.cmd_write}", "",
            f"calibration: negation of {CALIB_MIB} MiB (reads and writes {CALIB_MIB * 1024} KiB); "
            f"FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f} (counter KiB per byte-exact KiB)", "",
@@ -224,7 +240,7 @@ def summarize_profiles(a):
                        "write_kib_per_dispatch": write[k]["kib"], "fetch_factor": ff, "write_factor": wf,
                        "traffic_bytes_per_launch": round(traffic), "commands": [a.cmd_fetch, a.cmd_write],
                        "working_avg_us_from_trace": summary.get(k, {}).get("avg_us")}, f, indent=1)
-    txt.append(f"\nkernel source sha256 ({'batch.hip' if batched else 'solve.hip'} + amg_internal.hpp): {src}")
+    txt.append(f"\nkernel source sha256 ({source} + amg_internal.hpp): {src}")
     with open(os.path.join(out_dir, f"{tag}_pmc.txt"), "w") as f:
         f.write("\n".join(txt) + "\n")
     print("\n".join(txt))
@@ -860,6 +876,8 @@ def main():
     ap.add_argument("--diffusion-only", action="store_true",
                     help="only the 192^3 diffusion workload (with the counter calibration kernel); for profiling")
     ap.add_argument("--diffusion-grid", type=int, default=192)
+    ap.add_argument("--small-only", action="store_true",
+                    help="only the 32^2 Poisson solves (one workgroup and per-kernel); for profiling")
     ap.add_argument("--nonsym-only", action="store_true",
                     help="only the nonsymmetric BiCGSTAB and matrix-free workloads; for profiling")
     ap.add_argument("--nonsym-grid", type=int, default=128)
@@ -960,6 +978,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps({"batched": run_batched(args, dev)}), flush=True)
+        return
+    if args.small_only:
+        print(json.dumps({"poisson2d_32": run_small(args, dev)}), flush=True)
         return
 
     res = {}
