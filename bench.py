@@ -451,7 +451,7 @@ def run_diffusion(args, dev):
     xs_d = {}
     for prec in ("fp64", "fp32"):
         t0 = time.time()
-        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec)
+        H = AmgHierarchy(d_rp, d_ci, d_v, vcycle_prec=prec, autotune=args.autotune)
         torch.cuda.synchronize()
         setup_ms = (time.time() - t0) * 1e3
         H.solve(Bs[0], args.tol, out=x)
