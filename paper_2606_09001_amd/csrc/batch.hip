@@ -123,7 +123,9 @@ __device__ inline T row_at(const T* v, int i, int c, int W) {
 //   cols<V>(c0)         per-column scalars of columns c0 .. c0+V-1
 //   row_in<V>, epi<V>   the row's own operands and its outputs; kOwn: row_in
 //                       takes the row's own entries of gv (xo), which the
-//                       sweep reads from the staged window when it has one
+//                       sweep reads from the staged window when it has one;
+//                       kLateRow: the staged sweep loads them after the row's
+//                       gathers instead of before
 // and the sweep's per-column reductions in d[m * V + v].
 
 struct NoCols {};
@@ -134,7 +136,7 @@ struct WResid {
   using PT = T;
   using VT = T;
   using GT = T;
-  static constexpr bool kSys = SYS, kSquare = true, kOwn = false;
+  static constexpr bool kSys = SYS, kSquare = true, kOwn = false, kLateRow = false;
   static constexpr int NRED = 0;
   const T* v;
   const BT* b;
@@ -172,7 +174,7 @@ struct WRestrict {
   using PT = T;
   using VT = RT;
   using GT = T;
-  static constexpr bool kSys = SYS, kSquare = false, kOwn = false;
+  static constexpr bool kSys = SYS, kSquare = false, kOwn = false, kLateRow = false;
   static constexpr int NRED = 0;
   const RT* v;
   const T* gv;
@@ -217,7 +219,7 @@ struct WProlong {
   using PT = T;
   using VT = RT;
   using GT = T;
-  static constexpr bool kSys = SYS, kSquare = false, kOwn = false;
+  static constexpr bool kSys = SYS, kSquare = false, kOwn = false, kLateRow = false;
   static constexpr int NRED = 0;
   const RT* v;
   const T* gv;
@@ -251,7 +253,7 @@ struct WPost {
   using PT = T;
   using VT = T;
   using GT = T;
-  static constexpr bool kSys = SYS, kSquare = true, kOwn = true;
+  static constexpr bool kSys = SYS, kSquare = true, kOwn = true, kLateRow = true;
   static constexpr int NRED = RED;
   const T* v;
   const T* sw;
@@ -301,7 +303,7 @@ struct WSpmvXpay {
   using PT = double;
   using VT = double;
   using GT = double;
-  static constexpr bool kSys = SYS, kSquare = true, kOwn = true;
+  static constexpr bool kSys = SYS, kSquare = true, kOwn = true, kLateRow = false;
   static constexpr int NRED = 1;
   const double* v;
   const double* gv;  // z
@@ -365,7 +367,7 @@ struct WTrueResid {
   using PT = double;
   using VT = double;
   using GT = double;
-  static constexpr bool kSys = SYS, kSquare = true, kOwn = false;
+  static constexpr bool kSys = SYS, kSquare = true, kOwn = false, kLateRow = false;
   static constexpr int NRED = 1;
   const double* v;
   const double* gv;  // x
@@ -919,12 +921,20 @@ __global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int b
     __syncthreads();
     for (int q = lr; q < br; q += RB) {
       const int row = r0 + q;
-      GT xo[V];
-      if constexpr (Op::kOwn) {
-        if (win) ldv<V>(s_g, (int64_t)(min(row, n - 1) - r0 + 1) * W + cc0, xo);
-        else ldv<V>(op.gv, (int64_t)min(row, n - 1) * W + cc0, xo);
-      }
-      const auto in = op.template row_in<V>(min(row, n - 1), cc0, cs, xo);
+      // the row's own operands: before the gathers (their loads overlap), or
+      // for operators with many of them after (kLateRow: not live in
+      // registers across the gather loop, one more workgroup per CU)
+      const int rowc = min(row, n - 1);
+      auto row_operands = [&]() {
+        GT xo[V];
+        if constexpr (Op::kOwn) {
+          if (win) ldv<V>(s_g, (int64_t)(rowc - r0 + 1) * W + cc0, xo);
+          else ldv<V>(op.gv, (int64_t)rowc * W + cc0, xo);
+        }
+        return op.template row_in<V>(rowc, cc0, cs, xo);
+      };
+      decltype(row_operands()) in_early{};
+      if constexpr (!Op::kLateRow) in_early = row_operands();
       PT acc[V] = {};
       if (row < n && live) {
         const int a = s_rp[q] - k0, e = s_rp[q + 1] - k0;
@@ -957,7 +967,8 @@ __global__ void __launch_bounds__(kBlock) k_wide_st(int n, int W, int spx, int b
 #pragma unroll
               for (int w = 0; w < V; ++w) acc[w] += pr[u][w];
         }
-        op.template epi<V>(row, c0, acc, in, cs, d);
+        if constexpr (Op::kLateRow) op.template epi<V>(row, c0, acc, row_operands(), cs, d);
+        else op.template epi<V>(row, c0, acc, in_early, cs, d);
       }
     }
   }
