@@ -1040,11 +1040,7 @@ template <class Op>
 int wsweep(int vmax, int spx, int br, int n, int W, const int* rp, const int* ci, const Op& op,
            const BatchHead* head, double* partials, hipStream_t s) {
   constexpr int eb = (int)sizeof(typename Op::GT);
-  int v = wide_v(W, eb, vmax);
-  // a staged block's rows must fill the workgroup's row groups: fewer
-  // columns per lane (more lanes per row) when the block is short
-  if (br > 0)
-    while (v > 1 && kBlock / wide_lanes(W, v) > br) v >>= 1;
+  const int v = wide_v(W, eb, vmax);
   if constexpr (eb == 4) {
     if (v == 4) return wsweep_v<4>(spx, br, n, W, rp, ci, op, head, partials, s);
   }
